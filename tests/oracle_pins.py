@@ -1,0 +1,350 @@
+"""Pins of the CPU oracle: checks against what the paper and the mathematics fix.
+
+Each ``pin_*`` function takes a loaded oracle library and raises
+AssertionError if the oracle disagrees with:
+  - the worked example the paper prints (Table 1, figure "Stack vs. queue");
+  - hand-derived special cases of Algorithm 1 (ties, diagonals, dx != dy);
+  - brute force on tiny grids (path walks for levels and areas, a dense
+    linear solve for the implicit height update of Algorithm 6);
+  - closed forms: K = 0, very long time steps, the steady-state slope-area
+    law S = (U/K) A^-m and the 1-D channel profile.
+The same functions serve the mutation test, which plants mistakes in a copy
+of the oracle and expects at least one pin to fail for each.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+import oracle
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+# Neighbour offsets (dy, dx) in the oracle's neighbour order.
+OFFS = [(-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 1), (1, -1), (1, 0), (1, 1)]
+
+
+def _table1():
+    with open(os.path.join(GOLDEN, "table1_example.json")) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Worked example (Table 1; figure "Stack vs. queue").
+
+def pin_table1(lib):
+    t = _table1()
+    n = len(t["nodes"])
+    rec = np.array([(r - 1) if r is not None else i for i, r in enumerate(t["rec"])], np.int32)
+    g = oracle.graph_order(rec, lib=lib)
+    assert g["dnum"].tolist() == t["dnum"], ("Dnum", g["dnum"].tolist())
+    for node, dl in t["donors"].items():
+        c = int(node) - 1
+        got = [int(v) + 1 for v in g["donor"][c, : g["dnum"][c]]]
+        assert got == dl, ("Donor", node, got, dl)
+    assert (g["queue"] + 1).tolist() == t["queue"], ("Queue", (g["queue"] + 1).tolist())
+    assert g["levels"].tolist() == t["levels"], ("Levels", g["levels"].tolist())
+    assert g["count"].tolist() == t["accum"], ("Accum", g["count"].tolist())
+    order = (g["stack_order"] + 1).tolist()
+    expect = sorted(t["stack_visit_number"], key=lambda k: t["stack_visit_number"][k])
+    assert order == [int(k) for k in expect], ("stack order", order)
+    bfs = sorted(t["queue_visit_number"], key=lambda k: t["queue_visit_number"][k])
+    assert (g["queue"] + 1).tolist() == [int(k) for k in bfs]
+    # The levels of the queue are the depths of the nodes.
+    for l in range(len(t["levels"]) - 1):
+        for i in range(t["levels"][l], t["levels"][l + 1]):
+            assert g["depth"][g["queue"][i]] == l
+    assert n == 10
+
+
+# --------------------------------------------------------------------------
+# Receivers: hand-derived special cases of Algorithm 1.
+
+def _rec_of(lib, h, dx=100.0, dy=100.0):
+    return oracle.receivers(np.asarray(h, np.float64), dx, dy, lib=lib)
+
+
+def pin_receivers_special_cases(lib):
+    z = np.zeros((3, 3))
+    # Centre above a flat perimeter: the four orthogonal slopes tie at 1/100
+    # and beat the diagonals (1/141.4); the first in neighbour order (up) wins.
+    h = z.copy(); h[1, 1] = 1.0
+    assert _rec_of(lib, h)[1, 1] == 1
+    # A lower diagonal corner beats the orthogonal neighbours: 2/141.4 > 1/100.
+    h = z.copy(); h[1, 1] = 1.0; h[0, 0] = -1.0
+    assert _rec_of(lib, h)[1, 1] == 0
+    # ... but not when it is only slightly lower: 1.2/141.4 < 1/100.
+    h = z.copy(); h[1, 1] = 1.0; h[2, 2] = -0.2
+    assert _rec_of(lib, h)[1, 1] == 1
+    # Flat and pit: no strictly lower neighbour, so no receiver.
+    assert _rec_of(lib, z)[1, 1] == 4
+    h = z.copy(); h[1, 1] = -1.0
+    assert _rec_of(lib, h)[1, 1] == 4
+    # dx != dy: with dx = 50 the left neighbour (slope 1/50) beats up (1/100).
+    h = z.copy(); h[1, 1] = 1.0
+    assert _rec_of(lib, h, dx=50.0, dy=100.0)[1, 1] == 3
+    assert _rec_of(lib, h, dx=100.0, dy=50.0)[1, 1] == 1
+    # Perimeter cells never have a receiver.
+    h = np.arange(20, dtype=np.float64).reshape(4, 5)
+    rec = _rec_of(lib, h)
+    for y in range(4):
+        for x in range(5):
+            if y in (0, 3) or x in (0, 4):
+                assert rec[y, x] == y * 5 + x
+    # A plane rising in x drains every interior cell to its left neighbour;
+    # a plane rising in x and y drains to the upper-left diagonal.
+    yy, xx = np.mgrid[0:6, 0:7].astype(np.float64)
+    rec = _rec_of(lib, xx)
+    for y in range(1, 5):
+        for x in range(1, 6):
+            assert rec[y, x] == y * 7 + x - 1
+    rec = _rec_of(lib, xx + yy)
+    for y in range(1, 5):
+        for x in range(1, 6):
+            assert rec[y, x] == (y - 1) * 7 + x - 1
+
+
+def _receivers_brute(h, dx, dy):
+    """Every slope of every interior cell at once; the first maximum wins."""
+    ny, nx = h.shape
+    dd = np.sqrt(dx * dx + dy * dy)
+    dist = [dd, dy, dd, dx, dx, dd, dy, dd]
+    rec = np.arange(ny * nx, dtype=np.int64).reshape(ny, nx)
+    if ny < 3 or nx < 3:
+        return rec
+    hc = h[1:-1, 1:-1]
+    s = np.stack([(hc - h[1 + oy: ny - 1 + oy, 1 + ox: nx - 1 + ox]) / dist[k]
+                  for k, (oy, ox) in enumerate(OFFS)])
+    best = np.argmax(s, axis=0)
+    smax = np.take_along_axis(s, best[None], 0)[0]
+    iy, ix = np.mgrid[1:ny - 1, 1:nx - 1]
+    oy = np.array([o[0] for o in OFFS])[best]
+    ox = np.array([o[1] for o in OFFS])[best]
+    target = (iy + oy) * nx + (ix + ox)
+    rec[1:-1, 1:-1] = np.where(smax > 0.0, target, iy * nx + ix)
+    return rec
+
+
+def pin_receivers_brute_force(lib):
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        ny = int(rng.integers(3, 10))
+        nx = int(rng.integers(3, 10))
+        h = W.quantised_heights(ny, nx, 4, seed=1000 + trial)
+        dx = float(rng.choice([1.0, 30.0, 100.0]))
+        dy = dx if trial % 2 == 0 else float(rng.choice([20.0, 70.0]))
+        got = _rec_of(lib, h, dx, dy)
+        exp = _receivers_brute(h, dx, dy)
+        assert np.array_equal(got, exp), (trial, ny, nx, dx, dy)
+
+
+# --------------------------------------------------------------------------
+# Levels and areas: path-walk brute force and invariants.
+
+def _walk(rec):
+    """Each cell walks to its root: its depth is the number of hops, and it
+    adds one to the count of every cell on the way (itself included)."""
+    r = rec.ravel()
+    n = r.size
+    depth = np.zeros(n, np.int64)
+    count = np.zeros(n, np.int64)
+    for c in range(n):
+        v, d = c, 0
+        count[v] += 1
+        while r[v] != v:
+            v = r[v]
+            d += 1
+            count[v] += 1
+            assert d <= n
+        depth[c] = d
+    return depth, count
+
+
+def pin_levels_and_areas_brute_force(lib):
+    for seed, (ny, nx, q) in enumerate([(7, 9, 3), (12, 10, 5), (16, 16, 0), (5, 23, 2)]):
+        h = (W.quantised_heights(ny, nx, q, seed) if q else W.initial_heights(ny, nx, seed))
+        p = oracle.Params(ny, nx)
+        r = oracle.routing(h, p, lib=lib)
+        depth, count = _walk(r["rec"])
+        assert np.array_equal(r["depth"].ravel(), depth), (ny, nx)
+        assert np.array_equal(r["count"].ravel(), count), (ny, nx)
+        hist = np.bincount(depth, minlength=r["nlevels"])
+        assert r["nlevels"] == depth.max() + 1
+        assert np.array_equal(r["offsets"], np.concatenate([[0], np.cumsum(hist)]))
+
+
+def pin_forest_invariants(lib):
+    h = W.initial_heights(40, 33, 5)
+    p = oracle.Params(40, 33)
+    r = oracle.routing(h, p, lib=lib)
+    rec = r["rec"].ravel()
+    cnt = r["count"].ravel().astype(np.int64)
+    dep = r["depth"].ravel()
+    n = rec.size
+    roots = rec == np.arange(n)
+    assert cnt[roots].sum() == n
+    assert np.all(dep[roots] == 0)
+    nr = ~roots
+    assert np.all(dep[nr] == dep[rec[nr]] + 1)
+    inflow = np.zeros(n, np.int64)
+    np.add.at(inflow, rec[nr], cnt[nr])
+    assert np.array_equal(cnt, 1 + inflow)
+    # In depth-first order every subtree is one contiguous block of
+    # count[c] cells that starts at c.
+    donor, dnum = oracle.donors(r["rec"], lib=lib)
+    order, depth, emitted = oracle.stack_order(r["rec"], donor, dnum, lib=lib)
+    assert emitted == n
+    pos = np.empty(n, np.int64)
+    pos[order] = np.arange(n)
+    def has_ancestor(v, c):
+        while v != c and rec[v] != v:
+            v = rec[v]
+        return v == c
+
+    for c in range(n):
+        block = order[pos[c]: pos[c] + cnt[c]]
+        assert all(has_ancestor(int(v), c) for v in block), c
+    # The breadth-first queue of Algorithm 3 has exactly these levels.
+    queue, levels = oracle.bfs_queue(r["rec"], donor, dnum, lib=lib)
+    assert np.array_equal(levels, r["offsets"])
+    for l in range(len(levels) - 1):
+        assert np.all(dep[queue[levels[l]: levels[l + 1]]] == l)
+
+
+# --------------------------------------------------------------------------
+# Heights: brute force and closed forms.
+
+def _dist(c, r, nx, dx, dy):
+    cy, cx, ry, rx = c // nx, c % nx, r // nx, r % nx
+    if cy != ry and cx != rx:
+        return np.sqrt(dx * dx + dy * dy)
+    return dy if cy != ry else dx
+
+
+def pin_one_step_dense_solve(lib):
+    """Backward Euler for every cell at once: (I + diag(F)(I - P)) h' = h + U dt."""
+    for seed, (ny, nx, m, Kfield) in enumerate([(6, 7, 0.5, False), (8, 5, 0.45, True),
+                                                (9, 9, 0.6, False)]):
+        dx, dy, dt, U, K = 30.0, 45.0, 1e4, 2e-3, 4e-5
+        h = W.initial_heights(ny, nx, 50 + seed) * 5.0
+        Kf = (K * np.exp(0.5 * np.random.default_rng(seed).standard_normal((ny, nx)))
+              if Kfield else None)
+        Uf = np.random.default_rng(seed + 7).uniform(1e-4, 2e-3, (ny, nx))
+        p = oracle.Params(ny, nx, dx, dy, dt, m, 1.0, U, K)
+        rec = _receivers_brute(h, dx, dy).ravel()
+        _, count = _walk(rec.reshape(ny, nx))
+        n = ny * nx
+        A = np.eye(n)
+        rhs = h.ravel().copy()
+        for c in range(n):
+            y, x = divmod(c, nx)
+            interior = 0 < y < ny - 1 and 0 < x < nx - 1
+            if interior:
+                rhs[c] += Uf.ravel()[c] * dt
+            if rec[c] != c:
+                kc = Kf.ravel()[c] if Kfield else K
+                F = kc * dt * (count[c] * dx * dy) ** m / _dist(c, rec[c], nx, dx, dy)
+                A[c, c] += F
+                A[c, rec[c]] -= F
+        exp = np.linalg.solve(A, rhs).reshape(ny, nx)
+        got = oracle.run(h, p, 1, K=Kf, U=Uf, lib=lib)["h"]
+        assert np.allclose(got, exp, rtol=1e-12, atol=1e-12), (seed, np.abs(got - exp).max())
+
+
+def pin_no_erosion_is_pure_uplift(lib):
+    h = W.initial_heights(20, 17, 9)
+    p = oracle.Params(20, 17, 100.0, 100.0, 1000.0, 0.5, 1.0, 5e-4, 0.0)
+    got = oracle.run(h, p, 3, lib=lib)["h"]
+    exp = h.copy()
+    for _ in range(3):
+        exp[1:-1, 1:-1] = exp[1:-1, 1:-1] + 5e-4 * 1000.0
+    assert np.array_equal(got, exp)
+
+
+def pin_long_step_follows_receiver(lib):
+    """As dt grows, F grows and every eroding cell moves onto its receiver's
+    new height; roots keep only the uplift."""
+    h = W.initial_heights(12, 14, 21)
+    p = oracle.Params(12, 14, 100.0, 100.0, 1e9, 0.5, 1.0, 0.0, 1.0)
+    r = oracle.routing(h, p, lib=lib)
+    got = oracle.run(h, p, 1, lib=lib)["h"].ravel()
+    rec = r["rec"].ravel()
+    for c in range(rec.size):
+        root = c
+        while rec[root] != root:
+            root = rec[root]
+        assert abs(got[c] - got[root]) < 1e-6, c
+
+
+def _run_to_steady(lib, h, p, rec=None, block=200, max_blocks=200):
+    for _ in range(max_blocks):
+        if rec is None:
+            nxt = oracle.run(h, p, block, lib=lib)["h"]
+        else:
+            nxt = oracle.run_fixed_routing(h, rec, p, block, lib=lib)["h"]
+        change = np.abs(nxt - h).max() / max(np.abs(nxt).max(), 1e-300)
+        h = nxt
+        if change < 1e-14:
+            return h
+    raise AssertionError("no steady state")
+
+
+def pin_steady_state_slope_area(lib):
+    """At the fixed point of uplift and implicit erosion every cell satisfies
+    U dt = F (h_c - h_r), i.e. S = (h_c - h_r)/d = (U/K) A^-m, whatever dt."""
+    ny = nx = 24
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    cone = np.minimum.reduce([yy, xx, ny - 1 - yy, nx - 1 - xx]).astype(np.float64)
+    h = cone + 0.3 * np.random.default_rng(4).random((ny, nx))
+    h[0, :] = h[-1, :] = h[:, 0] = h[:, -1] = 0.0
+    U, K, m, dx = 1e-3, 2e-5, 0.45, 30.0
+    p = oracle.Params(ny, nx, dx, dx, 5e4, m, 1.0, U, K)
+    h = _run_to_steady(lib, h, p)
+    r = oracle.routing(h, p, lib=lib)
+    rec, cnt = r["rec"].ravel(), r["count"].ravel()
+    hf = h.ravel()
+    checked = 0
+    for c in range(hf.size):
+        y, x = divmod(c, nx)
+        if not (0 < y < ny - 1 and 0 < x < nx - 1):
+            continue
+        assert rec[c] != c, "an interior sink survived"
+        S = (hf[c] - hf[rec[c]]) / _dist(c, rec[c], nx, dx, dx)
+        law = (U / K) * (cnt[c] * dx * dx) ** (-m)
+        assert abs(S - law) <= 1e-9 * law, (c, S, law)
+        checked += 1
+    assert checked == (ny - 2) * (nx - 2)
+
+
+def pin_channel_profile(lib):
+    """A 1-D channel (fixed routing: every interior cell of the middle row
+    drains left) reaches h_i = sum_{j<=i} dx (U/K) A_j^-m, A_j = (nx-1-j) dx dy."""
+    ny, nx = 3, 40
+    U, K, m, dx, dy = 5e-4, 1e-5, 0.5, 100.0, 100.0
+    rec = np.arange(ny * nx, dtype=np.int32).reshape(ny, nx)
+    for x in range(1, nx - 1):
+        rec[1, x] = nx + x - 1
+    p = oracle.Params(ny, nx, dx, dy, 1e5, m, 1.0, U, K)
+    h = _run_to_steady(lib, np.zeros((ny, nx)), p, rec=rec)
+    expect = np.cumsum([dx * (U / K) * ((nx - 1 - j) * dx * dy) ** (-m) for j in range(1, nx - 1)])
+    assert np.allclose(h[1, 1:-1], expect, rtol=1e-10, atol=0), np.abs(h[1, 1:-1] - expect).max()
+    assert np.all(h[0] == 0) and np.all(h[2] == 0)
+
+
+def pin_newton_matches_closed_form(lib):
+    """Algorithm 6's Newton loop with n = 1 converges to the closed form."""
+    h = W.initial_heights(30, 30, 2) * 3
+    p1 = oracle.Params(30, 30, m=0.5, n=1.0)
+    pn = oracle.Params(30, 30, m=0.5, n=1.0 + 1e-15)
+    a = oracle.run(h, p1, 5, lib=lib)["h"]
+    b = oracle.run(h, pn, 5, lib=lib)["h"]
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
+ALL_PINS = [pin_table1, pin_receivers_special_cases, pin_receivers_brute_force,
+            pin_levels_and_areas_brute_force, pin_forest_invariants, pin_one_step_dense_solve,
+            pin_no_erosion_is_pure_uplift, pin_long_step_follows_receiver,
+            pin_steady_state_slope_area, pin_channel_profile, pin_newton_matches_closed_form]

@@ -1,0 +1,62 @@
+"""Mutation test of the oracle's pins: plant one plausible mistake at a time
+in a copy of the oracle (on the CPU), rebuild it, and require that at least
+one pin fails.  A mistake no pin catches would mean the pins are too weak."""
+from __future__ import annotations
+
+import os
+import shutil
+
+import pytest
+
+import oracle
+from tests import oracle_pins
+
+MUTANTS = [
+    ("diagonal distance is dx", "dist[k] = ddiag;", "dist[k] = dx;"),
+    ("ties go to the last neighbour", "if (s > smax) {", "if (s >= smax) {"),
+    ("transposed neighbour offset",
+     "(int64_t)(y + LEMO_DY[k]) * nx + (x + LEMO_DX[k])",
+     "(int64_t)(y + LEMO_DX[k]) * nx + (x + LEMO_DY[k])"),
+    ("dx and dy swapped", "dist[k] = dy;\n    else\n      dist[k] = dx;",
+     "dist[k] = dx;\n    else\n      dist[k] = dy;"),
+    ("donors of the perimeter ignored", "dnum[c] = 0;\n      for (int k = 0; k < 8; ++k) {",
+     "dnum[c] = 0;\n      if (lemo_is_perimeter(ny, nx, y, x)) continue;\n      for (int k = 0; k < 8; ++k) {"),
+    ("stack visits donors in reverse", "for (int k = (int)dnum[c] - 1; k >= 0; --k) {",
+     "for (int k = 0; k < (int)dnum[c]; ++k) {"),
+    ("first level offset is 1", "levels[ls++] = 0;", "levels[ls++] = 1;"),
+    ("cell does not count itself", "uint32_t a = 1u;", "uint32_t a = 0u;"),
+    ("perimeter is uplifted", "for (int32_t y = 1; y < ny - 1; ++y) {\n    for (int32_t x = 1; x < nx - 1; ++x) {\n      const int64_t c = (int64_t)y * nx + x;\n      h[c] = h[c] + (Ufield",
+     "for (int32_t y = 0; y < ny; ++y) {\n    for (int32_t x = 0; x < nx; ++x) {\n      const int64_t c = (int64_t)y * nx + x;\n      h[c] = h[c] + (Ufield"),
+    ("F without dt", "const double f = ((kc * dt) * am) / d;", "const double f = (kc * am) / d;"),
+    ("area without cell size", "const double area = (double)count[c] * dxdy;\n    const double am",
+     "const double area = (double)count[c];\n    const double am"),
+    ("wrong sign in the update", "h[c] = (h[c] + f * h[r]) / (1.0 + f);",
+     "h[c] = (h[c] - f * h[r]) / (1.0 + f);"),
+    ("old receiver height (reverse order)",
+     "for (int64_t i = 0; i < n; ++i) {\n    const int32_t c = order[i];\n    const int32_t r = rec[c];\n    if (r == c) continue;\n    const int32_t cy = c / nx, cx = c % nx, ry = r / nx, rx = r % nx;\n    const double d = (cy != ry && cx != rx) ? ddiag : (cy != ry ? dy : dx);\n    const double area = (double)count[c] * dxdy;\n    const double am",
+     "for (int64_t i = n - 1; i >= 0; --i) {\n    const int32_t c = order[i];\n    const int32_t r = rec[c];\n    if (r == c) continue;\n    const int32_t cy = c / nx, cx = c % nx, ry = r / nx, rx = r % nx;\n    const double d = (cy != ry && cx != rx) ? ddiag : (cy != ry ? dy : dx);\n    const double area = (double)count[c] * dxdy;\n    const double am"),
+    ("pits are not uplifted", "h[c] = h[c] + (Ufield ? Ufield[c] * dt : udt);",
+     "if (h[c] > 0.5) h[c] = h[c] + (Ufield ? Ufield[c] * dt : udt);"),
+    ("K field ignored", "const double kc = Kfield ? Kfield[c] : K;\n    const double f = ((kc",
+     "const double kc = K;\n    const double f = ((kc"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(tmp_path, name, old, new):
+    src = open(oracle.SOURCE).read()
+    assert src.count(old) >= 1, f"mutation site not found: {name}"
+    mutated = src.replace(old, new, 1)
+    d = tmp_path / "m"
+    d.mkdir()
+    (d / "lem_oracle.c").write_text(mutated)
+    shutil.copy(os.path.join(os.path.dirname(oracle.SOURCE), "lem_oracle.h"), d / "lem_oracle.h")
+    path = oracle.build(str(d / "lem_oracle.c"), str(d / "libmut.so"))
+    lib = oracle.load(path)
+    failed = []
+    for pin in oracle_pins.ALL_PINS:
+        try:
+            pin(lib)
+        except (AssertionError, ValueError):
+            failed.append(pin.__name__)
+    assert failed, f"no pin catches the mutant '{name}'"
