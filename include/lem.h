@@ -1,0 +1,160 @@
+/*
+ * lem.h -- C ABI of the MI355X (gfx950) landscape-evolution library.
+ *
+ * The library runs the per-timestep hot path of R. Barnes, "Accelerating a
+ * Landscape Evolution Model with Parallelism" (arXiv:1803.02977) on one GPU:
+ *   Step 2 / Algorithm 1  D8 steepest-descent receivers,
+ *   Step 3 / Algorithm 2  donor inversion,
+ *   Step 4 / Algorithm 3  breadth-first levels outward from cells without a
+ *                         receiver,
+ *   Step 5 / Algorithm 4  drainage area (Equation "flow_acc") in reverse
+ *                         level order,
+ *   Step 6 / Algorithm 5  uplift, and
+ *   Step 7 / Algorithm 6  implicit stream-power erosion (Equation
+ *                         "streampower" with slope exponent n = 1) in level
+ *                         order,
+ * repeated once per time step ("Rinse, Repeat").
+ *
+ * Conventions shared by every entry point:
+ *  - Grids are FP64, row-major, ny rows by nx columns; cell (x, y) is element
+ *    y*nx + x (Step 1).  The perimeter is the fixed base level (section "The
+ *    Equation"): perimeter cells are never written and pass no flow.
+ *  - Pointers named d_* are device pointers on the GPU that was current when
+ *    the context was created; pointers named h_* are host pointers.  The
+ *    caller owns every buffer.  The library allocates no device memory: its
+ *    scratch space is the caller's workspace (see lem_workspace_bytes).
+ *  - Work is enqueued on the HIP stream given to lem_create and returns
+ *    before it completes; device buffers must stay valid until the stream
+ *    has finished it.  Calls on one context must not overlap in time.
+ *  - Every call returns a lem_status; nothing is thrown or aborted across the
+ *    ABI.  Argument errors are detected before anything is enqueued and leave
+ *    all buffers untouched.  Errors found by the device (LEM_E_CYCLE) are
+ *    reported by the next lem_sync; the heights are then unspecified.
+ */
+#ifndef LEM_H
+#define LEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lem_status {
+  LEM_OK = 0,
+  LEM_E_ARG = 1,        /* a NULL pointer, a bad size or a bad parameter          */
+  LEM_E_SIZE = 2,       /* the grid is too small (< 3x3) or too large (> 2^31-1)  */
+  LEM_E_WORKSPACE = 3,  /* the workspace is missing, misaligned or too small      */
+  LEM_E_NONFINITE = 4,  /* LEM_F_VALIDATE found a NaN or infinity in an input     */
+  LEM_E_CYCLE = 5,      /* receivers form a cycle (only possible with fixed routing) */
+  LEM_E_HIP = 6,        /* a HIP runtime call failed                              */
+  LEM_E_STATE = 7       /* the call needs state the context does not have yet     */
+} lem_status;
+
+/* lem_params.flags */
+#define LEM_F_VALIDATE 0x1u     /* scan h, K and U for non-finite values before a run */
+#define LEM_F_PHASE_TIMERS 0x2u /* record per-phase device time with HIP events       */
+
+/* Problem statement (section "The Equation"; Step 1 "Initialization"):
+ *   ny, nx  rows and columns, each >= 3, ny*nx <= 2^31-1;
+ *   dx, dy  cell size in metres (> 0); diagonal neighbours are
+ *           sqrt(dx*dx + dy*dy) apart;
+ *   dt      time step in years (> 0);
+ *   m       exponent of the drainage area, m-hat (>= 0, finite);
+ *   n       exponent of the slope, n-hat: must be exactly 1.0;
+ *   U       uplift rate u-hat in m/yr, used where no U field is given;
+ *   K       erodibility in 1/yr (>= 0), used where no K field is given;
+ *   flags   LEM_F_* bits.                                                    */
+typedef struct lem_params {
+  int32_t ny, nx;
+  double dx, dy;
+  double dt;
+  double m;
+  double n;
+  double U, K;
+  uint32_t flags;
+} lem_params;
+
+/* Per-context statistics (filled by lem_stats). */
+typedef struct lem_stats_t {
+  int64_t steps_done;      /* steps completed by all lem_run* calls on this context  */
+  int64_t last_nlevels;    /* number of levels (Algorithm 3) of the most recent step */
+  int64_t max_nlevels;     /* largest level count of any step of the last run        */
+  int64_t last_run_steps;  /* steps of the last run                                  */
+  double phase_ms[4];      /* device ms of the last run with LEM_F_PHASE_TIMERS:
+                              [0] receivers+donors, [1] level ordering,
+                              [2] accumulation, [3] uplift+erosion                 */
+} lem_stats_t;
+
+typedef struct lem_ctx lem_ctx;
+
+/* Bytes of device workspace a context with these parameters needs, or 0 if
+ * the parameters are invalid.  The workspace holds the receiver codes, donor
+ * masks, the level queue and its offsets, drainage counts and the queue-order
+ * heights (Steps 2 to 7); it is about 24 bytes per cell. */
+size_t lem_workspace_bytes(const lem_params* p);
+
+/* Validates p and creates a context that uses d_workspace (device memory of
+ * ws_bytes >= lem_workspace_bytes(p), 256-byte aligned, owned by the caller,
+ * valid for the life of the context) and enqueues on hip_stream (a
+ * hipStream_t; NULL means the default stream).  Allocates host memory only.
+ * On success *out receives the context. */
+lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes,
+                      void* hip_stream, lem_ctx** out);
+
+/* Enqueues `steps` time steps (Steps 2 to 7, repeated) on d_h, updated in
+ * place.  d_K and d_U are optional per-cell fields (NULL: use p->K, p->U),
+ * read-only, ny*nx doubles each.  Each step routes flow on the heights it
+ * starts from, then uplifts every interior cell by U*dt and erodes every cell
+ * that has a receiver by the implicit n = 1 update
+ * h <- (h + F*h_rec)/(1 + F), F = K*dt*A^m/dist, A = dx*dy*(upstream cells).
+ * steps == 0 is a no-op. */
+lem_status lem_run(lem_ctx* ctx, double* d_h, const double* d_K, const double* d_U,
+                   int64_t steps);
+
+/* As lem_run, but Step 2 is replaced by fixed receivers given as direction
+ * codes d_rcode[ny*nx] (0..7 = neighbour (dy,dx) in the order (-1,-1) (-1,0)
+ * (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1); 8 = no receiver).  Codes must stay
+ * inside the grid; perimeter cells must be 8.  Receivers that form a cycle
+ * are reported as LEM_E_CYCLE by lem_sync.  Intended for tests and for
+ * callers that route flow themselves. */
+lem_status lem_run_fixed_routing(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode,
+                                 const double* d_K, const double* d_U, int64_t steps);
+
+/* Waits for the context's stream and reports device-detected errors of the
+ * work enqueued so far (LEM_E_CYCLE), then clears them. */
+lem_status lem_sync(lem_ctx* ctx);
+
+/* Exports the routing of the most recent step (computed from that step's
+ * starting heights): per cell the receiver index d_rec (itself when the cell
+ * has no receiver), the level d_depth (Algorithm 3: 0 for cells without a
+ * receiver) and the number of upstream cells d_count (drainage area divided
+ * by dx*dy, Equation "flow_acc"); and the level offsets into the queue,
+ * h_level_offsets[0..nlevels] (offset 0 is 0, the last is ny*nx), written
+ * when cap >= nlevels + 1.  *h_nlevels receives nlevels.  Any d_* pointer
+ * may be NULL.  Synchronizes the stream.  LEM_E_STATE before any step. */
+lem_status lem_routing(lem_ctx* ctx, int32_t* d_rec, int32_t* d_depth, uint32_t* d_count,
+                       int64_t* h_level_offsets, int64_t cap, int64_t* h_nlevels);
+
+/* Copies the level count of each step of the last run into h_levels
+ * (up to cap entries; *h_n receives the number of steps recorded). */
+lem_status lem_level_history(lem_ctx* ctx, int32_t* h_levels, int64_t cap, int64_t* h_n);
+
+/* Fills *out; synchronizes the stream. */
+lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out);
+
+/* Destroys the context (host state only; the workspace stays the caller's).
+ * Waits for the stream first.  NULL is a no-op. */
+lem_status lem_destroy(lem_ctx* ctx);
+
+/* Static description of a status code. */
+const char* lem_status_str(lem_status s);
+
+/* Message of the most recent error on this context ("" if none). */
+const char* lem_last_error(const lem_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LEM_H */

@@ -1,0 +1,238 @@
+"""ctypes binding of the C ABI in ``include/lem.h`` (argument marshalling only).
+
+Every function has the name of the C entry point it wraps.  ``Solver`` is a
+convenience wrapper that takes torch tensors on the ROCm device (torch is used
+for device memory and streams only) and calls the same entry points.  Nothing
+here computes any step of the method; if ``liblem.so`` is missing, loading
+fails with an error instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblem.so")
+
+LEM_OK, LEM_E_ARG, LEM_E_SIZE, LEM_E_WORKSPACE = 0, 1, 2, 3
+LEM_E_NONFINITE, LEM_E_CYCLE, LEM_E_HIP, LEM_E_STATE = 4, 5, 6, 7
+LEM_F_VALIDATE, LEM_F_PHASE_TIMERS = 0x1, 0x2
+
+# Symbols declared in include/lem.h.
+EXPORTS = ("lem_workspace_bytes", "lem_create", "lem_run", "lem_run_fixed_routing",
+           "lem_sync", "lem_routing", "lem_level_history", "lem_stats", "lem_destroy",
+           "lem_status_str", "lem_last_error")
+
+
+class lem_params(C.Structure):
+    _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("dt", C.c_double), ("m", C.c_double), ("n", C.c_double), ("U", C.c_double),
+                ("K", C.c_double), ("flags", C.c_uint32)]
+
+
+class lem_stats_t(C.Structure):
+    _fields_ = [("steps_done", C.c_int64), ("last_nlevels", C.c_int64),
+                ("max_nlevels", C.c_int64), ("last_run_steps", C.c_int64),
+                ("phase_ms", C.c_double * 4)]
+
+
+class LemError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+_LIB = None
+_P = C.c_void_p
+
+
+def load(path: str = LIB_PATH):
+    """Load ``liblem.so``; raise if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = C.CDLL(path)
+    lib.lem_workspace_bytes.argtypes = [C.POINTER(lem_params)]
+    lib.lem_workspace_bytes.restype = C.c_size_t
+    lib.lem_create.argtypes = [C.POINTER(lem_params), _P, C.c_size_t, _P, C.POINTER(_P)]
+    lib.lem_create.restype = C.c_int
+    lib.lem_run.argtypes = [_P, _P, _P, _P, C.c_int64]
+    lib.lem_run.restype = C.c_int
+    lib.lem_run_fixed_routing.argtypes = [_P, _P, _P, _P, _P, C.c_int64]
+    lib.lem_run_fixed_routing.restype = C.c_int
+    lib.lem_sync.argtypes = [_P]
+    lib.lem_sync.restype = C.c_int
+    lib.lem_routing.argtypes = [_P, _P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]
+    lib.lem_routing.restype = C.c_int
+    lib.lem_level_history.argtypes = [_P, _P, C.c_int64, C.POINTER(C.c_int64)]
+    lib.lem_level_history.restype = C.c_int
+    lib.lem_stats.argtypes = [_P, C.POINTER(lem_stats_t)]
+    lib.lem_stats.restype = C.c_int
+    lib.lem_destroy.argtypes = [_P]
+    lib.lem_destroy.restype = C.c_int
+    lib.lem_status_str.argtypes = [C.c_int]
+    lib.lem_status_str.restype = C.c_char_p
+    lib.lem_last_error.argtypes = [_P]
+    lib.lem_last_error.restype = C.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(st: int, ctx=None):
+    if st != LEM_OK:
+        lib = load()
+        msg = lib.lem_status_str(st).decode()
+        if ctx:
+            detail = lib.lem_last_error(ctx).decode()
+            if detail:
+                msg = f"{msg} ({detail})"
+        raise LemError(st, msg)
+
+
+# --- one wrapper per C entry point ------------------------------------------------
+
+def lem_workspace_bytes(p: lem_params) -> int:
+    return int(load().lem_workspace_bytes(C.byref(p)))
+
+
+def lem_create(p: lem_params, d_workspace: int, ws_bytes: int, hip_stream: int) -> int:
+    ctx = _P()
+    _check(load().lem_create(C.byref(p), d_workspace, ws_bytes, hip_stream, C.byref(ctx)))
+    return ctx.value
+
+
+def lem_run(ctx: int, d_h: int, d_K, d_U, steps: int) -> None:
+    _check(load().lem_run(ctx, d_h, d_K, d_U, steps), ctx)
+
+
+def lem_run_fixed_routing(ctx: int, d_h: int, d_rcode: int, d_K, d_U, steps: int) -> None:
+    _check(load().lem_run_fixed_routing(ctx, d_h, d_rcode, d_K, d_U, steps), ctx)
+
+
+def lem_sync(ctx: int) -> None:
+    _check(load().lem_sync(ctx), ctx)
+
+
+def lem_routing(ctx: int, d_rec, d_depth, d_count, cap: int):
+    import numpy as np
+    offsets = np.zeros(max(cap, 1), np.int64)
+    nl = C.c_int64(0)
+    _check(load().lem_routing(ctx, d_rec, d_depth, d_count,
+                              offsets.ctypes.data_as(_P), cap, C.byref(nl)), ctx)
+    return offsets[: nl.value + 1] if cap >= nl.value + 1 else None, nl.value
+
+
+def lem_level_history(ctx: int, cap: int):
+    import numpy as np
+    out = np.zeros(max(cap, 1), np.int32)
+    n = C.c_int64(0)
+    _check(load().lem_level_history(ctx, out.ctypes.data_as(_P), cap, C.byref(n)), ctx)
+    return out[: min(n.value, cap)]
+
+
+def lem_stats(ctx: int) -> lem_stats_t:
+    s = lem_stats_t()
+    _check(load().lem_stats(ctx, C.byref(s)), ctx)
+    return s
+
+
+def lem_destroy(ctx: int) -> None:
+    _check(load().lem_destroy(ctx))
+
+
+def lem_status_str(st: int) -> str:
+    return load().lem_status_str(st).decode()
+
+
+def lem_last_error(ctx: int) -> str:
+    return load().lem_last_error(ctx).decode()
+
+
+# --- torch convenience -----------------------------------------------------------
+
+def _dptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Solver:
+    """A context plus its workspace, for torch tensors on one ROCm device.
+
+    ``run(h, steps, K=None, U=None)`` updates ``h`` (float64, contiguous,
+    shape (ny, nx), on the device) in place on the current torch stream.
+    """
+
+    def __init__(self, ny, nx, dx=100.0, dy=100.0, dt=1000.0, m=0.5, U=5e-4, K=1e-5,
+                 n=1.0, flags=0, device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self.params = lem_params(ny, nx, dx, dy, dt, m, n, U, K, flags)
+        nbytes = lem_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise LemError(LEM_E_ARG, "invalid parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.ctx = lem_create(self.params, self.workspace.data_ptr(), nbytes,
+                                  self.stream.cuda_stream)
+
+    def _check_field(self, t, name):
+        torch = self.torch
+        if t is None:
+            return None
+        shape = (self.params.ny, self.params.nx)
+        if (t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous()
+                or t.device != self.device):
+            raise LemError(LEM_E_ARG, f"{name} must be a contiguous float64 {shape} tensor "
+                                      f"on {self.device}")
+        return t
+
+    def run(self, h, steps, K=None, U=None):
+        self._check_field(h, "h")
+        lem_run(self.ctx, h.data_ptr(), _dptr(self._check_field(K, "K")),
+                _dptr(self._check_field(U, "U")), int(steps))
+
+    def run_fixed_routing(self, h, rcode, steps, K=None, U=None):
+        torch = self.torch
+        self._check_field(h, "h")
+        if (rcode.dtype != torch.uint8 or tuple(rcode.shape) != tuple(h.shape)
+                or not rcode.is_contiguous() or rcode.device != self.device):
+            raise LemError(LEM_E_ARG, "rcode must be a contiguous uint8 tensor like h")
+        lem_run_fixed_routing(self.ctx, h.data_ptr(), rcode.data_ptr(),
+                              _dptr(self._check_field(K, "K")),
+                              _dptr(self._check_field(U, "U")), int(steps))
+
+    def sync(self):
+        lem_sync(self.ctx)
+
+    def routing(self):
+        """Routing of the last step: rec, depth, count (device tensors), offsets."""
+        torch = self.torch
+        shape = (self.params.ny, self.params.nx)
+        rec = torch.empty(shape, dtype=torch.int32, device=self.device)
+        depth = torch.empty(shape, dtype=torch.int32, device=self.device)
+        count = torch.empty(shape, dtype=torch.int32, device=self.device)  # holds uint32 bits
+        offsets, nl = lem_routing(self.ctx, rec.data_ptr(), depth.data_ptr(),
+                                  count.data_ptr(), 0)
+        offsets, _ = lem_routing(self.ctx, None, None, None, nl + 1)
+        return dict(rec=rec, depth=depth, count=count, offsets=offsets, nlevels=nl)
+
+    def level_history(self, cap=1 << 16):
+        return lem_level_history(self.ctx, cap)
+
+    def stats(self) -> lem_stats_t:
+        return lem_stats(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lem_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
