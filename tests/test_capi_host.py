@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/lem.h declares, and rejects bad arguments before it
+touches the device."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1803_02977_amd as pkg
+from paper_1803_02977_amd import lem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    names = []
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(lem_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load()
+    names = declared_entry_points()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), f"{n} is declared but not exported"
+    assert set(names) >= set(lem.EXPORTS)
+
+
+def _params(**kw):
+    base = dict(ny=256, nx=256, dx=100.0, dy=100.0, dt=1000.0, m=0.5, n=1.0, U=5e-4, K=1e-5,
+                flags=0)
+    base.update(kw)
+    return lem.lem_params(**base)
+
+
+def test_workspace_bytes():
+    small = lem.lem_workspace_bytes(_params())
+    big = lem.lem_workspace_bytes(_params(ny=2048, nx=2048))
+    assert small > 256 * 256 * 20
+    assert big > small
+    assert (big - small) / (2048 * 2048 - 256 * 256) < 48
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(ny=2), lem.LEM_E_SIZE), (dict(nx=0), lem.LEM_E_SIZE),
+    (dict(ny=50000, nx=50000), lem.LEM_E_SIZE),
+    (dict(dx=0.0), lem.LEM_E_ARG), (dict(dy=-1.0), lem.LEM_E_ARG),
+    (dict(dt=float("nan")), lem.LEM_E_ARG), (dict(m=-0.1), lem.LEM_E_ARG),
+    (dict(n=2.0), lem.LEM_E_ARG), (dict(K=-1e-5), lem.LEM_E_ARG),
+    (dict(U=float("inf")), lem.LEM_E_ARG), (dict(flags=0x80), lem.LEM_E_ARG),
+])
+def test_bad_parameters_are_rejected_on_the_host(kw, status):
+    p = _params(**kw)
+    assert lem.lem_workspace_bytes(p) == 0
+    lib = pkg.load()
+    ctx = C.c_void_p()
+    assert lib.lem_create(C.byref(p), C.c_void_p(1 << 20), 1 << 40, None, C.byref(ctx)) == status
+    assert ctx.value is None
+
+
+def test_workspace_is_checked_before_the_device():
+    lib = pkg.load()
+    p = _params()
+    need = lem.lem_workspace_bytes(p)
+    ctx = C.c_void_p()
+    assert lib.lem_create(C.byref(p), None, need, None, C.byref(ctx)) == lem.LEM_E_WORKSPACE
+    assert lib.lem_create(C.byref(p), C.c_void_p(4096 + 8), need, None,
+                          C.byref(ctx)) == lem.LEM_E_WORKSPACE
+    assert lib.lem_create(C.byref(p), C.c_void_p(4096), need - 1, None,
+                          C.byref(ctx)) == lem.LEM_E_WORKSPACE
+    assert lib.lem_create(C.byref(p), C.c_void_p(4096), need, None, None) == lem.LEM_E_ARG
+
+
+def test_null_context_calls():
+    lib = pkg.load()
+    assert lib.lem_run(None, None, None, None, 1) == lem.LEM_E_ARG
+    assert lib.lem_sync(None) == lem.LEM_E_ARG
+    assert lib.lem_destroy(None) == lem.LEM_OK
+    assert lib.lem_last_error(None) == b""
+    for s in range(8):
+        assert lib.lem_status_str(s).startswith(b"LEM_")
