@@ -84,7 +84,11 @@ typedef struct lem_stats_t {
   int64_t last_run_steps;  /* steps of the last run                                  */
   double phase_ms[4];      /* device ms of the last run with LEM_F_PHASE_TIMERS:
                               [0] receivers+donors, [1] level ordering,
-                              [2] accumulation, [3] uplift+erosion                 */
+                              [2] accumulation, [3] uplift+erosion (phases 1-3 by
+                              the device clock inside the ordering kernel)         */
+  double kernel_ms[2];     /* HIP-event ms of the last run with LEM_F_PHASE_TIMERS,
+                              summed over its steps: [0] receiver and donor sweeps,
+                              [1] the ordering/accumulation/erosion kernel          */
 } lem_stats_t;
 
 typedef struct lem_ctx lem_ctx;

@@ -22,8 +22,9 @@ struct lem_ctx {
   int64_t steps_done;
   int64_t last_run_steps;
   bool has_routing;
-  float route_ms;        // accumulated with LEM_F_PHASE_TIMERS
-  hipEvent_t ev0, ev1;
+  double route_ms;       // accumulated with LEM_F_PHASE_TIMERS
+  double order_ms;
+  hipEvent_t ev0, ev1, ev2;
   std::string err;
 };
 
@@ -118,22 +119,27 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
   e = lem::launch_begin_run(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "begin-run launch");
   const bool timers = (ctx->p.flags & LEM_F_PHASE_TIMERS) != 0;
-  ctx->route_ms = 0.f;
+  ctx->route_ms = 0.0;
+  ctx->order_ms = 0.0;
   for (int64_t s = 0; s < steps; ++s) {
     a.step = s;
     if (timers) (void)hipEventRecord(ctx->ev0, ctx->stream);
     e = d_rcode ? lem::launch_fixed_routing(a, d_rcode, ctx->stream)
                 : lem::launch_route(a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "routing launch");
-    if (timers) {
-      (void)hipEventRecord(ctx->ev1, ctx->stream);
-      (void)hipEventSynchronize(ctx->ev1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-      ctx->route_ms += ms;
-    }
+    if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
     e = lem::launch_order_accum_erode(a, ctx->grid, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "ordering launch");
+    if (timers) {
+      (void)hipEventRecord(ctx->ev2, ctx->stream);
+      e = hipEventSynchronize(ctx->ev2);
+      if (e != hipSuccess) return hip_fail(ctx, e, "timer event");
+      float ms0 = 0.f, ms1 = 0.f;
+      (void)hipEventElapsedTime(&ms0, ctx->ev0, ctx->ev1);
+      (void)hipEventElapsedTime(&ms1, ctx->ev1, ctx->ev2);
+      ctx->route_ms += ms0;
+      ctx->order_ms += ms1;
+    }
   }
   ctx->steps_done += steps;
   ctx->last_run_steps = steps;
@@ -173,6 +179,7 @@ lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes, v
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, ctx->device);
   if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
   if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->ev2);
   if (e != hipSuccess || per_cu < 1) {
     delete ctx;
     return LEM_E_HIP;
@@ -276,6 +283,8 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out) {
   out->max_nlevels = ct.max_nlevels;
   out->last_run_steps = ctx->last_run_steps;
   out->phase_ms[0] = ctx->route_ms;
+  out->kernel_ms[0] = ctx->route_ms;
+  out->kernel_ms[1] = ctx->order_ms;
   for (int k = 1; k < 4; ++k)
     out->phase_ms[k] = ctx->tick_khz > 0 ? (double)ct.ticks[k] / ctx->tick_khz : 0.0;
   return LEM_OK;
@@ -286,6 +295,7 @@ lem_status lem_destroy(lem_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipEventDestroy(ctx->ev0);
   (void)hipEventDestroy(ctx->ev1);
+  (void)hipEventDestroy(ctx->ev2);
   delete ctx;
   return LEM_OK;
 }

@@ -75,6 +75,11 @@ __device__ __forceinline__ int64_t neighbour_offset(int k, int nx) {
   return (int64_t)dy * nx + dx;
 }
 
+// A^m: sqrt for m = 0.5 and A itself for m = 1 (both exact), pow otherwise.
+__device__ __forceinline__ double area_power(double area, const StepArgs& a) {
+  return a.use_sqrt ? sqrt(area) : (a.m == 1.0 ? area : pow(area, a.m));
+}
+
 __device__ __forceinline__ double code_distance(int k, double dx, double dy, double ddiag) {
   return (k == 1 || k == 6) ? dy : ((k == 3 || k == 4) ? dx : ddiag);
 }
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_order_accum_erode(StepArgs a) {
       const double hr = w.hq[p];
       const double d = code_distance(w.kq[i], a.dx, a.dy, a.ddiag);
       const double area = (double)w.cnt[i] * a.dxdy;
-      const double am = a.use_sqrt ? sqrt(area) : pow(area, a.m);
+      const double am = area_power(area, a);
       const double kc = a.Kf ? a.Kf[c] : a.K;
       const double f = ((kc * a.dt) * am) / d;
       const double h0 = a.h[c] + (a.Uf ? a.Uf[c] * a.dt : a.udt);

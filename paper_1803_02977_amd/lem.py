@@ -33,7 +33,7 @@ class lem_params(C.Structure):
 class lem_stats_t(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("last_nlevels", C.c_int64),
                 ("max_nlevels", C.c_int64), ("last_run_steps", C.c_int64),
-                ("phase_ms", C.c_double * 4)]
+                ("phase_ms", C.c_double * 4), ("kernel_ms", C.c_double * 2)]
 
 
 class LemError(RuntimeError):
