@@ -27,14 +27,20 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
-# Algorithmic bytes per cell-update: each per-cell array counted as written
-# once and read once by each consuming phase, at its minimal width (h 32 B,
-# receiver code 2, donor mask 3, queue 16, counts 12; +8 for a K field).  The
-# ordering/accumulation/erosion kernel moves all of it except the receiver
-# sweep's h read and the two code/mask writes (10 B).
+# Algorithmic bytes per cell-update.
+#  - The whole step, counted as the level-queue formulation of the method
+#    moves it: each per-cell array written once and read once by each
+#    consuming phase at its minimal width (h 32 B, receiver code 2, donor
+#    mask 3, queue 16, counts 12; +8 per K or U field): 65 B.
+#  - k_tile_step (the fused tile pass): read h, write h, write the donor mask
+#    (8 + 8 + 1 B; +8 per K or U field read).
+#  - k_global_levels: the 65 B formulation minus the receiver sweep's h read
+#    and the code/mask writes (55 B), for each cell of a tree that crosses a
+#    tile edge.
 ALG_BYTES_STEP = 65
-ALG_BYTES_ROUTE = 10
-ALG_BYTES_K_FIELD = 8
+ALG_BYTES_TILE = 17
+ALG_BYTES_GLOBAL = 55
+ALG_BYTES_FIELD = 8
 
 
 def parse():
@@ -47,6 +53,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--repeats", type=int, default=1)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device-to-device copy of 2 GiB (three times) "
+                         "whose HBM counters calibrate FETCH_SIZE and WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -114,21 +123,27 @@ def main():
     tsolver.run(h, steps, K=Kt)
     tsolver.sync()
     st = tsolver.stats()
+    tsolver_crossing = st.crossing_run / steps
     tsolver.close()
-    route_ms = st.kernel_ms[0] / steps
-    order_ms = st.kernel_ms[1] / steps
+    tile_ms = st.kernel_ms[0] / steps
+    global_ms = st.kernel_ms[1] / steps
+    crossing = tsolver_crossing
 
     cells = w.cells
     value = cells * steps / (ms / 1e3)
-    alg_step = ALG_BYTES_STEP + (ALG_BYTES_K_FIELD if Kt is not None else 0)
-    alg_order = alg_step - ALG_BYTES_ROUTE
-    roofline = None
-    if order_ms:
-        achieved = alg_order * cells / (order_ms / 1e3) / 1e9
-        roofline = dict(bound="hbm", kernel="k_order_accum_erode", achieved=round(achieved, 1),
-                        peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                        traffic=None, alg_bytes_per_cell=alg_order,
-                        avg_launch_ms=round(order_ms, 4))
+    fields = (Kt is not None)
+    alg_step = ALG_BYTES_STEP + ALG_BYTES_FIELD * fields
+    alg_tile = ALG_BYTES_TILE + ALG_BYTES_FIELD * fields
+    if tile_ms >= global_ms:
+        kname, kms, kbytes = "k_tile_step", tile_ms, alg_tile * cells
+        per_unit = f"{alg_tile} B per cell"
+    else:
+        kname, kms, kbytes = "k_global_levels", global_ms, ALG_BYTES_GLOBAL * crossing
+        per_unit = f"{ALG_BYTES_GLOBAL} B per crossing-tree cell"
+    achieved = kbytes / (kms / 1e3) / 1e9
+    roofline = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    alg_bytes=per_unit, avg_launch_ms=round(kms, 4))
     out = {
         "metric": "cell-updates/s",
         "value": value,
@@ -146,14 +161,25 @@ def main():
                    "m": w.m, "n": 1.0, "U": w.U, "K": w.K,
                    "K_field": "lognormal" if Kt is not None else "scalar", "seed": args.seed},
         "roofline": roofline,
-        "step_roofline_frac": round(value * alg_step / (HBM_PEAK_GBS * 1e9), 4),
+        "hbm_roofline_frac_65B": round(value * alg_step / (HBM_PEAK_GBS * 1e9), 4),
         "wall_s": wall,
         "levels": {"min": int(levels.min()), "max": int(levels.max()),
                    "mean": float(levels.mean())} if len(levels) else None,
-        "phase_ms_per_step": {"route": route_ms, "order": st.phase_ms[1] / steps,
-                              "accumulate": st.phase_ms[2] / steps,
-                              "erode": st.phase_ms[3] / steps},
+        "kernel_ms_per_step": {"k_tile_step": tile_ms, "k_global_levels": global_ms},
+        "global_phase_ms_per_step": {"order": st.phase_ms[1] / steps,
+                                     "accumulate": st.phase_ms[2] / steps,
+                                     "erode": st.phase_ms[3] / steps},
+        "crossing_cells_per_step": crossing,
+        "crossing_frac": round(crossing / cells, 4),
     }
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes_each_way"] = src.numel() * 8
+        del src, dst
     if not args.no_cpu:
         cpu_steps = args.cpu_steps or (2 if cells >= 10 ** 8 else max(1, min(steps, int(2e8 // cells))))
         out["cpu_baseline"] = cpu_baseline(w, h0_np, K_np, cpu_steps)

@@ -83,12 +83,17 @@ typedef struct lem_stats_t {
   int64_t max_nlevels;     /* largest level count of any step of the last run        */
   int64_t last_run_steps;  /* steps of the last run                                  */
   double phase_ms[4];      /* device ms of the last run with LEM_F_PHASE_TIMERS:
-                              [0] receivers+donors, [1] level ordering,
-                              [2] accumulation, [3] uplift+erosion (phases 1-3 by
-                              the device clock inside the ordering kernel)         */
+                              [0] tile pass (receivers, donors, levels, counts and
+                              heights of trees inside one tile), [1] level
+                              ordering, [2] accumulation, [3] uplift+erosion of the
+                              trees that cross tile edges (1-3 by the device clock
+                              inside the global level kernel)                      */
   double kernel_ms[2];     /* HIP-event ms of the last run with LEM_F_PHASE_TIMERS,
-                              summed over its steps: [0] receiver and donor sweeps,
-                              [1] the ordering/accumulation/erosion kernel          */
+                              summed over its steps: [0] the tile pass, [1] the
+                              global level pass                                    */
+  int64_t crossing_last;   /* cells of the most recent step whose drainage tree
+                              crosses a tile edge (resolved by the global pass)     */
+  int64_t crossing_run;    /* the same, summed over the steps of the last run       */
 } lem_stats_t;
 
 typedef struct lem_ctx lem_ctx;
@@ -96,7 +101,8 @@ typedef struct lem_ctx lem_ctx;
 /* Bytes of device workspace a context with these parameters needs, or 0 if
  * the parameters are invalid.  The workspace holds the receiver codes, donor
  * masks, the level queue and its offsets, drainage counts and the queue-order
- * heights (Steps 2 to 7); it is about 24 bytes per cell. */
+ * heights, a second height buffer and the routing export (Steps 2 to 7); it
+ * is about 56 bytes per cell. */
 size_t lem_workspace_bytes(const lem_params* p);
 
 /* Validates p and creates a context that uses d_workspace (device memory of

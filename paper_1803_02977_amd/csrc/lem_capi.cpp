@@ -60,7 +60,7 @@ lem_status check_params(const lem_params* p, std::string* why) {
   return LEM_OK;
 }
 
-lem::StepArgs make_args(const lem_ctx* ctx, double* d_h, const double* d_K, const double* d_U) {
+lem::StepArgs make_args(const lem_ctx* ctx, const double* d_K, const double* d_U) {
   lem::StepArgs a{};
   const lem_params& p = ctx->p;
   a.ny = p.ny;
@@ -77,10 +77,11 @@ lem::StepArgs make_args(const lem_ctx* ctx, double* d_h, const double* d_K, cons
   a.udt = p.U * p.dt;
   a.Kf = d_K;
   a.Uf = d_U;
-  a.h = d_h;
   a.w = ctx->w;
   a.step = 0;
   a.timers = (p.flags & LEM_F_PHASE_TIMERS) ? 1 : 0;
+  a.tiles_x = (p.nx + lem::kTW - 1) / lem::kTW;
+  a.tiles_y = (p.ny + lem::kTH - 1) / lem::kTH;
   return a;
 }
 
@@ -115,21 +116,30 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
     lem_status st = validate_inputs(ctx, d_h, d_K, d_U);
     if (st != LEM_OK) return st;
   }
-  lem::StepArgs a = make_args(ctx, d_h, d_K, d_U);
+  lem::StepArgs a = make_args(ctx, d_K, d_U);
+  a.fixed = d_rcode ? 1 : 0;
   e = lem::launch_begin_run(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "begin-run launch");
+  if (d_rcode) {
+    e = lem::launch_fixed_routing(a, d_rcode, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fixed-routing launch");
+  }
   const bool timers = (ctx->p.flags & LEM_F_PHASE_TIMERS) != 0;
   ctx->route_ms = 0.0;
   ctx->order_ms = 0.0;
+  // Steps alternate between the caller's buffer and the workspace copy, so a
+  // tile never reads a neighbour's already-updated halo.
   for (int64_t s = 0; s < steps; ++s) {
     a.step = s;
+    a.h_in = (s & 1) ? ctx->w.h2 : d_h;
+    a.h_out = (s & 1) ? d_h : ctx->w.h2;
+    a.export_routing = (s == steps - 1) ? 1 : 0;
     if (timers) (void)hipEventRecord(ctx->ev0, ctx->stream);
-    e = d_rcode ? lem::launch_fixed_routing(a, d_rcode, ctx->stream)
-                : lem::launch_route(a, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "routing launch");
+    e = lem::launch_tile_step(a, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tile launch");
     if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
-    e = lem::launch_order_accum_erode(a, ctx->grid, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "ordering launch");
+    e = lem::launch_global_levels(a, ctx->grid, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "global-level launch");
     if (timers) {
       (void)hipEventRecord(ctx->ev2, ctx->stream);
       e = hipEventSynchronize(ctx->ev2);
@@ -140,6 +150,11 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
       ctx->route_ms += ms0;
       ctx->order_ms += ms1;
     }
+  }
+  if (steps & 1) {
+    e = hipMemcpyAsync(d_h, ctx->w.h2, sizeof(double) * (size_t)a.n, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "final copy");
   }
   ctx->steps_done += steps;
   ctx->last_run_steps = steps;
@@ -175,7 +190,7 @@ lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes, v
   hipError_t e = hipGetDevice(&ctx->device);
   int cus = 0, per_cu = 0, rate = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-  if (e == hipSuccess) e = lem::order_kernel_occupancy(&per_cu);
+  if (e == hipSuccess) e = lem::global_kernel_occupancy(&per_cu);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, ctx->device);
   if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
   if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
@@ -184,10 +199,9 @@ lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes, v
     delete ctx;
     return LEM_E_HIP;
   }
-  // Up to four resident workgroups per compute unit take part in the
-  // cooperative kernel: enough to cover memory latency, few enough that a
-  // grid-wide barrier stays cheap.
-  ctx->grid = cus * (per_cu < 4 ? per_cu : 4);
+  // The global level kernel uses at most kGlobalMaxWGs resident workgroups:
+  // a grid-wide barrier's cost grows with the number of participants.
+  ctx->grid = cus * per_cu < lem::kGlobalMaxWGs ? cus * per_cu : lem::kGlobalMaxWGs;
   ctx->tick_khz = (double)rate;
   e = hipMemsetAsync(ctx->w.ctrl, 0, sizeof(lem::Ctrl), ctx->stream);
   if (e != hipSuccess) {
@@ -232,10 +246,9 @@ lem_status lem_routing(lem_ctx* ctx, int32_t* d_rec, int32_t* d_depth, uint32_t*
   if (!ctx) return LEM_E_ARG;
   if (!ctx->has_routing) return fail(ctx, LEM_E_STATE, "no step has run on this context");
   if (cap < 0) return fail(ctx, LEM_E_ARG, "cap must be >= 0");
-  lem::StepArgs a = make_args(ctx, nullptr, nullptr, nullptr);
+  lem::StepArgs a = make_args(ctx, nullptr, nullptr);
   hipError_t e = hipSetDevice(ctx->device);
-  if (e == hipSuccess && (d_rec || d_depth || d_count))
-    e = lem::launch_export(a, d_rec, d_depth, d_count, ctx->stream);
+  if (e == hipSuccess) e = lem::launch_export(a, d_rec, d_depth, d_count, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "export launch");
   lem::Ctrl ct;
   e = hipMemcpyAsync(&ct, ctx->w.ctrl, sizeof(ct), hipMemcpyDeviceToHost, ctx->stream);
@@ -246,11 +259,16 @@ lem_status lem_routing(lem_ctx* ctx, int32_t* d_rec, int32_t* d_depth, uint32_t*
   if (h_level_offsets && cap >= nl + 1) {
     int32_t* tmp = new (std::nothrow) int32_t[nl + 1];
     if (!tmp) return fail(ctx, LEM_E_ARG, "host allocation failed");
-    e = hipMemcpy(tmp, ctx->w.lev, sizeof(int32_t) * (nl + 1), hipMemcpyDeviceToHost);
-    if (e == hipSuccess)
-      for (int64_t l = 0; l <= nl; ++l) h_level_offsets[l] = tmp[l];
+    e = hipMemcpy(tmp, ctx->w.dhist, sizeof(int32_t) * (nl + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) {
+      int64_t acc = 0;
+      for (int64_t l = 0; l <= nl; ++l) {
+        acc += (l == 0) ? 0 : tmp[l];
+        h_level_offsets[l] = acc;
+      }
+    }
     delete[] tmp;
-    if (e != hipSuccess) return hip_fail(ctx, e, "level offsets readback");
+    if (e != hipSuccess) return hip_fail(ctx, e, "level histogram readback");
   }
   return LEM_OK;
 }
@@ -285,6 +303,8 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out) {
   out->phase_ms[0] = ctx->route_ms;
   out->kernel_ms[0] = ctx->route_ms;
   out->kernel_ms[1] = ctx->order_ms;
+  out->crossing_last = ct.dirty_total;
+  out->crossing_run = ct.crossing_run;
   for (int k = 1; k < 4; ++k)
     out->phase_ms[k] = ctx->tick_khz > 0 ? (double)ct.ticks[k] / ctx->tick_khz : 0.0;
   return LEM_OK;

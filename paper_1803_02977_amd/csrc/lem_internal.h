@@ -11,40 +11,75 @@ namespace lem {
 // (dy,dx) = (-1,-1) (-1,0) (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1), i.e. in
 // ascending cell index; the opposite of code k is 7-k.  kSink: an interior
 // cell with no strictly lower neighbour (a root that is uplifted); kBase: a
-// perimeter cell (a root at base level that never changes).
+// perimeter cell (a root at base level that never changes); kNone: a
+// position outside the grid (only inside a tile's halo).
 constexpr uint8_t kSink = 8;
 constexpr uint8_t kBase = 9;
+constexpr uint8_t kNone = 10;
 
-// Threads per workgroup of the ordering/accumulation/erosion kernel and the
-// number of queue entries each thread takes per chunk.
-constexpr int kBlock = 256;
+// Tiles of the local pass: kTH x kTW cells per workgroup of kTileThreads.
+constexpr int kTH = 64;
+constexpr int kTW = 64;
+constexpr int kTileThreads = 512;
+// Levels a tile resolves on its own before it hands all its trees to the
+// global pass.
+constexpr int kLocalDepthCap = 255;
+// A^m is tabulated for upstream counts below kAmTab (same function, same
+// inputs as computing it in place).
+constexpr int kAmTab = 256;
+
+// Threads per workgroup of the global level kernel, the queue entries each
+// thread takes per chunk, the most workgroups it uses (a grid-wide barrier
+// costs about 45 ns per participating workgroup on this part), and the
+// level size below which one workgroup handles a level on its own.
+constexpr int kBlock = 1024;
 constexpr int kItems = 16;
 constexpr int kChunk = kBlock * kItems;
+constexpr int kGlobalMaxWGs = 128;
+constexpr int kTailLevel = 16384;
 
 // Device-side control block (one per context, in the workspace).
 struct Ctrl {
-  int32_t status;     // lem_status of device-detected errors (0 = OK)
-  int32_t nlevels;    // levels of the most recent step
-  int32_t total;      // cells enqueued by the most recent step
+  int32_t status;          // lem_status of device-detected errors (0 = OK)
+  int32_t nlevels;         // levels of the most recent step (whole grid)
+  int32_t dirty_total;     // cells the global pass ordered in the most recent step
+  int32_t dirty_nlevels;   // levels of the global pass in the most recent step
   int32_t max_nlevels;
-  int64_t steps;      // steps recorded in the level history of the current run
-  uint64_t ticks[4];  // device wall-clock ticks per phase (accumulated)
-  int32_t pad[48];
+  int32_t clean;           // cells resolved inside their tile (current step)
+  int32_t clean_maxdepth;  // deepest level among them (current step)
+  int32_t pad0;
+  int64_t steps;           // steps recorded in the level history of the current run
+  uint64_t ticks[4];       // device wall-clock ticks per phase (accumulated)
+  int32_t tail_lo, tail_hi, tail_L, tail_done;  // state handed back by a one-workgroup run
+  int64_t crossing_run;    // crossing-tree cells summed over the current run
+  int32_t pad[38];
+  // Grid-wide barrier of the global level kernel (own cache lines).
+  uint32_t bar_count;
+  uint32_t pad1[31];
+  uint32_t bar_gen;
+  uint32_t pad2[31];
 };
 
 // Pointers into the workspace.
 struct Work {
-  uint8_t* rcode;    // [N] receiver code per cell (grid order)
+  double* h2;        // [N] second height buffer (steps alternate between h and h2)
+  uint8_t* rcode;    // [N] receiver codes (fixed routing; export step)
   uint8_t* dmask;    // [N] donor mask per cell: bit k set <=> neighbour k drains here
-  int32_t* q;        // [N] queue: cell index per position, level-major
+  int32_t* q;        // [N] global queue: cell per position, level-major
   int32_t* par;      // [N] queue position of the receiver (-1 at level 0)
   int32_t* fc;       // [N] queue position of the first donor
   uint8_t* mq;       // [N] donor mask in queue order
   uint8_t* kq;       // [N] receiver code in queue order
   uint32_t* cnt;     // [N] upstream cell count in queue order
   double* hq;        // [N] new heights in queue order
-  int32_t* lcnt;     // [N+2] number of cells per level (built while ordering)
+  int32_t* lcnt;     // [N+2] cells appended per level
   int32_t* lev;      // [N+2] level offsets into the queue
+  int32_t* dep_g;    // [N] level per cell (export step)
+  uint32_t* cnt_g;   // [N] upstream count per cell (export step)
+  int32_t* dhist;    // [N+2] level histogram (export)
+  double* amtab;     // [kAmTab] A^m for small counts
+  double* ftab;      // [3*kAmTab] F = K*dt*A^m/d per distance class (scalar K)
+  double* gtab;      // [3*kAmTab] 1 + F
   int32_t* hist;     // [kHistCap] level count per step of the current run
   Ctrl* ctrl;
   int32_t* scratch;  // [kScratchInts] reductions (validation)
@@ -56,28 +91,32 @@ constexpr int64_t kScratchInts = 1024;
 // Everything one time step needs, passed by value to the kernels.
 struct StepArgs {
   int32_t ny, nx;
-  int32_t n;         // ny*nx
-  int32_t use_sqrt;  // m == 0.5: A^m computed as sqrt(A)
+  int32_t n;          // ny*nx
+  int32_t use_sqrt;   // m == 0.5: A^m computed as sqrt(A)
   double dx, dy, ddiag, dxdy;
   double dt, m, K, udt;
-  const double* Kf;  // nullable per-cell K
-  const double* Uf;  // nullable per-cell U
-  double* h;
+  const double* Kf;   // nullable per-cell K
+  const double* Uf;   // nullable per-cell U
+  const double* h_in; // heights at the start of the step
+  double* h_out;      // heights at the end of the step
   Work w;
-  int64_t step;      // index of this step within the run
-  int32_t timers;    // record per-phase ticks
+  int64_t step;       // index of this step within the run
+  int32_t timers;     // record per-phase ticks
+  int32_t fixed;      // receivers come from w.rcode (fixed routing)
+  int32_t export_routing;  // write per-cell codes, levels and counts
+  int32_t tiles_x, tiles_y;
 };
 
 size_t workspace_bytes(int64_t n);
 void carve(void* base, int64_t n, Work* w);
 
-hipError_t launch_route(const StepArgs& a, hipStream_t s);
-hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user_rcode, hipStream_t s);
-hipError_t launch_order_accum_erode(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_begin_run(const StepArgs& a, hipStream_t s);
+hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user_rcode, hipStream_t s);
+hipError_t launch_tile_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_export(const StepArgs& a, int32_t* rec, int32_t* depth, uint32_t* count,
                          hipStream_t s);
 hipError_t launch_validate(const double* x, int64_t n, int32_t* flag, hipStream_t s);
-hipError_t order_kernel_occupancy(int* blocks_per_cu);
+hipError_t global_kernel_occupancy(int* blocks_per_cu);
 
 }  // namespace lem

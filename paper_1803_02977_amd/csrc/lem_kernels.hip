@@ -1,34 +1,44 @@
 // lem_kernels.hip -- gfx950 kernels of the landscape-evolution hot path.
 //
-// One time step (Barnes, arXiv:1803.02977, Steps 2 to 7) is two launches:
+// One time step (Barnes, arXiv:1803.02977, Steps 2 to 7) is two launches.
 //
-//  k_receivers + k_donors   dense row-major sweeps over the grid:
-//      Step 2 / Algorithm 1: receiver code per cell (strict ">" over the
-//      slopes (h_c - h_n)/dist in neighbour order, first maximum wins);
-//      Step 3 / Algorithm 2: donor bit mask per cell, over every cell.
+//  k_tile_step   one workgroup of 512 threads per 64x64 tile.  The tile's heights and a
+//      2-cell halo are staged in LDS once.  In LDS the workgroup computes
+//      Step 2 / Algorithm 1 (receivers) for the tile and its 1-cell ring,
+//      Step 3 / Algorithm 2 (donor masks) for the tile, and the breadth-first
+//      levels of Step 4 / Algorithm 3 restricted to the tile, starting from
+//      every cell without a receiver and from every cell whose receiver lies
+//      outside the tile.  A tree whose root has no receiver and which has no
+//      donor outside the tile is the whole tree of the method: its levels are
+//      its global levels, so the workgroup finishes it in LDS -- Step 5 /
+//      Algorithm 4 (drainage counts, deepest level first) and Steps 6-7 /
+//      Algorithms 5-6 (uplift and the implicit n = 1 update, level by level
+//      from the root) -- and writes the new heights.  Every other tree
+//      ("crossing": it leaves or enters the tile) is handed to the global
+//      pass: its roots are appended to the global queue.  Heights are read
+//      from one buffer and written to the other, so halo reads never see a
+//      neighbouring tile's new values.
 //
-//  k_order_accum_erode      one cooperative (persistent) kernel whose level
-//      loops run on the device with grid-wide barriers between levels:
-//      Step 4 / Algorithm 3: breadth-first levels.  Level 0 is every cell
-//        without a receiver; level l+1 is the donors of level l.  Each chunk
-//        of a level is expanded with a workgroup prefix scan and reserves its
-//        output range with one atomic add, so the queue is written with no
-//        per-cell atomics.  Alongside the queue it records, per position,
-//        the receiver's position, the first donor's position, the donor mask
-//        and the receiver code, so that the later phases read the tree in
-//        queue order instead of gathering it from the grid.
-//      Step 5 / Algorithm 4 (Equation "flow_acc"): upstream cell counts,
-//        levels deepest first; each position pulls its donors' counts, which
-//        sit contiguously in the next level.
-//      Step 6 / Algorithm 5 and Step 7 / Algorithm 6: uplift and the
-//        implicit n = 1 update h <- (h0 + F*h_rec)/(1 + F), levels from the
-//        roots outward; the receiver's new height is read from the
-//        queue-order copy written by the previous level.
+//  k_global_levels   one cooperative (persistent) kernel of at most 128
+//      workgroups of 1024 threads for the crossing trees, with device-side
+//      level loops: breadth-first expansion (a workgroup prefix scan per
+//      chunk and one atomic add per chunk to reserve its output), counts in
+//      reverse level order (each queue position pulls its donors' counts,
+//      which sit contiguously in the next level), then uplift and erosion
+//      from the roots outward (the receiver's new height is read from the
+//      queue-order copy the previous level wrote).  Large levels are shared
+//      by all workgroups and end in a grid-wide barrier; runs of small levels
+//      are done by one workgroup with workgroup barriers only, because a
+//      grid-wide barrier costs far more than a small level's work.
+//
+// The results of the method do not depend on the order cells are processed
+// in (receivers, levels and counts are exact; each height depends only on
+// its own inputs and its receiver's new height), so resolving a tree inside
+// its tile gives the same bits as resolving it in the global queue.
 //
 // Arithmetic that decides results is written operation by operation in the
-// same order as the problem's definition and compiled without FP contraction
-// (-ffp-contract=off), so receivers, levels and counts are exact and heights
-// round the same way on every run.
+// order of the problem's definition and compiled without FP contraction
+// (-ffp-contract=off).
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
@@ -40,6 +50,123 @@ namespace lem {
 
 namespace {
 
+constexpr int kHW = kTW + 4;  // width of the staged height region
+constexpr int kHH = kTH + 4;
+constexpr int kRW = kTW + 2;  // width of the receiver region (tile + ring)
+constexpr int kRH = kTH + 2;
+constexpr int kTileCells = kTH * kTW;
+constexpr int kCellsPerThread = kTileCells / kTileThreads;
+constexpr int kStageLoads = (kHH * kHW + kTileThreads - 1) / kTileThreads;
+constexpr uint32_t kSpinLimit = 1u << 26;  // about 2 s of polling
+
+static_assert(kTileCells % kTileThreads == 0, "tile cells must split evenly over threads");
+static_assert(kCellsPerThread <= 32, "root bit mask holds 32 cells per thread");
+
+__device__ __forceinline__ int code_dy(int k) { return (k < 3) ? -1 : (k < 5 ? 0 : 1); }
+__device__ __forceinline__ int code_dx(int k) {
+  return (k == 0 || k == 3 || k == 5) ? -1 : ((k == 1 || k == 6) ? 0 : 1);
+}
+// Distance class of a receiver code: 0 vertical (dy), 1 horizontal (dx), 2 diagonal.
+__device__ __forceinline__ int code_class(int k) {
+  return (k == 1 || k == 6) ? 0 : ((k == 3 || k == 4) ? 1 : 2);
+}
+
+__device__ __forceinline__ int64_t neighbour_offset(int k, int nx) {
+  return (int64_t)code_dy(k) * nx + code_dx(k);
+}
+
+// A^m: sqrt for m = 0.5 and A itself for m = 1 (both exact), pow otherwise.
+__device__ __forceinline__ double area_power(double area, int use_sqrt, double m) {
+  return use_sqrt ? sqrt(area) : (m == 1.0 ? area : pow(area, m));
+}
+__device__ __noinline__ double area_power_call(double area, int use_sqrt, double m) {
+  return area_power(area, use_sqrt, m);
+}
+
+// Step 2 / Algorithm 1 by the definition: eight quotients (h_c - h_n)/dist
+// in neighbour order, strict ">" against a running maximum starting at 0.
+__device__ __noinline__ uint8_t receiver_code_by_definition(const double* h, int ci, int W,
+                                                            double dx, double dy, double dd) {
+  const double hc = h[ci];
+  const double s0 = (hc - h[ci - W - 1]) / dd;
+  const double s1 = (hc - h[ci - W]) / dy;
+  const double s2 = (hc - h[ci - W + 1]) / dd;
+  const double s3 = (hc - h[ci - 1]) / dx;
+  const double s4 = (hc - h[ci + 1]) / dx;
+  const double s5 = (hc - h[ci + W - 1]) / dd;
+  const double s6 = (hc - h[ci + W]) / dy;
+  const double s7 = (hc - h[ci + W + 1]) / dd;
+  double smax = 0.0;
+  uint8_t code = kSink;
+  if (s0 > smax) { smax = s0; code = 0; }
+  if (s1 > smax) { smax = s1; code = 1; }
+  if (s2 > smax) { smax = s2; code = 2; }
+  if (s3 > smax) { smax = s3; code = 3; }
+  if (s4 > smax) { smax = s4; code = 4; }
+  if (s5 > smax) { smax = s5; code = 5; }
+  if (s6 > smax) { smax = s6; code = 6; }
+  if (s7 > smax) { smax = s7; code = 7; }
+  return code;
+}
+
+// The same result with three divisions instead of eight.  The definition
+// picks the first neighbour whose rounded quotient s_k = fl(a_k / d_k)
+// equals the largest one, S, when S > 0 (a_k = fl(h_c - h_k)).  Neighbours
+// share one of three divisors (dy, dx, diagonal), and rounding is monotone,
+// so each class's largest quotient is fl(max a_k / d): three divisions give
+// S.  A neighbour matches S exactly if it holds its class maximum, or if its
+// own quotient rounds to the same value, which needs a_k within a relative
+// 2^-49 of the class maximum (beyond that the quotients differ by more than
+// two units in the last place); only those rare candidates are divided.
+// Quotients outside [2^-1000, 2^1000] go through the definition itself.
+__device__ __forceinline__ uint8_t receiver_code(const double* h, int ci, int W, double dx,
+                                                 double dy, double dd) {
+  const double hc = h[ci];
+  const double a0 = hc - h[ci - W - 1], a1 = hc - h[ci - W], a2 = hc - h[ci - W + 1];
+  const double a3 = hc - h[ci - 1], a4 = hc - h[ci + 1];
+  const double a5 = hc - h[ci + W - 1], a6 = hc - h[ci + W], a7 = hc - h[ci + W + 1];
+  const double mv = fmax(a1, a6), mh = fmax(a3, a4);
+  const double md = fmax(fmax(a0, a2), fmax(a5, a7));
+  const double sv = mv / dy, sh = mh / dx, sd = md / dd;
+  const double S = fmax(fmax(sv, sh), sd);
+  if (!(S > 0.0)) return kSink;
+  if (!(S >= 0x1p-1000 && S <= 0x1p1000))
+    return receiver_code_by_definition(h, ci, W, dx, dy, dd);
+  constexpr double kNear = 1.0 - 0x1p-49;
+#define LEM_CANDIDATE(k, ak, mc, sc, dc) \
+  if (sc == S && (ak == mc || (ak > mc * kNear && ak / dc == S))) return k;
+  LEM_CANDIDATE(0, a0, md, sd, dd)
+  LEM_CANDIDATE(1, a1, mv, sv, dy)
+  LEM_CANDIDATE(2, a2, md, sd, dd)
+  LEM_CANDIDATE(3, a3, mh, sh, dx)
+  LEM_CANDIDATE(4, a4, mh, sh, dx)
+  LEM_CANDIDATE(5, a5, md, sd, dd)
+  LEM_CANDIDATE(6, a6, mv, sv, dy)
+  LEM_CANDIDATE(7, a7, md, sd, dd)
+#undef LEM_CANDIDATE
+  return receiver_code_by_definition(h, ci, W, dx, dy, dd);
+}
+
+// F = K*dt*A^m/d and 1 + F for a cell with `count` upstream cells that
+// drains along code k (A = count*dx*dy).  Scalar K and small counts read the
+// tables built at the start of the run from the same expressions.
+__device__ __forceinline__ void erosion_factor(const StepArgs& a, uint32_t count, int k,
+                                               int64_t c, double* f, double* g) {
+  const int cls = code_class(k);
+  if (!a.Kf && count < (uint32_t)kAmTab) {
+    *f = a.w.ftab[cls * kAmTab + count];
+    *g = a.w.gtab[cls * kAmTab + count];
+    return;
+  }
+  const double d = cls == 0 ? a.dy : (cls == 1 ? a.dx : a.ddiag);
+  const double am = count < (uint32_t)kAmTab
+                        ? a.w.amtab[count]
+                        : area_power_call((double)count * a.dxdy, a.use_sqrt, a.m);
+  const double kc = a.Kf ? a.Kf[c] : a.K;
+  *f = ((kc * a.dt) * am) / d;
+  *g = 1.0 + *f;
+}
+
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -50,7 +177,8 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
   return v;
 }
 
-// Exclusive prefix sum of v over the workgroup; *total receives the sum.
+// Exclusive prefix sum of v over a workgroup of NT threads; *total gets the sum.
+template <int NT>
 __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int inc = wave_inclusive_scan(v);
@@ -58,7 +186,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total
   __syncthreads();
   int off = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
+  for (int k = 0; k < NT / 64; ++k) {
     const int s = wsum[k];
     off += (k < w) ? s : 0;
     tot += s;
@@ -68,67 +196,617 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total
   return off + inc - v;
 }
 
-__device__ __forceinline__ int64_t neighbour_offset(int k, int nx) {
-  // (dy,dx) in code order: (-1,-1) (-1,0) (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1)
-  const int dy = (k < 3) ? -1 : (k < 5 ? 0 : 1);
-  const int dx = (k == 0 || k == 3 || k == 5) ? -1 : ((k == 1 || k == 6) ? 0 : 1);
-  return (int64_t)dy * nx + dx;
+__device__ __forceinline__ int32_t load_acquire(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// A^m: sqrt for m = 0.5 and A itself for m = 1 (both exact), pow otherwise.
-__device__ __forceinline__ double area_power(double area, const StepArgs& a) {
-  return a.use_sqrt ? sqrt(area) : (a.m == 1.0 ? area : pow(area, a.m));
-}
-
-__device__ __forceinline__ double code_distance(int k, double dx, double dy, double ddiag) {
-  return (k == 1 || k == 6) ? dy : ((k == 3 || k == 4) ? dx : ddiag);
+// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous run of tiles so that tiles sharing halo rows share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int xcd = b & 7, k = b >> 3;
+  int start = 0;
+  for (int j = 0; j < xcd; ++j) start += (ntiles - j + 7) >> 3;
+  return start + k;
 }
 
 // ---------------------------------------------------------------------------
-// Step 2 / Algorithm 1: receivers.
-__global__ __launch_bounds__(256) void k_receivers(StepArgs a) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  if (x >= a.nx || y >= a.ny) return;
-  const int nx = a.nx;
-  const int64_t c = (int64_t)y * nx + x;
-  uint8_t code;
-  if (y == 0 || x == 0 || y == a.ny - 1 || x == nx - 1) {
-    code = kBase;
-  } else {
-    const double* h = a.h;
-    const double hc = h[c];
-    const double dxv = a.dx, dyv = a.dy, dd = a.ddiag;
-    const double s0 = (hc - h[c - nx - 1]) / dd;
-    const double s1 = (hc - h[c - nx]) / dyv;
-    const double s2 = (hc - h[c - nx + 1]) / dd;
-    const double s3 = (hc - h[c - 1]) / dxv;
-    const double s4 = (hc - h[c + 1]) / dxv;
-    const double s5 = (hc - h[c + nx - 1]) / dd;
-    const double s6 = (hc - h[c + nx]) / dyv;
-    const double s7 = (hc - h[c + nx + 1]) / dd;
-    double smax = 0.0;
-    code = kSink;
-    if (s0 > smax) { smax = s0; code = 0; }
-    if (s1 > smax) { smax = s1; code = 1; }
-    if (s2 > smax) { smax = s2; code = 2; }
-    if (s3 > smax) { smax = s3; code = 3; }
-    if (s4 > smax) { smax = s4; code = 4; }
-    if (s5 > smax) { smax = s5; code = 5; }
-    if (s6 > smax) { smax = s6; code = 6; }
-    if (s7 > smax) { smax = s7; code = 7; }
+__global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
+  __shared__ double hs[kHH * kHW];            // heights, tile + 2-cell halo
+  __shared__ uint16_t nxt[kTileCells];        // pointer jumping: ends as the local root
+  __shared__ uint32_t clw[kTileCells / 2];    // upstream counts, two 16-bit halves a word
+  __shared__ uint16_t lst[kTileCells];        // resolved cells sorted by level
+  __shared__ uint8_t rc[kRH * kRW];           // receiver codes, tile + ring
+  __shared__ uint8_t dm[kTileCells];          // donor masks
+  __shared__ uint8_t dp[kTileCells];          // level within the tile
+  __shared__ uint8_t crossing[kTileCells];    // per local root: tree leaves/enters the tile
+  __shared__ int lvl[kLocalDepthCap + 2];     // per-level counts, then offsets
+  __shared__ int wsum[kTileThreads / 64];
+  __shared__ int s_flag[2];
+  __shared__ int s_all, s_clean, s_cmax, s_base;
+
+  const int tid = threadIdx.x;
+  const int ntiles = a.tiles_x * a.tiles_y;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int y0 = (tile / a.tiles_x) * kTH, x0 = (tile % a.tiles_x) * kTW;
+  const int ny = a.ny, nx = a.nx;
+  const Work w = a.w;
+
+  if (tid == 0) {
+    s_flag[0] = 0;
+    s_flag[1] = 0;
+    s_all = 0;
+    s_clean = 0;
+    s_cmax = 0;
   }
-  a.w.rcode[c] = code;
+  for (int i = tid; i < kLocalDepthCap + 2; i += kTileThreads) lvl[i] = 0;
+  for (int i = tid; i < kTileCells / 2; i += kTileThreads) clw[i] = 0u;
+  // Heights of the tile and a 2-cell halo (positions outside the grid hold 0
+  // and are never used).  All loads are issued before the LDS stores.
+  {
+    double v[kStageLoads];
+#pragma unroll
+    for (int j = 0; j < kStageLoads; ++j) {
+      const int i = tid + j * kTileThreads;
+      const int gy = y0 - 2 + i / kHW, gx = x0 - 2 + i % kHW;
+      v[j] = (i < kHH * kHW && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
+                 ? a.h_in[(int64_t)gy * nx + gx] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kStageLoads; ++j) {
+      const int i = tid + j * kTileThreads;
+      if (i < kHH * kHW) hs[i] = v[j];
+    }
+  }
+  __syncthreads();
+
+  // Receiver codes of the tile and its ring.
+  for (int i = tid; i < kRH * kRW; i += kTileThreads) {
+    const int ly = i / kRW, lx = i % kRW;
+    const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
+    uint8_t code;
+    if (gy < 0 || gy >= ny || gx < 0 || gx >= nx)
+      code = kNone;
+    else if (a.fixed)
+      code = w.rcode[(int64_t)gy * nx + gx];
+    else if (gy == 0 || gx == 0 || gy == ny - 1 || gx == nx - 1)
+      code = kBase;
+    else
+      code = receiver_code(hs, (ly + 1) * kHW + (lx + 1), kHW, a.dx, a.dy, a.ddiag);
+    rc[i] = code;
+  }
+  __syncthreads();
+
+  // Donor masks.  Tile-local roots (cells without a receiver, and cells
+  // whose receiver is outside the tile) point to themselves at distance 0;
+  // every other cell points to its receiver at distance 1.
+#pragma unroll
+  for (int t = 0; t < kCellsPerThread; ++t) {
+    const int i = tid + t * kTileThreads;
+    const int ly = i / kTW, lx = i % kTW;
+    crossing[i] = 0;
+    if (y0 + ly >= ny || x0 + lx >= nx) {
+      nxt[i] = (uint16_t)i;
+      dp[i] = 0;
+      dm[i] = 0;
+      continue;
+    }
+    const int ri = (ly + 1) * kRW + (lx + 1);
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (rc[ri + code_dy(k) * kRW + code_dx(k)] == 7 - k) m |= 1u << k;
+    dm[i] = (uint8_t)m;
+    const int code = rc[ri];
+    int target = i, dist = 0;
+    if (code < kSink) {
+      const int ry = ly + code_dy(code), rx = lx + code_dx(code);
+      if (ry < 0 || ry >= kTH || rx < 0 || rx >= kTW)
+        crossing[i] = 1;  // exits the tile: a crossing tree's local root
+      else {
+        target = ry * kTW + rx;
+        dist = 1;
+      }
+    }
+    nxt[i] = (uint16_t)target;
+    dp[i] = (uint8_t)dist;
+  }
+  __syncthreads();
+
+  // Pointer jumping: after r rounds every cell points 2^r receivers down (or
+  // to its local root) and dp holds that distance, so dp ends as the level
+  // of the cell within its tile-local tree.  Depths beyond kLocalDepthCap
+  // and receiver cycles (possible only with fixed routing) leave cells
+  // unresolved and send the whole tile to the global pass.
+  for (int r = 0; r <= 8; ++r) {
+    uint16_t np[kCellsPerThread];
+    int nd[kCellsPerThread];
+    uint32_t upd = 0;
+#pragma unroll
+    for (int t = 0; t < kCellsPerThread; ++t) {
+      const int i = tid + t * kTileThreads;
+      const int p = nxt[i];
+      const int pp = nxt[p];
+      np[t] = (uint16_t)pp;
+      nd[t] = dp[i] + dp[p];
+      if (p != pp) upd |= 1u << t;
+    }
+    if (upd) s_flag[r & 1] = 1;
+    __syncthreads();
+    const bool go = s_flag[r & 1] != 0;
+    if (go && r == 8 && tid == 0) s_all = 1;  // still unresolved after 8 rounds
+#pragma unroll
+    for (int t = 0; t < kCellsPerThread; ++t) {
+      if (!(upd & (1u << t))) continue;
+      const int i = tid + t * kTileThreads;
+      nxt[i] = np[t];
+      dp[i] = (uint8_t)(nd[t] > kLocalDepthCap ? kLocalDepthCap : nd[t]);
+      if (nd[t] > kLocalDepthCap) s_all = 1;
+    }
+    if (tid == 0) s_flag[(r + 1) & 1] = 0;
+    __syncthreads();
+    if (!go) break;
+  }
+
+  // Every cell must now point at a genuine local root: a cell without a
+  // receiver or one whose receiver is outside the tile.  Pointer jumping maps
+  // a receiver cycle (fixed routing only) onto cells that point at
+  // themselves without being roots; such a tile goes to the global pass,
+  // which reports the cycle.  A tree crosses the tile edge if its local root
+  // exits the tile (marked above) or if any of its cells has a donor outside
+  // the tile.
+#pragma unroll
+  for (int t = 0; t < kCellsPerThread; ++t) {
+    const int i = tid + t * kTileThreads;
+    const int r = nxt[i];
+    const int rcode = rc[(r / kTW + 1) * kRW + (r % kTW + 1)];
+    if (rcode < kSink && !crossing[r]) s_all = 1;
+    uint32_t m = dm[i];
+    const int ly = i / kTW, lx = i % kTW;
+    bool entry = false;
+    while (m) {
+      const int k = __ffs(m) - 1;
+      m &= m - 1;
+      const int dy_ = ly + code_dy(k), dx_ = lx + code_dx(k);
+      entry |= (dy_ < 0 || dy_ >= kTH || dx_ < 0 || dx_ >= kTW);
+    }
+    if (entry) crossing[nxt[i]] = 1;
+  }
+  __syncthreads();
+  const bool all_cross = s_all != 0;
+
+  // Cells of trees that stay in the tile ("clean"), bucketed by level.
+  uint32_t clean_bits = 0;
+#pragma unroll
+  for (int t = 0; t < kCellsPerThread; ++t) {
+    const int i = tid + t * kTileThreads;
+    const int ly = i / kTW, lx = i % kTW;
+    if (all_cross || y0 + ly >= ny || x0 + lx >= nx || crossing[nxt[i]]) continue;
+    clean_bits |= 1u << t;
+    atomicAdd(&lvl[dp[i]], 1);
+  }
+  __syncthreads();
+  // Exclusive prefix over the level counts (wave 0, four bins per lane).
+  if (tid < 64) {
+    int c4[4], s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = tid * 4 + q;
+      c4[q] = b <= kLocalDepthCap ? lvl[b] : 0;
+      s += c4[q];
+    }
+    const int inc = wave_inclusive_scan(s);
+    int run = inc - s;
+    int top = -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = tid * 4 + q;
+      if (b <= kLocalDepthCap) lvl[b] = run;
+      if (c4[q]) top = b;
+      run += c4[q];
+    }
+    // Deepest non-empty level (wave-wide maximum).
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) top = max(top, __shfl_xor(top, d, 64));
+    if (tid == 0) {
+      s_cmax = top;
+      lvl[kLocalDepthCap + 1] = inc;  // unused slot keeps the total for reference
+    }
+  }
+  __syncthreads();
+  const int cmax = s_cmax;
+  // Scatter: afterwards lvl[l] is the end of level l in lst.
+#pragma unroll
+  for (int t = 0; t < kCellsPerThread; ++t) {
+    if (!(clean_bits & (1u << t))) continue;
+    const int i = tid + t * kTileThreads;
+    lst[atomicAdd(&lvl[dp[i]], 1)] = (uint16_t)i;
+  }
+  // Step 5: each clean cell adds one to the count of every cell on its path
+  // to the root (itself included): count = number of upstream cells.
+#pragma unroll
+  for (int t = 0; t < kCellsPerThread; ++t) {
+    if (!(clean_bits & (1u << t))) continue;
+    int v = tid + t * kTileThreads;
+    for (int s = 0; s <= kLocalDepthCap; ++s) {
+      atomicAdd(&clw[v >> 1], 1u << ((v & 1) * 16));
+      const int code = rc[(v / kTW + 1) * kRW + (v % kTW + 1)];
+      if (code >= kSink) break;
+      v += code_dy(code) * kTW + code_dx(code);
+    }
+  }
+  __syncthreads();
+
+  // Steps 6-7 for clean trees: uplift of interior roots (level 0), then the
+  // implicit update level by level from the root.
+  for (int l = 0; l <= cmax; ++l) {
+    const int lo = l == 0 ? 0 : lvl[l - 1], hi = lvl[l];
+    for (int j = lo + tid; j < hi; j += kTileThreads) {
+      const int i = lst[j];
+      const int ly = i / kTW, lx = i % kTW;
+      const int64_t c = (int64_t)(y0 + ly) * nx + (x0 + lx);
+      const int hidx = (ly + 2) * kHW + (lx + 2);
+      const int code = rc[(ly + 1) * kRW + (lx + 1)];
+      if (code == kBase) continue;
+      const double up = a.Uf ? a.Uf[c] * a.dt : a.udt;
+      if (code == kSink) {
+        hs[hidx] = hs[hidx] + up;
+        continue;
+      }
+      const uint32_t count = (clw[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
+      double f, g;
+      erosion_factor(a, count, code, c, &f, &g);
+      const double h0 = hs[hidx] + up;
+      hs[hidx] = (h0 + f * hs[hidx + code_dy(code) * kHW + code_dx(code)]) / g;
+    }
+    __syncthreads();
+  }
+
+  // Write the tile back; queue the roots of crossing trees for the global
+  // pass; count the cells resolved here.
+  int my_clean = 0, my_roots = 0;
+  uint32_t root_bits = 0;
+#pragma unroll
+  for (int t = 0; t < kCellsPerThread; ++t) {
+    const int i = tid + t * kTileThreads;
+    const int ly = i / kTW, lx = i % kTW;
+    if (y0 + ly >= ny || x0 + lx >= nx) continue;
+    const int64_t c = (int64_t)(y0 + ly) * nx + (x0 + lx);
+    const int code = rc[(ly + 1) * kRW + (lx + 1)];
+    const bool clean = (clean_bits >> t) & 1u;
+    a.h_out[c] = hs[(ly + 2) * kHW + (lx + 2)];
+    w.dmask[c] = dm[i];
+    if (clean) {
+      ++my_clean;
+      if (a.export_routing) {
+        w.dep_g[c] = dp[i];
+        w.cnt_g[c] = (clw[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
+      }
+    } else if (code >= kSink) {
+      root_bits |= 1u << t;
+      ++my_roots;
+    }
+    if (a.export_routing && !a.fixed) w.rcode[c] = (uint8_t)code;
+  }
+  atomicAdd(&s_clean, my_clean);
+  int tot;
+  const int pre = block_exclusive_scan<kTileThreads>(my_roots, wsum, &tot);
+  if (tid == 0) s_base = tot ? atomicAdd(&w.lcnt[0], tot) : 0;
+  __syncthreads();
+  int pos = s_base + pre;
+  while (root_bits) {
+    const int t = __ffs(root_bits) - 1;
+    root_bits &= root_bits - 1;
+    const int i = tid + t * kTileThreads;
+    const int ly = i / kTW, lx = i % kTW;
+    const int64_t c = (int64_t)(y0 + ly) * nx + (x0 + lx);
+    w.q[pos] = (int32_t)c;
+    w.par[pos] = -1;
+    w.kq[pos] = rc[(ly + 1) * kRW + (lx + 1)];
+    ++pos;
+  }
+  if (tid == 0 && s_clean) {
+    atomicAdd(&w.ctrl->clean, s_clean);
+    atomicMax(&w.ctrl->clean_maxdepth, cmax);
+  }
 }
 
-// Fixed routing (test hook): copy caller codes, checking that each stays in
-// the grid and that perimeter cells have none.  Bad codes raise LEM_E_ARG on
-// the device and are treated as "no receiver".
+// ---------------------------------------------------------------------------
+// Crossing trees: Steps 4 to 7 over the whole grid in one cooperative launch.
+
+// Grid-wide barrier: arrival counter plus generation word on separate cache
+// lines, agent-scope release on arrival and acquire on departure.  The wait
+// is bounded; a timeout raises LEM_E_HIP on the device instead of hanging.
+__device__ __forceinline__ void grid_barrier(Ctrl* ct) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t g0 = __hip_atomic_load(&ct->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(&ct->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&ct->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ct->bar_gen, g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&ct->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins == kSpinLimit) {
+          atomicMax(&ct->status, 6);
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+  }
+  __syncthreads();
+}
+
+// Breadth-first expansion of queue positions [lo, hi) (level L) by
+// workgroups wg of nwg: the donors of each position are appended after hi.
+__device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t L, int wg,
+                             int nwg, int* wsum, int* s_base) {
+  const Work& w = a.w;
+  const int tid = threadIdx.x;
+  const int nx = a.nx;
+  for (int64_t base = lo + (int64_t)wg * kChunk; base < hi; base += (int64_t)nwg * kChunk) {
+    int32_t cs[kItems];
+    uint32_t ms[kItems];
+    int cntv = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = base + (int64_t)j * kBlock + tid;
+      cs[j] = 0;
+      ms[j] = 0;
+      if (i < hi) {
+        cs[j] = w.q[i];
+        ms[j] = w.dmask[cs[j]];
+        cntv += __popc(ms[j]);
+      }
+    }
+    int tot;
+    const int pre = block_exclusive_scan<kBlock>(cntv, wsum, &tot);
+    if (tid == 0) *s_base = tot ? atomicAdd(&w.lcnt[L + 1], tot) : 0;
+    __syncthreads();
+    int32_t pos = hi + *s_base + pre;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = base + (int64_t)j * kBlock + tid;
+      if (i < hi) {
+        uint32_t m = ms[j];
+        w.mq[i] = (uint8_t)m;
+        w.fc[i] = pos;
+        while (m) {
+          const int b = __ffs(m) - 1;
+          m &= m - 1;
+          w.q[pos] = (int32_t)(cs[j] + neighbour_offset(b, nx));
+          w.par[pos] = (int32_t)i;
+          w.kq[pos] = (uint8_t)(7 - b);
+          ++pos;
+        }
+      }
+    }
+  }
+}
+
+// Step 5 for queue positions [a0, a1): count = 1 + the donors' counts.
+__device__ __forceinline__ void accumulate_level(const Work& w, int32_t a0, int32_t a1, int wg,
+                                                 int nwg) {
+  for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1;
+       i += (int64_t)nwg * kBlock) {
+    const uint32_t m = w.mq[i];
+    uint32_t s = 1u;
+    if (m) {
+      const int32_t f = w.fc[i];
+      const int k = __popc(m);
+      for (int j = 0; j < k; ++j) s += w.cnt[f + j];
+    }
+    w.cnt[i] = s;
+  }
+}
+
+// Steps 6-7 for queue positions [a0, a1) of a level >= 1.
+__device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32_t a1, int wg,
+                                            int nwg) {
+  const Work& w = a.w;
+  for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1;
+       i += (int64_t)nwg * kBlock) {
+    const int32_t c = w.q[i];
+    const double hr = w.hq[w.par[i]];
+    double f, g;
+    erosion_factor(a, w.cnt[i], w.kq[i], c, &f, &g);
+    const double h0 = a.h_in[c] + (a.Uf ? a.Uf[c] * a.dt : a.udt);
+    const double hn = (h0 + f * hr) / g;
+    w.hq[i] = hn;
+    a.h_out[c] = hn;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
+  __shared__ int wsum[kBlock / 64];
+  __shared__ int s_base;
+  const Work w = a.w;
+  Ctrl* ct = w.ctrl;
+  const int tid = threadIdx.x;
+  const int wg = blockIdx.x, nwg = gridDim.x;
+  const bool lead = (wg == 0 && tid == 0);
+  uint64_t t0 = 0, t1 = 0, t2 = 0;
+  if (lead && a.timers) t0 = wall_clock64();
+
+  // Breadth-first levels.  Cells appended to level L+1 are counted in
+  // lcnt[L+1]; the workgroup-0 lead clears lcnt[L+2] while level L runs
+  // (nobody else touches it then) and records lev[L+1].
+  int32_t lo = 0, hi = load_acquire(&w.lcnt[0]), L = 0;
+  bool done = false;
+  if (lead) w.lev[0] = 0;
+  while (!done) {
+    if (hi - lo >= kTailLevel) {
+      if (lead) {
+        w.lev[L + 1] = hi;
+        w.lcnt[L + 2] = 0;
+      }
+      expand_level(a, lo, hi, L, wg, nwg, wsum, &s_base);
+      grid_barrier(ct);
+      const int32_t added = load_acquire(&w.lcnt[L + 1]);
+      if (added == 0) {
+        done = true;
+      } else {
+        lo = hi;
+        hi += added;
+        ++L;
+      }
+    } else {
+      // Small levels: workgroup 0 continues alone until a level grows past
+      // the threshold again or the queue ends.
+      if (wg == 0) {
+        int32_t tlo = lo, thi = hi, tL = L;
+        bool tdone = false;
+        while (true) {
+          if (tid == 0) {
+            w.lev[tL + 1] = thi;
+            w.lcnt[tL + 2] = 0;
+          }
+          expand_level(a, tlo, thi, tL, 0, 1, wsum, &s_base);
+          __syncthreads();
+          const int32_t added = load_acquire(&w.lcnt[tL + 1]);
+          __syncthreads();
+          if (added == 0) {
+            tdone = true;
+            break;
+          }
+          tlo = thi;
+          thi += added;
+          ++tL;
+          if (thi - tlo >= kTailLevel) break;
+        }
+        if (tid == 0) {
+          ct->tail_lo = tlo;
+          ct->tail_hi = thi;
+          ct->tail_L = tL;
+          ct->tail_done = tdone ? 1 : 0;
+        }
+      }
+      grid_barrier(ct);
+      lo = __hip_atomic_load(&ct->tail_lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hi = __hip_atomic_load(&ct->tail_hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      L = __hip_atomic_load(&ct->tail_L, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      done = __hip_atomic_load(&ct->tail_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    }
+  }
+  const int32_t nlevels = L + 1;
+  const int32_t total = hi;
+  if (lead && a.timers) t1 = wall_clock64();
+
+  // Step 5: counts, deepest level first, down to level 1.
+  for (int32_t l = nlevels - 1; l >= 1;) {
+    if (w.lev[l + 1] - w.lev[l] >= kTailLevel) {
+      accumulate_level(w, w.lev[l], w.lev[l + 1], wg, nwg);
+      grid_barrier(ct);
+      --l;
+    } else {
+      int32_t l2 = l;
+      while (l2 >= 1 && w.lev[l2 + 1] - w.lev[l2] < kTailLevel) --l2;
+      if (wg == 0) {
+        for (int32_t k = l; k > l2; --k) {
+          accumulate_level(w, w.lev[k], w.lev[k + 1], 0, 1);
+          __syncthreads();
+        }
+      }
+      grid_barrier(ct);
+      l = l2;
+    }
+  }
+  // Level 0: counts of the roots, and uplift of the interior roots.
+  {
+    const int32_t a1 = w.lev[1];
+    accumulate_level(w, 0, a1, wg, nwg);
+    for (int64_t i = (int64_t)wg * kBlock + tid; i < a1; i += (int64_t)nwg * kBlock) {
+      const int32_t c = w.q[i];
+      double hv = a.h_in[c];
+      if (w.kq[i] == kSink) hv = hv + (a.Uf ? a.Uf[c] * a.dt : a.udt);
+      a.h_out[c] = hv;
+      w.hq[i] = hv;
+    }
+  }
+  if (lead && a.timers) t2 = wall_clock64();
+
+  // Steps 6-7, levels 1 and up, from the roots outward.
+  for (int32_t l = 1; l < nlevels;) {
+    grid_barrier(ct);
+    if (w.lev[l + 1] - w.lev[l] >= kTailLevel) {
+      erode_level(a, w.lev[l], w.lev[l + 1], wg, nwg);
+      ++l;
+    } else {
+      int32_t l2 = l;
+      while (l2 < nlevels && w.lev[l2 + 1] - w.lev[l2] < kTailLevel) ++l2;
+      if (wg == 0) {
+        for (int32_t k = l; k < l2; ++k) {
+          erode_level(a, w.lev[k], w.lev[k + 1], 0, 1);
+          __syncthreads();
+        }
+      }
+      l = l2;
+    }
+  }
+
+  if (lead) {
+    const int32_t clean = ct->clean;
+    const int32_t nl_clean = clean ? ct->clean_maxdepth + 1 : 0;
+    const int32_t nl_cross = total ? nlevels : 0;
+    const int32_t nl = nl_clean > nl_cross ? nl_clean : nl_cross;
+    ct->nlevels = nl;
+    ct->dirty_total = total;
+    ct->dirty_nlevels = nl_cross;
+    ct->crossing_run += total;
+    if (nl > ct->max_nlevels) ct->max_nlevels = nl;
+    if (a.step < kHistCap) w.hist[a.step] = nl;
+    ct->steps = a.step + 1;
+    if ((int64_t)clean + total != (int64_t)a.n) atomicMax(&ct->status, 5);
+    // Reset the per-step counters for the next step's tile pass.
+    ct->clean = 0;
+    ct->clean_maxdepth = 0;
+    w.lcnt[0] = 0;
+    w.lcnt[1] = 0;
+    if (a.timers) {
+      const uint64_t t3 = wall_clock64();
+      ct->ticks[1] += t1 - t0;
+      ct->ticks[2] += t2 - t1;
+      ct->ticks[3] += t3 - t2;
+    }
+  }
+}
+
+// Start of a run: reset the control block and tabulate A^m, F and 1 + F.
+__global__ void k_begin_run(StepArgs a) {
+  const int i = threadIdx.x;
+  if (i < kAmTab) {
+    const double am = area_power((double)i * a.dxdy, a.use_sqrt, a.m);
+    a.w.amtab[i] = am;
+    const double d[3] = {a.dy, a.dx, a.ddiag};
+    for (int c = 0; c < 3; ++c) {
+      const double f = ((a.K * a.dt) * am) / d[c];
+      a.w.ftab[c * kAmTab + i] = f;
+      a.w.gtab[c * kAmTab + i] = 1.0 + f;
+    }
+  }
+  if (i == 0) {
+    Ctrl* ct = a.w.ctrl;
+    ct->max_nlevels = 0;
+    ct->steps = 0;
+    ct->clean = 0;
+    ct->clean_maxdepth = 0;
+    ct->crossing_run = 0;
+    for (int k = 0; k < 4; ++k) ct->ticks[k] = 0;
+    a.w.lcnt[0] = 0;
+    a.w.lcnt[1] = 0;
+  }
+}
+
+// Fixed routing: copy caller codes, checking that each stays in the grid and
+// that perimeter cells have none.  Bad codes raise LEM_E_ARG on the device
+// and are treated as "no receiver".
 __global__ __launch_bounds__(256) void k_fixed_routing(StepArgs a, const uint8_t* user) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  if (x >= a.nx || y >= a.ny) return;
-  const int64_t c = (int64_t)y * a.nx + x;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n) return;
+  const int y = (int)(c / a.nx), x = (int)(c % a.nx);
   const uint8_t u = user[c];
   const bool perim = (y == 0 || x == 0 || y == a.ny - 1 || x == a.nx - 1);
   uint8_t code;
@@ -144,246 +822,44 @@ __global__ __launch_bounds__(256) void k_fixed_routing(StepArgs a, const uint8_t
   a.w.rcode[c] = code;
 }
 
-// Step 3 / Algorithm 2 over every cell: bit k of the mask is set when the
-// neighbour at offset k has this cell as its receiver (code 7-k).
-__global__ __launch_bounds__(256) void k_donors(StepArgs a) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-    a.w.lcnt[0] = 0;
-    a.w.lcnt[1] = 0;
-  }
-  if (x >= a.nx || y >= a.ny) return;
-  const int nx = a.nx;
-  const int64_t c = (int64_t)y * nx + x;
-  const uint8_t* r = a.w.rcode;
-  const bool up = y > 0, dn = y < a.ny - 1, lf = x > 0, rt = x < nx - 1;
-  uint32_t m = 0;
-  if (up && lf && r[c - nx - 1] == 7) m |= 1u << 0;
-  if (up && r[c - nx] == 6) m |= 1u << 1;
-  if (up && rt && r[c - nx + 1] == 5) m |= 1u << 2;
-  if (lf && r[c - 1] == 4) m |= 1u << 3;
-  if (rt && r[c + 1] == 3) m |= 1u << 4;
-  if (dn && lf && r[c + nx - 1] == 2) m |= 1u << 5;
-  if (dn && r[c + nx] == 1) m |= 1u << 6;
-  if (dn && rt && r[c + nx + 1] == 0) m |= 1u << 7;
-  a.w.dmask[c] = (uint8_t)m;
-}
-
-__device__ __forceinline__ int32_t load_acquire(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---------------------------------------------------------------------------
-// Steps 4 to 7 in one cooperative launch.
-__global__ __launch_bounds__(kBlock) void k_order_accum_erode(StepArgs a) {
-  cg::grid_group grid = cg::this_grid();
-  __shared__ int wsum[kBlock / 64];
-  __shared__ int s_base;
+// Routing export, part 1: levels and counts of the crossing trees.
+__global__ __launch_bounds__(256) void k_export_cross(StepArgs a) {
   const Work w = a.w;
-  const int tid = threadIdx.x;
-  const int64_t n = a.n;
-  const int nx = a.nx;
-  const bool lead = (blockIdx.x == 0 && tid == 0);
-  uint64_t t0 = 0, t1 = 0, t2 = 0;
-  if (lead && a.timers) t0 = wall_clock64();
-
-  // Level 0: every cell without a receiver, compacted chunk by chunk.
-  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
-       base += (int64_t)gridDim.x * kChunk) {
-    uint32_t bits = 0;
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int64_t c = base + (int64_t)j * kBlock + tid;
-      if (c < n && w.rcode[c] >= kSink) bits |= 1u << j;
+  const int32_t nlev = w.ctrl->dirty_nlevels;
+  const int32_t total = w.ctrl->dirty_total;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    int32_t lo = 0, hi = nlev;  // largest l with lev[l] <= i
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (w.lev[mid] <= i) lo = mid; else hi = mid;
     }
-    int tot;
-    const int pre = block_exclusive_scan(__popc(bits), wsum, &tot);
-    if (tid == 0) s_base = tot ? atomicAdd(&w.lcnt[0], tot) : 0;
-    __syncthreads();
-    int pos = s_base + pre;
-    while (bits) {
-      const int j = __ffs(bits) - 1;
-      bits &= bits - 1;
-      const int64_t c = base + (int64_t)j * kBlock + tid;
-      w.q[pos] = (int32_t)c;
-      w.par[pos] = -1;
-      w.kq[pos] = w.rcode[c];
-      ++pos;
-    }
+    const int32_t c = w.q[i];
+    w.dep_g[c] = lo;
+    w.cnt_g[c] = w.cnt[i];
   }
-  grid.sync();
-
-  // Breadth-first expansion, one level per grid-wide barrier.  The number of
-  // cells appended to level L+1 accumulates in lcnt[L+1]; the workgroup 0
-  // lead clears lcnt[L+2] while level L runs, so nobody else touches it.
-  int32_t lo = 0;
-  int32_t hi = load_acquire(&w.lcnt[0]);
-  int32_t L = 0;
-  if (lead) w.lev[0] = 0;
-  while (true) {
-    if (lead) {
-      w.lev[L + 1] = hi;
-      w.lcnt[L + 2] = 0;
-    }
-    for (int64_t base = lo + (int64_t)blockIdx.x * kChunk; base < hi;
-         base += (int64_t)gridDim.x * kChunk) {
-      int32_t cs[kItems];
-      uint32_t ms[kItems];
-      int cntv = 0;
-#pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        const int64_t i = base + (int64_t)j * kBlock + tid;
-        cs[j] = 0;
-        ms[j] = 0;
-        if (i < hi) {
-          cs[j] = w.q[i];
-          ms[j] = w.dmask[cs[j]];
-          cntv += __popc(ms[j]);
-        }
-      }
-      int tot;
-      const int pre = block_exclusive_scan(cntv, wsum, &tot);
-      if (tid == 0) s_base = tot ? atomicAdd(&w.lcnt[L + 1], tot) : 0;
-      __syncthreads();
-      int32_t pos = hi + s_base + pre;
-#pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        const int64_t i = base + (int64_t)j * kBlock + tid;
-        if (i < hi) {
-          uint32_t m = ms[j];
-          w.mq[i] = (uint8_t)m;
-          w.fc[i] = pos;
-          while (m) {
-            const int b = __ffs(m) - 1;
-            m &= m - 1;
-            w.q[pos] = (int32_t)(cs[j] + neighbour_offset(b, nx));
-            w.par[pos] = (int32_t)i;
-            w.kq[pos] = (uint8_t)(7 - b);
-            ++pos;
-          }
-        }
-      }
-    }
-    grid.sync();
-    const int32_t added = load_acquire(&w.lcnt[L + 1]);
-    if (added == 0) break;
-    lo = hi;
-    hi += added;
-    ++L;
-  }
-  const int32_t nlevels = L + 1;
-  const int32_t total = hi;
-  if (lead && a.timers) t1 = wall_clock64();
-
-  // Step 5: counts, deepest level first (levels >= 1).
-  for (int32_t l = nlevels - 1; l >= 1; --l) {
-    const int32_t a0 = w.lev[l], a1 = w.lev[l + 1];
-    for (int64_t i = a0 + (int64_t)blockIdx.x * kBlock + tid; i < a1;
-         i += (int64_t)gridDim.x * kBlock) {
-      const uint32_t m = w.mq[i];
-      uint32_t s = 1u;
-      if (m) {
-        const int32_t f = w.fc[i];
-        const int k = __popc(m);
-        for (int j = 0; j < k; ++j) s += w.cnt[f + j];
-      }
-      w.cnt[i] = s;
-    }
-    grid.sync();
-  }
-  if (lead && a.timers) t2 = wall_clock64();
-
-  // Level 0: counts of the roots, and uplift of the interior roots (Step 6).
-  {
-    const int32_t a1 = w.lev[1];
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < a1;
-         i += (int64_t)gridDim.x * kBlock) {
-      const uint32_t m = w.mq[i];
-      uint32_t s = 1u;
-      if (m) {
-        const int32_t f = w.fc[i];
-        const int k = __popc(m);
-        for (int j = 0; j < k; ++j) s += w.cnt[f + j];
-      }
-      w.cnt[i] = s;
-      const int32_t c = w.q[i];
-      double hv = a.h[c];
-      if (w.kq[i] == kSink) {
-        hv = hv + (a.Uf ? a.Uf[c] * a.dt : a.udt);
-        a.h[c] = hv;
-      }
-      w.hq[i] = hv;
-    }
-  }
-
-  // Steps 6 and 7 for levels >= 1: uplift, then the implicit update against
-  // the receiver's new height (from the previous level).
-  for (int32_t l = 1; l < nlevels; ++l) {
-    grid.sync();
-    const int32_t a0 = w.lev[l], a1 = w.lev[l + 1];
-    for (int64_t i = a0 + (int64_t)blockIdx.x * kBlock + tid; i < a1;
-         i += (int64_t)gridDim.x * kBlock) {
-      const int32_t c = w.q[i];
-      const int32_t p = w.par[i];
-      const double hr = w.hq[p];
-      const double d = code_distance(w.kq[i], a.dx, a.dy, a.ddiag);
-      const double area = (double)w.cnt[i] * a.dxdy;
-      const double am = area_power(area, a);
-      const double kc = a.Kf ? a.Kf[c] : a.K;
-      const double f = ((kc * a.dt) * am) / d;
-      const double h0 = a.h[c] + (a.Uf ? a.Uf[c] * a.dt : a.udt);
-      const double hn = (h0 + f * hr) / (1.0 + f);
-      w.hq[i] = hn;
-      a.h[c] = hn;
-    }
-  }
-
-  if (lead) {
-    Ctrl* ct = w.ctrl;
-    ct->nlevels = nlevels;
-    ct->total = total;
-    if (nlevels > ct->max_nlevels) ct->max_nlevels = nlevels;
-    if (a.step < kHistCap) w.hist[a.step] = nlevels;
-    ct->steps = a.step + 1;
-    if (total != n) atomicMax(&ct->status, 5);
-    if (a.timers) {
-      const uint64_t t3 = wall_clock64();
-      ct->ticks[1] += t1 - t0;
-      ct->ticks[2] += t2 - t1;
-      ct->ticks[3] += t3 - t2;
-    }
-  }
+  // Clear the level histogram for part 2.
+  const int32_t nl = w.ctrl->nlevels;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nl + 2; i += stride)
+    w.dhist[i] = 0;
 }
 
-__global__ void k_begin_run(Ctrl* ct) {
-  ct->max_nlevels = 0;
-  ct->steps = 0;
-  for (int k = 0; k < 4; ++k) ct->ticks[k] = 0;
-}
-
-// Routing export: receiver index, level and upstream count per cell.
-__global__ __launch_bounds__(256) void k_export(StepArgs a, int32_t* rec, int32_t* depth,
-                                                uint32_t* count) {
+// Routing export, part 2: per-cell receiver, level and count for the caller,
+// and the level histogram.
+__global__ __launch_bounds__(256) void k_export_cells(StepArgs a, int32_t* rec, int32_t* depth,
+                                                      uint32_t* count) {
   const Work w = a.w;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int32_t nlev = w.ctrl->nlevels;
-  const int32_t total = w.ctrl->total;
+  const int32_t nl = w.ctrl->nlevels;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
     if (rec) {
       const uint8_t k = w.rcode[i];
       rec[i] = (k >= kSink) ? (int32_t)i : (int32_t)(i + neighbour_offset(k, a.nx));
     }
-    if (i < total && (depth || count)) {
-      int32_t lo = 0, hi = nlev;  // largest l with lev[l] <= i
-      while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (w.lev[mid] <= i) lo = mid; else hi = mid;
-      }
-      const int32_t c = w.q[i];
-      if (depth) depth[c] = lo;
-      if (count) count[c] = w.cnt[i];
-    }
+    const int32_t d = w.dep_g[i];
+    if (depth) depth[i] = d;
+    if (count) count[i] = w.cnt_g[i];
+    if (d >= 0 && d < nl) atomicAdd(&w.dhist[d + 1], 1);
   }
 }
 
@@ -395,16 +871,13 @@ __global__ __launch_bounds__(256) void k_validate(const double* x, int64_t n, in
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
-dim3 grid2d(const StepArgs& a) {
-  return dim3((unsigned)((a.nx + 63) / 64), (unsigned)((a.ny + 3) / 4));
-}
-
 }  // namespace
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
 size_t workspace_bytes(int64_t n) {
   int64_t b = 0;
+  b += align256(8 * n);                   // h2
   b += align256(n);                       // rcode
   b += align256(n);                       // dmask
   b += align256(4 * n);                   // q
@@ -416,6 +889,12 @@ size_t workspace_bytes(int64_t n) {
   b += align256(8 * n);                   // hq
   b += align256(4 * (n + 2));             // lcnt
   b += align256(4 * (n + 2));             // lev
+  b += align256(4 * n);                   // dep_g
+  b += align256(4 * n);                   // cnt_g
+  b += align256(4 * (n + 2));             // dhist
+  b += align256(8 * kAmTab);              // amtab
+  b += align256(8 * 3 * kAmTab);          // ftab
+  b += align256(8 * 3 * kAmTab);          // gtab
   b += align256(4 * kHistCap);            // hist
   b += align256(sizeof(Ctrl));            // ctrl
   b += align256(4 * kScratchInts);        // scratch
@@ -425,6 +904,7 @@ size_t workspace_bytes(int64_t n) {
 void carve(void* base, int64_t n, Work* w) {
   char* p = (char*)base;
   auto take = [&](int64_t bytes) { char* r = p; p += align256(bytes); return (void*)r; };
+  w->h2 = (double*)take(8 * n);
   w->rcode = (uint8_t*)take(n);
   w->dmask = (uint8_t*)take(n);
   w->q = (int32_t*)take(4 * n);
@@ -436,42 +916,47 @@ void carve(void* base, int64_t n, Work* w) {
   w->hq = (double*)take(8 * n);
   w->lcnt = (int32_t*)take(4 * (n + 2));
   w->lev = (int32_t*)take(4 * (n + 2));
+  w->dep_g = (int32_t*)take(4 * n);
+  w->cnt_g = (uint32_t*)take(4 * n);
+  w->dhist = (int32_t*)take(4 * (n + 2));
+  w->amtab = (double*)take(8 * kAmTab);
+  w->ftab = (double*)take(8 * 3 * kAmTab);
+  w->gtab = (double*)take(8 * 3 * kAmTab);
   w->hist = (int32_t*)take(4 * kHistCap);
   w->ctrl = (Ctrl*)take(sizeof(Ctrl));
   w->scratch = (int32_t*)take(4 * kScratchInts);
 }
 
-hipError_t launch_route(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_receivers, grid2d(a), dim3(64, 4), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_donors, grid2d(a), dim3(64, 4), 0, s, a);
+hipError_t launch_begin_run(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin_run, dim3(1), dim3(kAmTab), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user, hipStream_t s) {
-  hipLaunchKernelGGL(k_fixed_routing, grid2d(a), dim3(64, 4), 0, s, a, user);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_donors, grid2d(a), dim3(64, 4), 0, s, a);
+  hipLaunchKernelGGL(k_fixed_routing, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a,
+                     user);
   return hipGetLastError();
 }
 
-hipError_t launch_order_accum_erode(const StepArgs& a, int grid, hipStream_t s) {
+hipError_t launch_tile_step(const StepArgs& a, hipStream_t s) {
+  const unsigned ntiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
+  hipLaunchKernelGGL(k_tile_step, dim3(ntiles), dim3(kTileThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s) {
   StepArgs copy = a;
   void* args[] = {&copy};
-  return hipLaunchCooperativeKernel((const void*)k_order_accum_erode, dim3(grid), dim3(kBlock),
-                                    args, 0, s);
-}
-
-hipError_t launch_begin_run(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_begin_run, dim3(1), dim3(1), 0, s, a.w.ctrl);
-  return hipGetLastError();
+  return hipLaunchCooperativeKernel((const void*)k_global_levels, dim3(grid), dim3(kBlock), args,
+                                    0, s);
 }
 
 hipError_t launch_export(const StepArgs& a, int32_t* rec, int32_t* depth, uint32_t* count,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_export, dim3(2048), dim3(256), 0, s, a, rec, depth, count);
+  hipLaunchKernelGGL(k_export_cross, dim3(1024), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_export_cells, dim3(2048), dim3(256), 0, s, a, rec, depth, count);
   return hipGetLastError();
 }
 
@@ -480,10 +965,9 @@ hipError_t launch_validate(const double* x, int64_t n, int32_t* flag, hipStream_
   return hipGetLastError();
 }
 
-hipError_t order_kernel_occupancy(int* blocks_per_cu) {
+hipError_t global_kernel_occupancy(int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                      (const void*)k_order_accum_erode,
-                                                      kBlock, 0);
+                                                      (const void*)k_global_levels, kBlock, 0);
 }
 
 }  // namespace lem
