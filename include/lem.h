@@ -154,6 +154,23 @@ lem_status lem_level_history(lem_ctx* ctx, int32_t* h_levels, int64_t cap, int64
 /* Fills *out; synchronizes the stream. */
 lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out);
 
+/* Launch tuning of a context (performance only; results are identical for
+ * every setting).  global_workgroups: workgroups of 1024 threads in the
+ * cooperative level kernel for trees that cross tile edges (0 = default,
+ * clamped to what the device can keep resident); tail_level: levels with
+ * fewer cells than this are handled by one workgroup without grid-wide
+ * barriers (0 = default, >= 1). */
+typedef struct lem_tuning {
+  int32_t global_workgroups;
+  int32_t tail_level;
+} lem_tuning;
+
+/* Applies *t to later runs on ctx.  LEM_E_ARG for negative fields. */
+lem_status lem_set_tuning(lem_ctx* ctx, const lem_tuning* t);
+
+/* Current settings (after defaults and clamping). */
+lem_status lem_get_tuning(const lem_ctx* ctx, lem_tuning* out);
+
 /* Destroys the context (host state only; the workspace stays the caller's).
  * Waits for the stream first.  NULL is a no-op. */
 lem_status lem_destroy(lem_ctx* ctx);

@@ -16,7 +16,9 @@ struct lem_ctx {
   lem_params p;
   hipStream_t stream;
   lem::Work w;
-  int grid;              // workgroups of the cooperative ordering kernel
+  int grid;              // workgroups of the cooperative level kernel
+  int grid_max;          // most that stay resident on this device
+  int tail_level;
   int device;
   double tick_khz;       // device wall-clock rate
   int64_t steps_done;
@@ -82,6 +84,7 @@ lem::StepArgs make_args(const lem_ctx* ctx, const double* d_K, const double* d_U
   a.timers = (p.flags & LEM_F_PHASE_TIMERS) ? 1 : 0;
   a.tiles_x = (p.nx + lem::kTW - 1) / lem::kTW;
   a.tiles_y = (p.ny + lem::kTH - 1) / lem::kTH;
+  a.tail_level = ctx->tail_level;
   return a;
 }
 
@@ -201,7 +204,9 @@ lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes, v
   }
   // The global level kernel uses at most kGlobalMaxWGs resident workgroups:
   // a grid-wide barrier's cost grows with the number of participants.
-  ctx->grid = cus * per_cu < lem::kGlobalMaxWGs ? cus * per_cu : lem::kGlobalMaxWGs;
+  ctx->grid_max = cus * per_cu;
+  ctx->grid = ctx->grid_max < lem::kGlobalMaxWGs ? ctx->grid_max : lem::kGlobalMaxWGs;
+  ctx->tail_level = lem::kTailLevel;
   ctx->tick_khz = (double)rate;
   e = hipMemsetAsync(ctx->w.ctrl, 0, sizeof(lem::Ctrl), ctx->stream);
   if (e != hipSuccess) {
@@ -307,6 +312,23 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out) {
   out->crossing_run = ct.crossing_run;
   for (int k = 1; k < 4; ++k)
     out->phase_ms[k] = ctx->tick_khz > 0 ? (double)ct.ticks[k] / ctx->tick_khz : 0.0;
+  return LEM_OK;
+}
+
+lem_status lem_set_tuning(lem_ctx* ctx, const lem_tuning* t) {
+  if (!ctx || !t) return LEM_E_ARG;
+  if (t->global_workgroups < 0 || t->tail_level < 0)
+    return fail(ctx, LEM_E_ARG, "tuning fields must be >= 0");
+  int g = t->global_workgroups ? t->global_workgroups : lem::kGlobalMaxWGs;
+  ctx->grid = g < ctx->grid_max ? g : ctx->grid_max;
+  ctx->tail_level = t->tail_level ? t->tail_level : lem::kTailLevel;
+  return LEM_OK;
+}
+
+lem_status lem_get_tuning(const lem_ctx* ctx, lem_tuning* out) {
+  if (!ctx || !out) return LEM_E_ARG;
+  out->global_workgroups = ctx->grid;
+  out->tail_level = ctx->tail_level;
   return LEM_OK;
 }
 

@@ -35,8 +35,8 @@ constexpr int kAmTab = 256;
 constexpr int kBlock = 1024;
 constexpr int kItems = 16;
 constexpr int kChunk = kBlock * kItems;
-constexpr int kGlobalMaxWGs = 128;
-constexpr int kTailLevel = 16384;
+constexpr int kGlobalMaxWGs = 192;
+constexpr int kTailLevel = 8192;  // default; lem_set_tuning changes it per context
 
 // Device-side control block (one per context, in the workspace).
 struct Ctrl {
@@ -105,6 +105,7 @@ struct StepArgs {
   int32_t fixed;      // receivers come from w.rcode (fixed routing)
   int32_t export_routing;  // write per-cell codes, levels and counts
   int32_t tiles_x, tiles_y;
+  int32_t tail_level;      // levels smaller than this run in one workgroup
 };
 
 size_t workspace_bytes(int64_t n);

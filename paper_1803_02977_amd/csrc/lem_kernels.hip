@@ -109,42 +109,81 @@ __device__ __noinline__ uint8_t receiver_code_by_definition(const double* h, int
   return code;
 }
 
-// The same result with three divisions instead of eight.  The definition
-// picks the first neighbour whose rounded quotient s_k = fl(a_k / d_k)
-// equals the largest one, S, when S > 0 (a_k = fl(h_c - h_k)).  Neighbours
-// share one of three divisors (dy, dx, diagonal), and rounding is monotone,
-// so each class's largest quotient is fl(max a_k / d): three divisions give
-// S.  A neighbour matches S exactly if it holds its class maximum, or if its
-// own quotient rounds to the same value, which needs a_k within a relative
-// 2^-49 of the class maximum (beyond that the quotients differ by more than
-// two units in the last place); only those rare candidates are divided.
-// Quotients outside [2^-1000, 2^1000] go through the definition itself.
-__device__ __forceinline__ uint8_t receiver_code(const double* h, int ci, int W, double dx,
-                                                 double dy, double dd) {
+// Reciprocals of the three neighbour distances (fl(1/d)).
+struct RecvConst {
+  double dx, dy, dd;
+  double inv_dx, inv_dy, inv_dd;
+};
+
+// The same result as the definition, usually without any division.  The
+// definition picks the first neighbour whose rounded quotient
+// s_k = fl(a_k / d_k) (a_k = fl(h_c - h_k)) equals the largest one, S, when
+// S > 0.  Neighbours fall in distance classes with one divisor each (with
+// dx == dy the four orthogonal neighbours form one class), and rounding is
+// monotone, so a class's largest quotient belongs to its largest numerator.
+//  - Classes are ranked by m_c * fl(1/d_c), which is within 3 units in the
+//    last place of fl(m_c / d_c); if the best class leads every other by a
+//    relative 2^-48, its rounded quotient is strictly the largest.
+//  - Inside the winning class the first neighbour holding the class maximum
+//    wins, unless another member is within a relative 2^-49 of it (its
+//    rounded quotient could then equal S).
+//  - All numerators <= 0 means no receiver.
+// Anything else (near-ties across classes, near-ties inside the class, or
+// quotients outside [2^-1000, 2^1000]) is decided by the definition itself.
+template <bool kSquare>
+__device__ __forceinline__ uint8_t receiver_code(const double* h, int ci, int W,
+                                                 const RecvConst& rk) {
   const double hc = h[ci];
   const double a0 = hc - h[ci - W - 1], a1 = hc - h[ci - W], a2 = hc - h[ci - W + 1];
   const double a3 = hc - h[ci - 1], a4 = hc - h[ci + 1];
   const double a5 = hc - h[ci + W - 1], a6 = hc - h[ci + W], a7 = hc - h[ci + W + 1];
-  const double mv = fmax(a1, a6), mh = fmax(a3, a4);
-  const double md = fmax(fmax(a0, a2), fmax(a5, a7));
-  const double sv = mv / dy, sh = mh / dx, sd = md / dd;
-  const double S = fmax(fmax(sv, sh), sd);
-  if (!(S > 0.0)) return kSink;
-  if (!(S >= 0x1p-1000 && S <= 0x1p1000))
-    return receiver_code_by_definition(h, ci, W, dx, dy, dd);
   constexpr double kNear = 1.0 - 0x1p-49;
-#define LEM_CANDIDATE(k, ak, mc, sc, dc) \
-  if (sc == S && (ak == mc || (ak > mc * kNear && ak / dc == S))) return k;
-  LEM_CANDIDATE(0, a0, md, sd, dd)
-  LEM_CANDIDATE(1, a1, mv, sv, dy)
-  LEM_CANDIDATE(2, a2, md, sd, dd)
-  LEM_CANDIDATE(3, a3, mh, sh, dx)
-  LEM_CANDIDATE(4, a4, mh, sh, dx)
-  LEM_CANDIDATE(5, a5, md, sd, dd)
-  LEM_CANDIDATE(6, a6, mv, sv, dy)
-  LEM_CANDIDATE(7, a7, md, sd, dd)
-#undef LEM_CANDIDATE
-  return receiver_code_by_definition(h, ci, W, dx, dy, dd);
+  constexpr double kMargin = 1.0 - 0x1p-48;
+  const double md = fmax(fmax(a0, a2), fmax(a5, a7));
+  const double qd = md * rk.inv_dd;
+  double m, q, q2, q3;
+  uint32_t eq, near;
+  if (kSquare) {
+    const double mo = fmax(fmax(a1, a3), fmax(a4, a6));
+    if (!(mo > 0.0) && !(md > 0.0)) return kSink;
+    const double qo = mo * rk.inv_dx;
+    const bool orth = qo > qd || md != md;
+    m = orth ? mo : md;
+    q = orth ? qo : qd;
+    q2 = orth ? qd : qo;
+    q3 = -1.0;
+    const double b0 = orth ? a1 : a0, b1 = orth ? a3 : a2, b2 = orth ? a4 : a5, b3 = orth ? a6 : a7;
+    const uint32_t k0 = orth ? 1 : 0, k1 = orth ? 3 : 2, k2 = orth ? 4 : 5, k3 = orth ? 6 : 7;
+    eq = ((b0 == m) << k0) | ((b1 == m) << k1) | ((b2 == m) << k2) | ((b3 == m) << k3);
+    near = ((b0 != m && b0 > m * kNear) << k0) | ((b1 != m && b1 > m * kNear) << k1) |
+           ((b2 != m && b2 > m * kNear) << k2) | ((b3 != m && b3 > m * kNear) << k3);
+  } else {
+    const double mv = fmax(a1, a6), mh = fmax(a3, a4);
+    if (!(mv > 0.0) && !(mh > 0.0) && !(md > 0.0)) return kSink;
+    const double qv = mv * rk.inv_dy, qh = mh * rk.inv_dx;
+    // Rank the classes (NaN classes never win).
+    int win = 2;
+    q = qd;
+    if (qv > q || q != q) { win = 0; q = qv; }
+    if (qh > q || q != q) { win = 1; q = qh; }
+    q2 = win == 0 ? qh : qv;
+    q3 = win == 2 ? qh : qd;
+    m = win == 0 ? mv : (win == 1 ? mh : md);
+    const double b0 = win == 0 ? a1 : (win == 1 ? a3 : a0);
+    const double b1 = win == 0 ? a6 : (win == 1 ? a4 : a2);
+    const uint32_t k0 = win == 0 ? 1 : (win == 1 ? 3 : 0);
+    const uint32_t k1 = win == 0 ? 6 : (win == 1 ? 4 : 2);
+    eq = ((b0 == m) << k0) | ((b1 == m) << k1);
+    near = ((b0 != m && b0 > m * kNear) << k0) | ((b1 != m && b1 > m * kNear) << k1);
+    if (win == 2) {
+      eq |= ((a5 == m) << 5) | ((a7 == m) << 7);
+      near |= ((a5 != m && a5 > m * kNear) << 5) | ((a7 != m && a7 > m * kNear) << 7);
+    }
+  }
+  const bool fast = q >= 0x1p-1000 && q <= 0x1p1000 && !(q2 >= q * kMargin) &&
+                    !(q3 >= q * kMargin) && near == 0u;
+  if (fast) return (uint8_t)(__ffs(eq) - 1);
+  return receiver_code_by_definition(h, ci, W, rk.dx, rk.dy, rk.dd);
 }
 
 // F = K*dt*A^m/d and 1 + F for a cell with `count` upstream cells that
@@ -260,6 +299,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   __syncthreads();
 
   // Receiver codes of the tile and its ring.
+  const bool square = a.dx == a.dy;
+  RecvConst rk;
+  rk.dx = a.dx;
+  rk.dy = a.dy;
+  rk.dd = a.ddiag;
+  rk.inv_dx = 1.0 / a.dx;
+  rk.inv_dy = 1.0 / a.dy;
+  rk.inv_dd = 1.0 / a.ddiag;
   for (int i = tid; i < kRH * kRW; i += kTileThreads) {
     const int ly = i / kRW, lx = i % kRW;
     const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
@@ -270,8 +317,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
       code = w.rcode[(int64_t)gy * nx + gx];
     else if (gy == 0 || gx == 0 || gy == ny - 1 || gx == nx - 1)
       code = kBase;
+    else if (square)
+      code = receiver_code<true>(hs, (ly + 1) * kHW + (lx + 1), kHW, rk);
     else
-      code = receiver_code(hs, (ly + 1) * kHW + (lx + 1), kHW, a.dx, a.dy, a.ddiag);
+      code = receiver_code<false>(hs, (ly + 1) * kHW + (lx + 1), kHW, rk);
     rc[i] = code;
   }
   __syncthreads();
@@ -638,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
   bool done = false;
   if (lead) w.lev[0] = 0;
   while (!done) {
-    if (hi - lo >= kTailLevel) {
+    if (hi - lo >= a.tail_level) {
       if (lead) {
         w.lev[L + 1] = hi;
         w.lcnt[L + 2] = 0;
@@ -675,7 +724,7 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
           tlo = thi;
           thi += added;
           ++tL;
-          if (thi - tlo >= kTailLevel) break;
+          if (thi - tlo >= a.tail_level) break;
         }
         if (tid == 0) {
           ct->tail_lo = tlo;
@@ -697,13 +746,13 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
 
   // Step 5: counts, deepest level first, down to level 1.
   for (int32_t l = nlevels - 1; l >= 1;) {
-    if (w.lev[l + 1] - w.lev[l] >= kTailLevel) {
+    if (w.lev[l + 1] - w.lev[l] >= a.tail_level) {
       accumulate_level(w, w.lev[l], w.lev[l + 1], wg, nwg);
       grid_barrier(ct);
       --l;
     } else {
       int32_t l2 = l;
-      while (l2 >= 1 && w.lev[l2 + 1] - w.lev[l2] < kTailLevel) --l2;
+      while (l2 >= 1 && w.lev[l2 + 1] - w.lev[l2] < a.tail_level) --l2;
       if (wg == 0) {
         for (int32_t k = l; k > l2; --k) {
           accumulate_level(w, w.lev[k], w.lev[k + 1], 0, 1);
@@ -731,12 +780,12 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
   // Steps 6-7, levels 1 and up, from the roots outward.
   for (int32_t l = 1; l < nlevels;) {
     grid_barrier(ct);
-    if (w.lev[l + 1] - w.lev[l] >= kTailLevel) {
+    if (w.lev[l + 1] - w.lev[l] >= a.tail_level) {
       erode_level(a, w.lev[l], w.lev[l + 1], wg, nwg);
       ++l;
     } else {
       int32_t l2 = l;
-      while (l2 < nlevels && w.lev[l2 + 1] - w.lev[l2] < kTailLevel) ++l2;
+      while (l2 < nlevels && w.lev[l2 + 1] - w.lev[l2] < a.tail_level) ++l2;
       if (wg == 0) {
         for (int32_t k = l; k < l2; ++k) {
           erode_level(a, w.lev[k], w.lev[k + 1], 0, 1);

@@ -20,8 +20,8 @@ LEM_F_VALIDATE, LEM_F_PHASE_TIMERS = 0x1, 0x2
 
 # Symbols declared in include/lem.h.
 EXPORTS = ("lem_workspace_bytes", "lem_create", "lem_run", "lem_run_fixed_routing",
-           "lem_sync", "lem_routing", "lem_level_history", "lem_stats", "lem_destroy",
-           "lem_status_str", "lem_last_error")
+           "lem_sync", "lem_routing", "lem_level_history", "lem_stats", "lem_set_tuning",
+           "lem_get_tuning", "lem_destroy", "lem_status_str", "lem_last_error")
 
 
 class lem_params(C.Structure):
@@ -35,6 +35,10 @@ class lem_stats_t(C.Structure):
                 ("max_nlevels", C.c_int64), ("last_run_steps", C.c_int64),
                 ("phase_ms", C.c_double * 4), ("kernel_ms", C.c_double * 2),
                 ("crossing_last", C.c_int64), ("crossing_run", C.c_int64)]
+
+
+class lem_tuning(C.Structure):
+    _fields_ = [("global_workgroups", C.c_int32), ("tail_level", C.c_int32)]
 
 
 class LemError(RuntimeError):
@@ -72,6 +76,10 @@ def load(path: str = LIB_PATH):
     lib.lem_level_history.restype = C.c_int
     lib.lem_stats.argtypes = [_P, C.POINTER(lem_stats_t)]
     lib.lem_stats.restype = C.c_int
+    lib.lem_set_tuning.argtypes = [_P, C.POINTER(lem_tuning)]
+    lib.lem_set_tuning.restype = C.c_int
+    lib.lem_get_tuning.argtypes = [_P, C.POINTER(lem_tuning)]
+    lib.lem_get_tuning.restype = C.c_int
     lib.lem_destroy.argtypes = [_P]
     lib.lem_destroy.restype = C.c_int
     lib.lem_status_str.argtypes = [C.c_int]
@@ -138,6 +146,16 @@ def lem_stats(ctx: int) -> lem_stats_t:
     s = lem_stats_t()
     _check(load().lem_stats(ctx, C.byref(s)), ctx)
     return s
+
+
+def lem_set_tuning(ctx: int, t: lem_tuning) -> None:
+    _check(load().lem_set_tuning(ctx, C.byref(t)), ctx)
+
+
+def lem_get_tuning(ctx: int) -> lem_tuning:
+    t = lem_tuning()
+    _check(load().lem_get_tuning(ctx, C.byref(t)), ctx)
+    return t
 
 
 def lem_destroy(ctx: int) -> None:
@@ -226,6 +244,11 @@ class Solver:
 
     def stats(self) -> lem_stats_t:
         return lem_stats(self.ctx)
+
+    def set_tuning(self, global_workgroups=0, tail_level=0):
+        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level))
+        t = lem_get_tuning(self.ctx)
+        return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -167,3 +167,24 @@ def test_zero_steps_is_a_no_op():
     with pytest.raises(LemError):
         s.routing()
     s.close()
+
+
+@pytest.mark.parametrize("tuning", [(0, 0), (1, 1), (16, 1 << 30), (256, 64), (3, 5000)])
+def test_tuning_does_not_change_results(tuning):
+    """Workgroup count and the one-workgroup level threshold of the global
+    pass change only the schedule: heights and routing stay bit-identical."""
+    torch = require_gpu()
+    w = W.SMALL_256.with_(ny=500, nx=700)
+    h0 = W.initial_heights(w.ny, w.nx, 21)
+    ref_h, ref_r, _ = _run_gpu(torch, w, h0, 12)
+    h = _to_dev(torch, h0)
+    s = _solver(torch, w)
+    got = s.set_tuning(*tuning)
+    assert got["global_workgroups"] >= 1 and got["tail_level"] >= 1
+    s.run(h, 12)
+    s.sync()
+    r = s.routing()
+    assert np.array_equal(h.cpu().numpy(), ref_h)
+    for k in ("rec", "depth", "count"):
+        assert torch.equal(r[k], ref_r[k])
+    s.close()
