@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default=W.LARGE_10000.name, choices=sorted(W.WORKLOADS))
+    ap.add_argument("--workload", default=W.LARGE_10000.name,
+                    choices=sorted(W.WORKLOADS) + [BATCH_NAME])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=None)
@@ -57,6 +58,89 @@ def parse():
                     help="also run a plain device-to-device copy of 2 GiB (three times) "
                          "whose HBM counters calibrate FETCH_SIZE and WRITE_SIZE")
     return ap.parse_args()
+
+
+BATCH_NAME = "batch-512-realizations-fp64"
+
+
+def bench_batch(args):
+    """512 independent realizations (sizes 128..1024, per-realization K, U, m)
+    advanced together for 500 steps; compared with the same grids run one by
+    one through the single-grid path on the same GPU."""
+    import torch
+
+    from paper_1803_02977_amd import Batch, Solver
+    reals = W.batch_realizations(512, seed=args.seed)
+    steps = args.steps or 500
+    dev = torch.device("cuda:0")
+    h0 = torch.from_numpy(W.batch_initial_heights(reals)).to(dev)
+    h = h0.clone()
+    b = Batch(reals, device=dev)
+    if args.warmup > 0:
+        b.run(h, args.warmup)
+        b.sync()
+    h.copy_(h0)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(b.stream)
+    b.run(h, steps)
+    ev1.record(b.stream)
+    b.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    st = b.stats()
+    b.close()
+    cells = sum(r.ny * r.nx for r in reals)
+    value = cells * steps / (ms / 1e3)
+    # The same grids one at a time through the single-grid path (fewer steps).
+    one_steps = max(1, min(steps, 20))
+    solvers = [Solver(r.ny, r.nx, r.dx, r.dy, r.dt, r.m, r.U, r.K, device=dev) for r in reals]
+    views = [h0[sum(q.ny * q.nx for q in reals[:i]):][: r.ny * r.nx].clone().view(r.ny, r.nx)
+             for i, r in enumerate(reals)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s_, v in zip(solvers, views):
+        s_.run(v, one_steps)
+    torch.cuda.synchronize()
+    one_wall = time.perf_counter() - t1
+    for s_ in solvers:
+        s_.close()
+    one_value = cells * one_steps / one_wall
+    out = {
+        "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": BATCH_NAME, "realizations": len(reals), "cells": cells,
+                   "sizes": "square, uniform over {128,192,...,1024}",
+                   "K": "logUniform[1e-6,1e-4]", "U": "Uniform[1e-4,2e-3]",
+                   "m": "Uniform[0.35,0.6]", "dt": 1000.0, "dx": 100.0, "seed": args.seed},
+        "wall_s": wall,
+        "crossing_frac": round(st.crossing_run / steps / cells, 4),
+        "grid_by_grid": {"value": one_value, "unit": "cell-updates/s", "steps": one_steps,
+                         "note": "same realizations, one single-grid context each, run "
+                                 "one after another on the same GPU"},
+        "batch_speedup_vs_grid_by_grid": round(value / one_value, 2),
+        "roofline": None,
+    }
+    if not args.no_cpu:
+        import oracle
+        sample = reals[:3]
+        t = time.perf_counter()
+        for r in sample:
+            p = oracle.Params(r.ny, r.nx, r.dx, r.dy, r.dt, r.m, 1.0, r.U, r.K)
+            oracle.run(W.initial_heights(r.ny, r.nx, r.seed), p, 10)
+        dt_ = time.perf_counter() - t
+        c = sum(r.ny * r.nx for r in sample) * 10
+        out["cpu_baseline"] = dict(value=c / dt_, unit="cell-updates/s", cores=1, kind="oracle",
+                                   sample=f"10 steps of each of the first 3 realizations "
+                                          f"({[r.ny for r in sample]} square), serial C oracle, "
+                                          f"{dt_:.2f} s")
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(w, h0, K, steps):
@@ -77,6 +161,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "a multi-GPU sharding design is described but not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == BATCH_NAME:
+        bench_batch(args)
+        return
     import torch
 
     from paper_1803_02977_amd import LEM_F_PHASE_TIMERS, Solver

@@ -147,6 +147,55 @@ lem_status lem_sync(lem_ctx* ctx);
 lem_status lem_routing(lem_ctx* ctx, int32_t* d_rec, int32_t* d_depth, uint32_t* d_count,
                        int64_t* h_level_offsets, int64_t cap, int64_t* h_nlevels);
 
+/* ------------------------------------------------------------------------
+ * Batched realizations.  Many independent grids (each with its own size and
+ * parameters, slope exponent 1) advance together: every time step covers
+ * all of them in one tile launch and one level launch, so small grids share
+ * the GPU instead of each paying its own launches and barriers (the paper
+ * notes that spare GPU capacity can process other models at the same time,
+ * section "GPU Implementation").  Heights of all grids live in one device
+ * buffer, grid after grid, each row-major. */
+typedef struct lem_grid {
+  int32_t ny, nx;      /* rows and columns, each >= 3                              */
+  double dx, dy;       /* cell size [m] > 0                                        */
+  double dt;           /* time step [yr] > 0                                       */
+  double m;            /* area exponent >= 0                                       */
+  double U, K;         /* uplift rate [m/yr], erodibility [1/yr] >= 0 (scalars)    */
+  int64_t offset;      /* index of the grid's first cell in the batch buffer; must
+                          equal the sum of ny*nx of the grids before it           */
+} lem_grid;
+
+/* Workspace bytes for a batch, or 0 if a descriptor is invalid (at most
+ * 65535 grids and fewer than 2^31-2 cells in total). */
+size_t lem_batch_workspace_bytes(const lem_grid* grids, int32_t count);
+
+/* As lem_create for a batch of `count` grids (host array, copied).  flags:
+ * LEM_F_VALIDATE and/or LEM_F_PHASE_TIMERS. */
+lem_status lem_batch_create(const lem_grid* grids, int32_t count, uint32_t flags,
+                            void* d_workspace, size_t ws_bytes, void* hip_stream,
+                            lem_ctx** out);
+
+/* Enqueues `steps` time steps of every grid of the batch on d_h (the batch
+ * buffer, updated in place); each grid evolves exactly as it would alone.
+ * Per-cell K or U fields are not available for batches. */
+lem_status lem_batch_run(lem_ctx* ctx, double* d_h, int64_t steps);
+
+/* Steps every grid until its heights stop changing: after every
+ * `check_every` steps a grid whose last step changed no cell by more than
+ * rtol * max|h| is frozen (it is no longer stepped).  Stops when all grids
+ * are frozen or after max_steps steps.  h_steps[count] receives, per grid,
+ * the number of steps it took (-1 if it did not converge).  Synchronizes the
+ * stream. */
+lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, double rtol, int64_t check_every,
+                                   int64_t max_steps, int64_t* h_steps);
+
+/* lem_routing for grid `grid` of the batch (after lem_batch_run); d_rec,
+ * d_depth and d_count hold that grid's cells only and indices are local to
+ * the grid. */
+lem_status lem_batch_routing(lem_ctx* ctx, int32_t grid, int32_t* d_rec, int32_t* d_depth,
+                             uint32_t* d_count, int64_t* h_level_offsets, int64_t cap,
+                             int64_t* h_nlevels);
+
 /* Copies the level count of each step of the last run into h_levels
  * (up to cap entries; *h_n receives the number of steps recorded). */
 lem_status lem_level_history(lem_ctx* ctx, int32_t* h_levels, int64_t cap, int64_t* h_n);

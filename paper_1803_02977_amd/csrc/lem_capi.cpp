@@ -8,23 +8,30 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/lem.h"
 #include "lem_internal.h"
 
 struct lem_ctx {
-  lem_params p;
+  uint32_t flags;
+  bool batch;                       // created by lem_batch_create
+  std::vector<lem::GridDev> grids;  // host copy of the grid descriptors
+  std::vector<int32_t> tiles;       // all tiles, in order
+  std::vector<int32_t> active;      // tiles of unfinished grids (steady-state driver)
+  int64_t cells;                    // cells of all grids
+  int32_t ntiles;
   hipStream_t stream;
   lem::Work w;
-  int grid;              // workgroups of the cooperative level kernel
-  int grid_max;          // most that stay resident on this device
+  int grid;                         // workgroups of the cooperative level kernel
+  int grid_max;                     // most that stay resident on this device
   int tail_level;
   int device;
-  double tick_khz;       // device wall-clock rate
+  double tick_khz;                  // device wall-clock rate
   int64_t steps_done;
   int64_t last_run_steps;
   bool has_routing;
-  double route_ms;       // accumulated with LEM_F_PHASE_TIMERS
+  double route_ms;                  // accumulated with LEM_F_PHASE_TIMERS
   double order_ms;
   hipEvent_t ev0, ev1, ev2;
   std::string err;
@@ -42,54 +49,102 @@ lem_status hip_fail(lem_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, LEM_E_HIP, m);
 }
 
-lem_status check_params(const lem_params* p, std::string* why) {
-  if (!p) { *why = "params is NULL"; return LEM_E_ARG; }
-  if (p->ny < 3 || p->nx < 3) { *why = "ny and nx must be >= 3"; return LEM_E_SIZE; }
-  if ((int64_t)p->ny * (int64_t)p->nx > (int64_t)INT32_MAX - 2) {
+// Checks one grid's problem statement.
+lem_status check_grid(int32_t ny, int32_t nx, double dx, double dy, double dt, double m, double n,
+                      double U, double K, std::string* why) {
+  if (ny < 3 || nx < 3) { *why = "ny and nx must be >= 3"; return LEM_E_SIZE; }
+  if ((int64_t)ny * (int64_t)nx > (int64_t)INT32_MAX - 2) {
     *why = "ny*nx must be below 2^31-2";
     return LEM_E_SIZE;
   }
-  if (!(p->dx > 0.0) || !(p->dy > 0.0) || !std::isfinite(p->dx) || !std::isfinite(p->dy)) {
+  if (!(dx > 0.0) || !(dy > 0.0) || !std::isfinite(dx) || !std::isfinite(dy)) {
     *why = "dx and dy must be finite and > 0";
     return LEM_E_ARG;
   }
-  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { *why = "dt must be finite and > 0"; return LEM_E_ARG; }
-  if (!(p->m >= 0.0) || !std::isfinite(p->m)) { *why = "m must be finite and >= 0"; return LEM_E_ARG; }
-  if (p->n != 1.0) { *why = "only the slope exponent n = 1 is supported"; return LEM_E_ARG; }
-  if (!std::isfinite(p->U)) { *why = "U must be finite"; return LEM_E_ARG; }
-  if (!(p->K >= 0.0) || !std::isfinite(p->K)) { *why = "K must be finite and >= 0"; return LEM_E_ARG; }
+  if (!(dt > 0.0) || !std::isfinite(dt)) { *why = "dt must be finite and > 0"; return LEM_E_ARG; }
+  if (!(m >= 0.0) || !std::isfinite(m)) { *why = "m must be finite and >= 0"; return LEM_E_ARG; }
+  if (n != 1.0) { *why = "only the slope exponent n = 1 is supported"; return LEM_E_ARG; }
+  if (!std::isfinite(U)) { *why = "U must be finite"; return LEM_E_ARG; }
+  if (!(K >= 0.0) || !std::isfinite(K)) { *why = "K must be finite and >= 0"; return LEM_E_ARG; }
+  return LEM_OK;
+}
+
+lem_status check_params(const lem_params* p, std::string* why) {
+  if (!p) { *why = "params is NULL"; return LEM_E_ARG; }
+  lem_status st = check_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->n, p->U, p->K, why);
+  if (st != LEM_OK) return st;
   if (p->flags & ~(LEM_F_VALIDATE | LEM_F_PHASE_TIMERS)) { *why = "unknown flag bits"; return LEM_E_ARG; }
+  return LEM_OK;
+}
+
+lem::GridDev make_grid(int32_t ny, int32_t nx, double dx, double dy, double dt, double m, double U,
+                       double K, int64_t offset, int32_t tile_base) {
+  lem::GridDev g{};
+  g.offset = offset;
+  g.ny = ny;
+  g.nx = nx;
+  g.tiles_x = (nx + lem::kTW - 1) / lem::kTW;
+  g.tile_base = tile_base;
+  g.use_sqrt = (m == 0.5) ? 1 : 0;
+  g.square = (dx == dy) ? 1 : 0;
+  g.dx = dx;
+  g.dy = dy;
+  g.ddiag = std::sqrt(dx * dx + dy * dy);
+  g.dxdy = dx * dy;
+  g.dt = dt;
+  g.m = m;
+  g.K = K;
+  g.udt = U * dt;
+  g.inv_dx = 1.0 / dx;
+  g.inv_dy = 1.0 / dy;
+  g.inv_dd = 1.0 / g.ddiag;
+  return g;
+}
+
+int32_t grid_tiles(const lem::GridDev& g) {
+  return g.tiles_x * ((g.ny + lem::kTH - 1) / lem::kTH);
+}
+
+// Builds the descriptors of a batch; grids are laid out back to back in the
+// order given (offsets must match that layout).
+lem_status build_batch(const lem_grid* gs, int32_t count, std::vector<lem::GridDev>* out,
+                       int64_t* cells, int32_t* ntiles, std::string* why) {
+  if (!gs || count < 1) { *why = "a batch needs at least one grid"; return LEM_E_ARG; }
+  if (count > 65535) { *why = "at most 65535 grids per batch"; return LEM_E_SIZE; }
+  out->clear();
+  int64_t off = 0, tiles = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const lem_grid& g = gs[i];
+    lem_status st = check_grid(g.ny, g.nx, g.dx, g.dy, g.dt, g.m, 1.0, g.U, g.K, why);
+    if (st != LEM_OK) return st;
+    if (g.offset != off) { *why = "grid offsets must follow the grids back to back"; return LEM_E_ARG; }
+    lem::GridDev d = make_grid(g.ny, g.nx, g.dx, g.dy, g.dt, g.m, g.U, g.K, off, (int32_t)tiles);
+    tiles += grid_tiles(d);
+    off += (int64_t)g.ny * g.nx;
+    if (off > (int64_t)INT32_MAX - 2) { *why = "a batch holds fewer than 2^31-2 cells"; return LEM_E_SIZE; }
+    out->push_back(d);
+  }
+  *cells = off;
+  *ntiles = (int32_t)tiles;
   return LEM_OK;
 }
 
 lem::StepArgs make_args(const lem_ctx* ctx, const double* d_K, const double* d_U) {
   lem::StepArgs a{};
-  const lem_params& p = ctx->p;
-  a.ny = p.ny;
-  a.nx = p.nx;
-  a.n = p.ny * p.nx;
-  a.use_sqrt = (p.m == 0.5) ? 1 : 0;
-  a.dx = p.dx;
-  a.dy = p.dy;
-  a.ddiag = std::sqrt(p.dx * p.dx + p.dy * p.dy);
-  a.dxdy = p.dx * p.dy;
-  a.dt = p.dt;
-  a.m = p.m;
-  a.K = p.K;
-  a.udt = p.U * p.dt;
+  a.grids = ctx->w.grids;
+  a.ngrids = (int32_t)ctx->grids.size();
+  a.ntiles = ctx->ntiles;
+  a.n = (int32_t)ctx->cells;
+  a.timers = (ctx->flags & LEM_F_PHASE_TIMERS) ? 1 : 0;
   a.Kf = d_K;
   a.Uf = d_U;
   a.w = ctx->w;
-  a.step = 0;
-  a.timers = (p.flags & LEM_F_PHASE_TIMERS) ? 1 : 0;
-  a.tiles_x = (p.nx + lem::kTW - 1) / lem::kTW;
-  a.tiles_y = (p.ny + lem::kTH - 1) / lem::kTH;
   a.tail_level = ctx->tail_level;
   return a;
 }
 
 lem_status validate_inputs(lem_ctx* ctx, const double* d_h, const double* d_K, const double* d_U) {
-  const int64_t n = (int64_t)ctx->p.ny * ctx->p.nx;
+  const int64_t n = ctx->cells;
   int32_t* flag = ctx->w.scratch;
   hipError_t e = hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync");
@@ -107,6 +162,36 @@ lem_status validate_inputs(lem_ctx* ctx, const double* d_h, const double* d_K, c
   return LEM_OK;
 }
 
+// One step: the tile pass, then the global level pass for crossing trees.
+lem_status step(lem_ctx* ctx, lem::StepArgs& a, bool timers) {
+  if (timers) (void)hipEventRecord(ctx->ev0, ctx->stream);
+  hipError_t e = lem::launch_tile_step(a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "tile launch");
+  if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
+  e = lem::launch_global_levels(a, ctx->grid, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "global-level launch");
+  if (timers) {
+    (void)hipEventRecord(ctx->ev2, ctx->stream);
+    e = hipEventSynchronize(ctx->ev2);
+    if (e != hipSuccess) return hip_fail(ctx, e, "timer event");
+    float ms0 = 0.f, ms1 = 0.f;
+    (void)hipEventElapsedTime(&ms0, ctx->ev0, ctx->ev1);
+    (void)hipEventElapsedTime(&ms1, ctx->ev1, ctx->ev2);
+    ctx->route_ms += ms0;
+    ctx->order_ms += ms1;
+  }
+  return LEM_OK;
+}
+
+lem_status upload_tiles(lem_ctx* ctx, const std::vector<int32_t>& tiles) {
+  if (tiles.empty()) return LEM_OK;
+  hipError_t e = hipMemcpyAsync(ctx->w.tiles, tiles.data(), sizeof(int32_t) * tiles.size(),
+                                hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "tile list upload");
+  return LEM_OK;
+}
+
 lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const double* d_K,
                     const double* d_U, int64_t steps) {
   if (!ctx) return LEM_E_ARG;
@@ -115,7 +200,7 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
   if (steps == 0) return LEM_OK;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
-  if (ctx->p.flags & LEM_F_VALIDATE) {
+  if (ctx->flags & LEM_F_VALIDATE) {
     lem_status st = validate_inputs(ctx, d_h, d_K, d_U);
     if (st != LEM_OK) return st;
   }
@@ -127,7 +212,7 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
     e = lem::launch_fixed_routing(a, d_rcode, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "fixed-routing launch");
   }
-  const bool timers = (ctx->p.flags & LEM_F_PHASE_TIMERS) != 0;
+  const bool timers = (ctx->flags & LEM_F_PHASE_TIMERS) != 0;
   ctx->route_ms = 0.0;
   ctx->order_ms = 0.0;
   // Steps alternate between the caller's buffer and the workspace copy, so a
@@ -137,31 +222,88 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
     a.h_in = (s & 1) ? ctx->w.h2 : d_h;
     a.h_out = (s & 1) ? d_h : ctx->w.h2;
     a.export_routing = (s == steps - 1) ? 1 : 0;
-    if (timers) (void)hipEventRecord(ctx->ev0, ctx->stream);
-    e = lem::launch_tile_step(a, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "tile launch");
-    if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
-    e = lem::launch_global_levels(a, ctx->grid, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "global-level launch");
-    if (timers) {
-      (void)hipEventRecord(ctx->ev2, ctx->stream);
-      e = hipEventSynchronize(ctx->ev2);
-      if (e != hipSuccess) return hip_fail(ctx, e, "timer event");
-      float ms0 = 0.f, ms1 = 0.f;
-      (void)hipEventElapsedTime(&ms0, ctx->ev0, ctx->ev1);
-      (void)hipEventElapsedTime(&ms1, ctx->ev1, ctx->ev2);
-      ctx->route_ms += ms0;
-      ctx->order_ms += ms1;
-    }
+    lem_status st = step(ctx, a, timers);
+    if (st != LEM_OK) return st;
   }
   if (steps & 1) {
-    e = hipMemcpyAsync(d_h, ctx->w.h2, sizeof(double) * (size_t)a.n, hipMemcpyDeviceToDevice,
-                       ctx->stream);
+    e = hipMemcpyAsync(d_h, ctx->w.h2, sizeof(double) * (size_t)ctx->cells,
+                       hipMemcpyDeviceToDevice, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "final copy");
   }
   ctx->steps_done += steps;
   ctx->last_run_steps = steps;
   ctx->has_routing = true;
+  return LEM_OK;
+}
+
+lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* hip_stream) {
+  const int64_t ng = (int64_t)ctx->grids.size();
+  if (!d_workspace || ((uintptr_t)d_workspace & 255u) != 0) return LEM_E_WORKSPACE;
+  if (ws_bytes < lem::workspace_bytes(ctx->cells, ng, ctx->ntiles)) return LEM_E_WORKSPACE;
+  ctx->stream = (hipStream_t)hip_stream;
+  lem::carve(d_workspace, ctx->cells, ng, ctx->ntiles, &ctx->w);
+  ctx->tiles.resize(ctx->ntiles);
+  for (int32_t t = 0; t < ctx->ntiles; ++t) ctx->tiles[t] = t;
+  hipError_t e = hipGetDevice(&ctx->device);
+  int cus = 0, per_cu = 0, rate = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  if (e == hipSuccess) e = lem::global_kernel_occupancy(&per_cu);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, ctx->device);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->ev2);
+  if (e != hipSuccess || per_cu < 1) return LEM_E_HIP;
+  // The global level kernel uses at most kGlobalMaxWGs resident workgroups:
+  // a grid-wide barrier's cost grows with the number of participants.
+  ctx->grid_max = cus * per_cu;
+  ctx->grid = ctx->grid_max < lem::kGlobalMaxWGs ? ctx->grid_max : lem::kGlobalMaxWGs;
+  ctx->tail_level = lem::kTailLevel;
+  ctx->tick_khz = (double)rate;
+  e = hipMemsetAsync(ctx->w.ctrl, 0, sizeof(lem::Ctrl), ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->w.grids, ctx->grids.data(), sizeof(lem::GridDev) * ng,
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->w.tiles, ctx->tiles.data(), sizeof(int32_t) * ctx->ntiles,
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return LEM_E_HIP;
+  return LEM_OK;
+}
+
+lem_status routing_impl(lem_ctx* ctx, int32_t g, int32_t* d_rec, int32_t* d_depth,
+                        uint32_t* d_count, int64_t* h_level_offsets, int64_t cap,
+                        int64_t* h_nlevels) {
+  if (!ctx) return LEM_E_ARG;
+  if (!ctx->has_routing) return fail(ctx, LEM_E_STATE, "no lem_run/lem_batch_run step yet");
+  if (cap < 0) return fail(ctx, LEM_E_ARG, "cap must be >= 0");
+  if (g < 0 || g >= (int32_t)ctx->grids.size()) return fail(ctx, LEM_E_ARG, "no such grid");
+  const lem::GridDev& G = ctx->grids[g];
+  lem::StepArgs a = make_args(ctx, nullptr, nullptr);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess)
+    e = lem::launch_export(a, g, G.offset, (int64_t)G.ny * G.nx, d_rec, d_depth, d_count,
+                           ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "export launch");
+  lem::Ctrl ct;
+  e = hipMemcpyAsync(&ct, ctx->w.ctrl, sizeof(ct), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "routing readback");
+  // The histogram spans the batch's deepest level; this grid's levels end
+  // at its last non-empty bin.
+  std::vector<int32_t> tmp((size_t)ct.nlevels + 1);
+  e = hipMemcpy(tmp.data(), ctx->w.dhist, sizeof(int32_t) * tmp.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "level histogram readback");
+  int64_t nl = ct.nlevels;
+  while (nl > 1 && tmp[nl] == 0) --nl;
+  if (h_nlevels) *h_nlevels = nl;
+  if (h_level_offsets && cap >= nl + 1) {
+    int64_t acc = 0;
+    for (int64_t l = 0; l <= nl; ++l) {
+      acc += (l == 0) ? 0 : tmp[l];
+      h_level_offsets[l] = acc;
+    }
+  }
   return LEM_OK;
 }
 
@@ -172,7 +314,8 @@ extern "C" {
 size_t lem_workspace_bytes(const lem_params* p) {
   std::string why;
   if (check_params(p, &why) != LEM_OK) return 0;
-  return lem::workspace_bytes((int64_t)p->ny * p->nx);
+  lem::GridDev g = make_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->U, p->K, 0, 0);
+  return lem::workspace_bytes((int64_t)p->ny * p->nx, 1, grid_tiles(g));
 }
 
 lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream,
@@ -182,36 +325,50 @@ lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes, v
   std::string why;
   lem_status st = check_params(p, &why);
   if (st != LEM_OK) return st;
-  const int64_t n = (int64_t)p->ny * p->nx;
   if (!d_workspace || ((uintptr_t)d_workspace & 255u) != 0) return LEM_E_WORKSPACE;
-  if (ws_bytes < lem::workspace_bytes(n)) return LEM_E_WORKSPACE;
+  if (ws_bytes < lem_workspace_bytes(p)) return LEM_E_WORKSPACE;
   lem_ctx* ctx = new (std::nothrow) lem_ctx();
   if (!ctx) return LEM_E_ARG;
-  ctx->p = *p;
-  ctx->stream = (hipStream_t)hip_stream;
-  lem::carve(d_workspace, n, &ctx->w);
-  hipError_t e = hipGetDevice(&ctx->device);
-  int cus = 0, per_cu = 0, rate = 0;
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-  if (e == hipSuccess) e = lem::global_kernel_occupancy(&per_cu);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, ctx->device);
-  if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
-  if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
-  if (e == hipSuccess) e = hipEventCreate(&ctx->ev2);
-  if (e != hipSuccess || per_cu < 1) {
+  ctx->flags = p->flags;
+  ctx->batch = false;
+  ctx->grids.push_back(make_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->U, p->K, 0, 0));
+  ctx->cells = (int64_t)p->ny * p->nx;
+  ctx->ntiles = grid_tiles(ctx->grids[0]);
+  st = create_impl(ctx, d_workspace, ws_bytes, hip_stream);
+  if (st != LEM_OK) {
     delete ctx;
-    return LEM_E_HIP;
+    return st;
   }
-  // The global level kernel uses at most kGlobalMaxWGs resident workgroups:
-  // a grid-wide barrier's cost grows with the number of participants.
-  ctx->grid_max = cus * per_cu;
-  ctx->grid = ctx->grid_max < lem::kGlobalMaxWGs ? ctx->grid_max : lem::kGlobalMaxWGs;
-  ctx->tail_level = lem::kTailLevel;
-  ctx->tick_khz = (double)rate;
-  e = hipMemsetAsync(ctx->w.ctrl, 0, sizeof(lem::Ctrl), ctx->stream);
-  if (e != hipSuccess) {
+  *out = ctx;
+  return LEM_OK;
+}
+
+size_t lem_batch_workspace_bytes(const lem_grid* grids, int32_t count) {
+  std::vector<lem::GridDev> g;
+  int64_t cells = 0;
+  int32_t ntiles = 0;
+  std::string why;
+  if (build_batch(grids, count, &g, &cells, &ntiles, &why) != LEM_OK) return 0;
+  return lem::workspace_bytes(cells, count, ntiles);
+}
+
+lem_status lem_batch_create(const lem_grid* grids, int32_t count, uint32_t flags,
+                            void* d_workspace, size_t ws_bytes, void* hip_stream, lem_ctx** out) {
+  if (!out) return LEM_E_ARG;
+  *out = nullptr;
+  if (flags & ~(LEM_F_VALIDATE | LEM_F_PHASE_TIMERS)) return LEM_E_ARG;
+  lem_ctx* ctx = new (std::nothrow) lem_ctx();
+  if (!ctx) return LEM_E_ARG;
+  std::string why;
+  lem_status st = build_batch(grids, count, &ctx->grids, &ctx->cells, &ctx->ntiles, &why);
+  if (st == LEM_OK) {
+    ctx->flags = flags;
+    ctx->batch = true;
+    st = create_impl(ctx, d_workspace, ws_bytes, hip_stream);
+  }
+  if (st != LEM_OK) {
     delete ctx;
-    return LEM_E_HIP;
+    return st;
   }
   *out = ctx;
   return LEM_OK;
@@ -219,12 +376,108 @@ lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes, v
 
 lem_status lem_run(lem_ctx* ctx, double* d_h, const double* d_K, const double* d_U,
                    int64_t steps) {
+  if (ctx && ctx->batch && (d_K || d_U))
+    return fail(ctx, LEM_E_ARG, "per-cell K or U fields need a single-grid context");
   return run_impl(ctx, d_h, nullptr, d_K, d_U, steps);
+}
+
+lem_status lem_batch_run(lem_ctx* ctx, double* d_h, int64_t steps) {
+  return run_impl(ctx, d_h, nullptr, nullptr, nullptr, steps);
+}
+
+lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, double rtol, int64_t check_every,
+                                   int64_t max_steps, int64_t* h_steps) {
+  if (!ctx) return LEM_E_ARG;
+  if (!d_h || !h_steps) return fail(ctx, LEM_E_ARG, "d_h and h_steps must not be NULL");
+  if (!(rtol > 0.0) || check_every < 1 || max_steps < 1)
+    return fail(ctx, LEM_E_ARG, "rtol must be > 0, check_every and max_steps >= 1");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  if (ctx->flags & LEM_F_VALIDATE) {
+    lem_status st = validate_inputs(ctx, d_h, nullptr, nullptr);
+    if (st != LEM_OK) return st;
+  }
+  const int32_t ng = (int32_t)ctx->grids.size();
+  for (int32_t g = 0; g < ng; ++g) h_steps[g] = -1;
+  lem::StepArgs a = make_args(ctx, nullptr, nullptr);
+  e = lem::launch_begin_run(a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "begin-run launch");
+  const bool timers = (ctx->flags & LEM_F_PHASE_TIMERS) != 0;
+  ctx->route_ms = ctx->order_ms = 0.0;
+  std::vector<char> done(ng, 0);
+  std::vector<double> conv(2 * (size_t)ng);
+  int64_t active_cells = ctx->cells;
+  int64_t s = 0;
+  double* cur = d_h;  // buffer holding the latest heights
+  double* other = ctx->w.h2;
+  lem_status st = LEM_OK;
+  while (s < max_steps && active_cells > 0 && st == LEM_OK) {
+    const int64_t k = (max_steps - s) < check_every ? (max_steps - s) : check_every;
+    for (int64_t j = 0; j < k; ++j, ++s) {
+      a.step = s;
+      a.h_in = cur;
+      a.h_out = other;
+      a.export_routing = 0;
+      st = step(ctx, a, timers);
+      if (st != LEM_OK) break;
+      double* t = cur;
+      cur = other;
+      other = t;
+    }
+    if (st != LEM_OK) break;
+    // Relative change of the last step, per grid: max|dh| <= rtol * max|h|.
+    lem::StepArgs c = a;
+    c.h_in = other;
+    c.h_out = cur;
+    e = lem::launch_change(c, ctx->cells, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(conv.data(), ctx->w.conv, sizeof(double) * conv.size(),
+                         hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "convergence check");
+    bool changed = false;
+    for (int32_t g = 0; g < ng; ++g) {
+      if (done[g] || !(conv[2 * g] <= rtol * conv[2 * g + 1])) continue;
+      done[g] = 1;
+      h_steps[g] = s;
+      changed = true;
+      // Both height buffers hold the grid's final heights from now on.
+      const lem::GridDev& G = ctx->grids[g];
+      e = hipMemcpyAsync(other + G.offset, cur + G.offset, sizeof(double) * G.ny * G.nx,
+                         hipMemcpyDeviceToDevice, ctx->stream);
+      if (e != hipSuccess) return hip_fail(ctx, e, "freeze copy");
+      active_cells -= (int64_t)G.ny * G.nx;
+    }
+    if (changed && active_cells > 0) {
+      ctx->active.clear();
+      for (int32_t g = 0; g < ng; ++g) {
+        if (done[g]) continue;
+        const lem::GridDev& G = ctx->grids[g];
+        for (int32_t t = 0; t < grid_tiles(G); ++t) ctx->active.push_back(G.tile_base + t);
+      }
+      st = upload_tiles(ctx, ctx->active);
+      a.ntiles = (int32_t)ctx->active.size();
+      a.n = (int32_t)active_cells;
+    }
+  }
+  // Restore the full tile list for later runs.
+  const lem_status st2 = upload_tiles(ctx, ctx->tiles);
+  if (st == LEM_OK) st = st2;
+  if (st != LEM_OK) return st;
+  if (cur != d_h) {
+    e = hipMemcpyAsync(d_h, cur, sizeof(double) * (size_t)ctx->cells, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "final copy");
+  }
+  ctx->steps_done += s;
+  ctx->last_run_steps = s;
+  return LEM_OK;
 }
 
 lem_status lem_run_fixed_routing(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode,
                                  const double* d_K, const double* d_U, int64_t steps) {
   if (!ctx) return LEM_E_ARG;
+  if (ctx->batch) return fail(ctx, LEM_E_ARG, "fixed routing needs a single-grid context");
   if (!d_rcode) return fail(ctx, LEM_E_ARG, "d_rcode is NULL");
   return run_impl(ctx, d_h, d_rcode, d_K, d_U, steps);
 }
@@ -241,6 +494,8 @@ lem_status lem_sync(lem_ctx* ctx) {
     (void)hipMemcpy(&ctx->w.ctrl->status, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
     if (status == LEM_E_CYCLE)
       return fail(ctx, LEM_E_CYCLE, "receivers form a cycle or leave cells unreachable");
+    if (status == LEM_E_HIP)
+      return fail(ctx, LEM_E_HIP, "a device-wide barrier timed out");
     return fail(ctx, (lem_status)status, "fixed routing holds an invalid receiver code");
   }
   return LEM_OK;
@@ -248,34 +503,13 @@ lem_status lem_sync(lem_ctx* ctx) {
 
 lem_status lem_routing(lem_ctx* ctx, int32_t* d_rec, int32_t* d_depth, uint32_t* d_count,
                        int64_t* h_level_offsets, int64_t cap, int64_t* h_nlevels) {
-  if (!ctx) return LEM_E_ARG;
-  if (!ctx->has_routing) return fail(ctx, LEM_E_STATE, "no step has run on this context");
-  if (cap < 0) return fail(ctx, LEM_E_ARG, "cap must be >= 0");
-  lem::StepArgs a = make_args(ctx, nullptr, nullptr);
-  hipError_t e = hipSetDevice(ctx->device);
-  if (e == hipSuccess) e = lem::launch_export(a, d_rec, d_depth, d_count, ctx->stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "export launch");
-  lem::Ctrl ct;
-  e = hipMemcpyAsync(&ct, ctx->w.ctrl, sizeof(ct), hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "routing readback");
-  const int64_t nl = ct.nlevels;
-  if (h_nlevels) *h_nlevels = nl;
-  if (h_level_offsets && cap >= nl + 1) {
-    int32_t* tmp = new (std::nothrow) int32_t[nl + 1];
-    if (!tmp) return fail(ctx, LEM_E_ARG, "host allocation failed");
-    e = hipMemcpy(tmp, ctx->w.dhist, sizeof(int32_t) * (nl + 1), hipMemcpyDeviceToHost);
-    if (e == hipSuccess) {
-      int64_t acc = 0;
-      for (int64_t l = 0; l <= nl; ++l) {
-        acc += (l == 0) ? 0 : tmp[l];
-        h_level_offsets[l] = acc;
-      }
-    }
-    delete[] tmp;
-    if (e != hipSuccess) return hip_fail(ctx, e, "level histogram readback");
-  }
-  return LEM_OK;
+  return routing_impl(ctx, 0, d_rec, d_depth, d_count, h_level_offsets, cap, h_nlevels);
+}
+
+lem_status lem_batch_routing(lem_ctx* ctx, int32_t grid, int32_t* d_rec, int32_t* d_depth,
+                             uint32_t* d_count, int64_t* h_level_offsets, int64_t cap,
+                             int64_t* h_nlevels) {
+  return routing_impl(ctx, grid, d_rec, d_depth, d_count, h_level_offsets, cap, h_nlevels);
 }
 
 lem_status lem_level_history(lem_ctx* ctx, int32_t* h_levels, int64_t cap, int64_t* h_n) {

@@ -60,12 +60,31 @@ struct Ctrl {
   uint32_t pad2[31];
 };
 
+// One grid of a batch (a single-grid context is a batch of one).  Grids
+// are stored one after another in the batch arrays; tiles are numbered
+// across the whole batch.
+struct GridDev {
+  int64_t offset;          // first cell of this grid in the batch arrays
+  int32_t ny, nx;
+  int32_t tiles_x, tile_base;  // tiles [tile_base, tile_base + tiles_x * tiles_y)
+  int32_t use_sqrt;        // m == 0.5: A^m computed as sqrt(A)
+  int32_t square;          // dx == dy
+  double dx, dy, ddiag, dxdy;
+  double dt, m, K, udt;
+  double inv_dx, inv_dy, inv_dd;
+  double pad;
+};
+
 // Pointers into the workspace.
 struct Work {
   double* h2;        // [N] second height buffer (steps alternate between h and h2)
   uint8_t* rcode;    // [N] receiver codes (fixed routing; export step)
   uint8_t* dmask;    // [N] donor mask per cell: bit k set <=> neighbour k drains here
+  GridDev* grids;    // [ngrids] grid descriptors
+  int32_t* tiles;    // [ntiles] tiles to process (all, or those of unfinished grids)
+  double* conv;      // [2*ngrids] per grid: largest |change| and largest |h| of a step
   int32_t* q;        // [N] global queue: cell per position, level-major
+  uint16_t* gq;      // [N] grid of each queue position
   int32_t* par;      // [N] queue position of the receiver (-1 at level 0)
   int32_t* fc;       // [N] queue position of the first donor
   uint8_t* mq;       // [N] donor mask in queue order
@@ -77,9 +96,9 @@ struct Work {
   int32_t* dep_g;    // [N] level per cell (export step)
   uint32_t* cnt_g;   // [N] upstream count per cell (export step)
   int32_t* dhist;    // [N+2] level histogram (export)
-  double* amtab;     // [kAmTab] A^m for small counts
-  double* ftab;      // [3*kAmTab] F = K*dt*A^m/d per distance class (scalar K)
-  double* gtab;      // [3*kAmTab] 1 + F
+  double* amtab;     // [ngrids*kAmTab] A^m for small counts
+  double* ftab;      // [ngrids*3*kAmTab] F = K*dt*A^m/d per distance class (scalar K)
+  double* gtab;      // [ngrids*3*kAmTab] 1 + F
   int32_t* hist;     // [kHistCap] level count per step of the current run
   Ctrl* ctrl;
   int32_t* scratch;  // [kScratchInts] reductions (validation)
@@ -90,33 +109,35 @@ constexpr int64_t kScratchInts = 1024;
 
 // Everything one time step needs, passed by value to the kernels.
 struct StepArgs {
-  int32_t ny, nx;
-  int32_t n;          // ny*nx
-  int32_t use_sqrt;   // m == 0.5: A^m computed as sqrt(A)
-  double dx, dy, ddiag, dxdy;
-  double dt, m, K, udt;
-  const double* Kf;   // nullable per-cell K
-  const double* Uf;   // nullable per-cell U
-  const double* h_in; // heights at the start of the step
-  double* h_out;      // heights at the end of the step
+  const GridDev* grids;  // device copy of the grid descriptors
+  int32_t ngrids;
+  int32_t ntiles;        // entries of w.tiles to process
+  int32_t n;             // cells of all grids
+  int32_t timers;        // record per-phase ticks
+  const double* Kf;      // nullable per-cell K (single-grid contexts only)
+  const double* Uf;      // nullable per-cell U (single-grid contexts only)
+  const double* h_in;    // heights at the start of the step
+  double* h_out;         // heights at the end of the step
   Work w;
-  int64_t step;       // index of this step within the run
-  int32_t timers;     // record per-phase ticks
-  int32_t fixed;      // receivers come from w.rcode (fixed routing)
+  int64_t step;          // index of this step within the run
+  int32_t fixed;         // receivers come from w.rcode (fixed routing)
   int32_t export_routing;  // write per-cell codes, levels and counts
-  int32_t tiles_x, tiles_y;
-  int32_t tail_level;      // levels smaller than this run in one workgroup
+  int32_t tail_level;    // levels smaller than this run in one workgroup
+  int32_t pad;
 };
 
-size_t workspace_bytes(int64_t n);
-void carve(void* base, int64_t n, Work* w);
+size_t workspace_bytes(int64_t n, int64_t ngrids, int64_t ntiles);
+void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w);
 
 hipError_t launch_begin_run(const StepArgs& a, hipStream_t s);
 hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user_rcode, hipStream_t s);
 hipError_t launch_tile_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s);
-hipError_t launch_export(const StepArgs& a, int32_t* rec, int32_t* depth, uint32_t* count,
-                         hipStream_t s);
+// Routing export of grid g (its cells [offset, offset + ny*nx)).
+hipError_t launch_export(const StepArgs& a, int g, int64_t offset, int64_t cells, int32_t* rec,
+                         int32_t* depth, uint32_t* count, hipStream_t s);
+// Per grid: largest |h_out - h_in| and largest |h_out| (into w.conv).
+hipError_t launch_change(const StepArgs& a, int64_t total_cells, hipStream_t s);
 hipError_t launch_validate(const double* x, int64_t n, int32_t* flag, hipStream_t s);
 hipError_t global_kernel_occupancy(int* blocks_per_cu);
 

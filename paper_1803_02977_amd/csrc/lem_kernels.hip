@@ -186,24 +186,36 @@ __device__ __forceinline__ uint8_t receiver_code(const double* h, int ci, int W,
   return receiver_code_by_definition(h, ci, W, rk.dx, rk.dy, rk.dd);
 }
 
-// F = K*dt*A^m/d and 1 + F for a cell with `count` upstream cells that
-// drains along code k (A = count*dx*dy).  Scalar K and small counts read the
-// tables built at the start of the run from the same expressions.
-__device__ __forceinline__ void erosion_factor(const StepArgs& a, uint32_t count, int k,
-                                               int64_t c, double* f, double* g) {
+// F = K*dt*A^m/d and 1 + F for a cell of grid gi (descriptor G) with
+// `count` upstream cells that drains along code k (A = count*dx*dy).
+// Scalar K and small counts read the grid's tables, built at the start of
+// the run from the same expressions.
+__device__ __forceinline__ void erosion_factor(const StepArgs& a, const GridDev& G, int gi,
+                                               uint32_t count, int k, int64_t c, double* f,
+                                               double* g) {
   const int cls = code_class(k);
   if (!a.Kf && count < (uint32_t)kAmTab) {
-    *f = a.w.ftab[cls * kAmTab + count];
-    *g = a.w.gtab[cls * kAmTab + count];
+    *f = a.w.ftab[(gi * 3 + cls) * kAmTab + count];
+    *g = a.w.gtab[(gi * 3 + cls) * kAmTab + count];
     return;
   }
-  const double d = cls == 0 ? a.dy : (cls == 1 ? a.dx : a.ddiag);
+  const double d = cls == 0 ? G.dy : (cls == 1 ? G.dx : G.ddiag);
   const double am = count < (uint32_t)kAmTab
-                        ? a.w.amtab[count]
-                        : area_power_call((double)count * a.dxdy, a.use_sqrt, a.m);
-  const double kc = a.Kf ? a.Kf[c] : a.K;
-  *f = ((kc * a.dt) * am) / d;
+                        ? a.w.amtab[gi * kAmTab + count]
+                        : area_power_call((double)count * G.dxdy, G.use_sqrt, G.m);
+  const double kc = a.Kf ? a.Kf[c] : G.K;
+  *f = ((kc * G.dt) * am) / d;
   *g = 1.0 + *f;
+}
+
+// Grid of a tile: the last grid whose first tile is at or before it.
+__device__ __forceinline__ int grid_of_tile(const GridDev* grids, int ngrids, int tile) {
+  int lo = 0, hi = ngrids;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (grids[mid].tile_base <= tile) lo = mid; else hi = mid;
+  }
+  return lo;
 }
 
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
@@ -264,11 +276,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   __shared__ int s_all, s_clean, s_cmax, s_base;
 
   const int tid = threadIdx.x;
-  const int ntiles = a.tiles_x * a.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int y0 = (tile / a.tiles_x) * kTH, x0 = (tile % a.tiles_x) * kTW;
-  const int ny = a.ny, nx = a.nx;
   const Work w = a.w;
+  const int tile = w.tiles[xcd_tile(blockIdx.x, a.ntiles)];
+  const int gi = grid_of_tile(a.grids, a.ngrids, tile);
+  const GridDev G = a.grids[gi];
+  const int lt = tile - G.tile_base;
+  const int y0 = (lt / G.tiles_x) * kTH, x0 = (lt % G.tiles_x) * kTW;
+  const int ny = G.ny, nx = G.nx;
+  const int64_t off = G.offset;
 
   if (tid == 0) {
     s_flag[0] = 0;
@@ -288,7 +303,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
       const int i = tid + j * kTileThreads;
       const int gy = y0 - 2 + i / kHW, gx = x0 - 2 + i % kHW;
       v[j] = (i < kHH * kHW && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
-                 ? a.h_in[(int64_t)gy * nx + gx] : 0.0;
+                 ? a.h_in[off + (int64_t)gy * nx + gx] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < kStageLoads; ++j) {
@@ -299,14 +314,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   __syncthreads();
 
   // Receiver codes of the tile and its ring.
-  const bool square = a.dx == a.dy;
+  const bool square = G.square != 0;
   RecvConst rk;
-  rk.dx = a.dx;
-  rk.dy = a.dy;
-  rk.dd = a.ddiag;
-  rk.inv_dx = 1.0 / a.dx;
-  rk.inv_dy = 1.0 / a.dy;
-  rk.inv_dd = 1.0 / a.ddiag;
+  rk.dx = G.dx;
+  rk.dy = G.dy;
+  rk.dd = G.ddiag;
+  rk.inv_dx = G.inv_dx;
+  rk.inv_dy = G.inv_dy;
+  rk.inv_dd = G.inv_dd;
   for (int i = tid; i < kRH * kRW; i += kTileThreads) {
     const int ly = i / kRW, lx = i % kRW;
     const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
@@ -314,7 +329,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     if (gy < 0 || gy >= ny || gx < 0 || gx >= nx)
       code = kNone;
     else if (a.fixed)
-      code = w.rcode[(int64_t)gy * nx + gx];
+      code = w.rcode[off + (int64_t)gy * nx + gx];
     else if (gy == 0 || gx == 0 || gy == ny - 1 || gx == nx - 1)
       code = kBase;
     else if (square)
@@ -492,18 +507,18 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     for (int j = lo + tid; j < hi; j += kTileThreads) {
       const int i = lst[j];
       const int ly = i / kTW, lx = i % kTW;
-      const int64_t c = (int64_t)(y0 + ly) * nx + (x0 + lx);
+      const int64_t c = off + (int64_t)(y0 + ly) * nx + (x0 + lx);
       const int hidx = (ly + 2) * kHW + (lx + 2);
       const int code = rc[(ly + 1) * kRW + (lx + 1)];
       if (code == kBase) continue;
-      const double up = a.Uf ? a.Uf[c] * a.dt : a.udt;
+      const double up = a.Uf ? a.Uf[c] * G.dt : G.udt;
       if (code == kSink) {
         hs[hidx] = hs[hidx] + up;
         continue;
       }
       const uint32_t count = (clw[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
       double f, g;
-      erosion_factor(a, count, code, c, &f, &g);
+      erosion_factor(a, G, gi, count, code, c, &f, &g);
       const double h0 = hs[hidx] + up;
       hs[hidx] = (h0 + f * hs[hidx + code_dy(code) * kHW + code_dx(code)]) / g;
     }
@@ -519,7 +534,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     const int i = tid + t * kTileThreads;
     const int ly = i / kTW, lx = i % kTW;
     if (y0 + ly >= ny || x0 + lx >= nx) continue;
-    const int64_t c = (int64_t)(y0 + ly) * nx + (x0 + lx);
+    const int64_t c = off + (int64_t)(y0 + ly) * nx + (x0 + lx);
     const int code = rc[(ly + 1) * kRW + (lx + 1)];
     const bool clean = (clean_bits >> t) & 1u;
     a.h_out[c] = hs[(ly + 2) * kHW + (lx + 2)];
@@ -547,8 +562,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     root_bits &= root_bits - 1;
     const int i = tid + t * kTileThreads;
     const int ly = i / kTW, lx = i % kTW;
-    const int64_t c = (int64_t)(y0 + ly) * nx + (x0 + lx);
+    const int64_t c = off + (int64_t)(y0 + ly) * nx + (x0 + lx);
     w.q[pos] = (int32_t)c;
+    w.gq[pos] = (uint16_t)gi;
     w.par[pos] = -1;
     w.kq[pos] = rc[(ly + 1) * kRW + (lx + 1)];
     ++pos;
@@ -595,10 +611,9 @@ __device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t 
                              int nwg, int* wsum, int* s_base) {
   const Work& w = a.w;
   const int tid = threadIdx.x;
-  const int nx = a.nx;
   for (int64_t base = lo + (int64_t)wg * kChunk; base < hi; base += (int64_t)nwg * kChunk) {
     int32_t cs[kItems];
-    uint32_t ms[kItems];
+    uint32_t ms[kItems];  // donor mask | grid << 8
     int cntv = 0;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
@@ -607,8 +622,9 @@ __device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t 
       ms[j] = 0;
       if (i < hi) {
         cs[j] = w.q[i];
-        ms[j] = w.dmask[cs[j]];
-        cntv += __popc(ms[j]);
+        const uint32_t m = w.dmask[cs[j]];
+        ms[j] = m | ((uint32_t)w.gq[i] << 8);
+        cntv += __popc(m);
       }
     }
     int tot;
@@ -620,16 +636,21 @@ __device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t 
     for (int j = 0; j < kItems; ++j) {
       const int64_t i = base + (int64_t)j * kBlock + tid;
       if (i < hi) {
-        uint32_t m = ms[j];
+        uint32_t m = ms[j] & 0xFFu;
+        const uint32_t gi = ms[j] >> 8;
         w.mq[i] = (uint8_t)m;
         w.fc[i] = pos;
-        while (m) {
-          const int b = __ffs(m) - 1;
-          m &= m - 1;
-          w.q[pos] = (int32_t)(cs[j] + neighbour_offset(b, nx));
-          w.par[pos] = (int32_t)i;
-          w.kq[pos] = (uint8_t)(7 - b);
-          ++pos;
+        if (m) {
+          const int nx = a.grids[gi].nx;
+          while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1;
+            w.q[pos] = (int32_t)(cs[j] + neighbour_offset(b, nx));
+            w.gq[pos] = (uint16_t)gi;
+            w.par[pos] = (int32_t)i;
+            w.kq[pos] = (uint8_t)(7 - b);
+            ++pos;
+          }
         }
       }
     }
@@ -659,10 +680,12 @@ __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32
   for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1;
        i += (int64_t)nwg * kBlock) {
     const int32_t c = w.q[i];
+    const int gi = w.gq[i];
+    const GridDev& G = a.grids[gi];
     const double hr = w.hq[w.par[i]];
     double f, g;
-    erosion_factor(a, w.cnt[i], w.kq[i], c, &f, &g);
-    const double h0 = a.h_in[c] + (a.Uf ? a.Uf[c] * a.dt : a.udt);
+    erosion_factor(a, G, gi, w.cnt[i], w.kq[i], c, &f, &g);
+    const double h0 = a.h_in[c] + (a.Uf ? a.Uf[c] * G.dt : G.udt);
     const double hn = (h0 + f * hr) / g;
     w.hq[i] = hn;
     a.h_out[c] = hn;
@@ -770,7 +793,10 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
     for (int64_t i = (int64_t)wg * kBlock + tid; i < a1; i += (int64_t)nwg * kBlock) {
       const int32_t c = w.q[i];
       double hv = a.h_in[c];
-      if (w.kq[i] == kSink) hv = hv + (a.Uf ? a.Uf[c] * a.dt : a.udt);
+      if (w.kq[i] == kSink) {
+        const GridDev& G = a.grids[w.gq[i]];
+        hv = hv + (a.Uf ? a.Uf[c] * G.dt : G.udt);
+      }
       a.h_out[c] = hv;
       w.hq[i] = hv;
     }
@@ -823,20 +849,22 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
   }
 }
 
-// Start of a run: reset the control block and tabulate A^m, F and 1 + F.
+// Start of a run: tabulate A^m, F and 1 + F per grid (block g does grid g)
+// and reset the control block.
 __global__ void k_begin_run(StepArgs a) {
-  const int i = threadIdx.x;
+  const int i = threadIdx.x, gi = blockIdx.x;
+  const GridDev& G = a.grids[gi];
   if (i < kAmTab) {
-    const double am = area_power((double)i * a.dxdy, a.use_sqrt, a.m);
-    a.w.amtab[i] = am;
-    const double d[3] = {a.dy, a.dx, a.ddiag};
+    const double am = area_power((double)i * G.dxdy, G.use_sqrt, G.m);
+    a.w.amtab[gi * kAmTab + i] = am;
+    const double d[3] = {G.dy, G.dx, G.ddiag};
     for (int c = 0; c < 3; ++c) {
-      const double f = ((a.K * a.dt) * am) / d[c];
-      a.w.ftab[c * kAmTab + i] = f;
-      a.w.gtab[c * kAmTab + i] = 1.0 + f;
+      const double f = ((G.K * G.dt) * am) / d[c];
+      a.w.ftab[(gi * 3 + c) * kAmTab + i] = f;
+      a.w.gtab[(gi * 3 + c) * kAmTab + i] = 1.0 + f;
     }
   }
-  if (i == 0) {
+  if (i == 0 && gi == 0) {
     Ctrl* ct = a.w.ctrl;
     ct->max_nlevels = 0;
     ct->steps = 0;
@@ -855,9 +883,10 @@ __global__ void k_begin_run(StepArgs a) {
 __global__ __launch_bounds__(256) void k_fixed_routing(StepArgs a, const uint8_t* user) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n) return;
-  const int y = (int)(c / a.nx), x = (int)(c % a.nx);
+  const GridDev& G = a.grids[0];
+  const int y = (int)(c / G.nx), x = (int)(c % G.nx);
   const uint8_t u = user[c];
-  const bool perim = (y == 0 || x == 0 || y == a.ny - 1 || x == a.nx - 1);
+  const bool perim = (y == 0 || x == 0 || y == G.ny - 1 || x == G.nx - 1);
   uint8_t code;
   if (perim) {
     code = kBase;
@@ -893,23 +922,56 @@ __global__ __launch_bounds__(256) void k_export_cross(StepArgs a) {
     w.dhist[i] = 0;
 }
 
-// Routing export, part 2: per-cell receiver, level and count for the caller,
-// and the level histogram.
-__global__ __launch_bounds__(256) void k_export_cells(StepArgs a, int32_t* rec, int32_t* depth,
-                                                      uint32_t* count) {
+// Routing export, part 2: per-cell receiver, level and count of grid g
+// (cells [off, off + cells)) for the caller, and its level histogram.
+__global__ __launch_bounds__(256) void k_export_cells(StepArgs a, int gi, int64_t off,
+                                                      int64_t cells, int32_t* rec,
+                                                      int32_t* depth, uint32_t* count) {
   const Work w = a.w;
+  const int nx = a.grids[gi].nx;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int32_t nl = w.ctrl->nlevels;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
     if (rec) {
-      const uint8_t k = w.rcode[i];
-      rec[i] = (k >= kSink) ? (int32_t)i : (int32_t)(i + neighbour_offset(k, a.nx));
+      const uint8_t k = w.rcode[off + i];
+      rec[i] = (k >= kSink) ? (int32_t)i : (int32_t)(i + neighbour_offset(k, nx));
     }
-    const int32_t d = w.dep_g[i];
+    const int32_t d = w.dep_g[off + i];
     if (depth) depth[i] = d;
-    if (count) count[i] = w.cnt_g[i];
+    if (count) count[i] = w.cnt_g[off + i];
     if (d >= 0 && d < nl) atomicAdd(&w.dhist[d + 1], 1);
   }
+}
+
+// Per grid (blockIdx.y): the largest |h_out - h_in| and the largest |h_out|
+// of the step just taken.  Non-negative doubles order like their bit
+// patterns, so an unsigned atomic maximum on the bits is exact.
+__global__ __launch_bounds__(256) void k_change(StepArgs a) {
+  const GridDev& G = a.grids[blockIdx.y];
+  const int64_t cells = (int64_t)G.ny * G.nx;
+  double dmax = 0.0, hmax = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double hn = a.h_out[G.offset + i];
+    dmax = fmax(dmax, fabs(hn - a.h_in[G.offset + i]));
+    hmax = fmax(hmax, fabs(hn));
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    dmax = fmax(dmax, __shfl_xor(dmax, d, 64));
+    hmax = fmax(hmax, __shfl_xor(hmax, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    unsigned long long* cv = (unsigned long long*)a.w.conv;
+    atomicMax(&cv[2 * blockIdx.y], (unsigned long long)__double_as_longlong(dmax));
+    atomicMax(&cv[2 * blockIdx.y + 1], (unsigned long long)__double_as_longlong(hmax));
+  }
+}
+
+__global__ void k_zero_f64(double* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_validate(const double* x, int64_t n, int32_t* flag) {
@@ -924,39 +986,25 @@ __global__ __launch_bounds__(256) void k_validate(const double* x, int64_t n, in
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
-size_t workspace_bytes(int64_t n) {
-  int64_t b = 0;
-  b += align256(8 * n);                   // h2
-  b += align256(n);                       // rcode
-  b += align256(n);                       // dmask
-  b += align256(4 * n);                   // q
-  b += align256(4 * n);                   // par
-  b += align256(4 * n);                   // fc
-  b += align256(n);                       // mq
-  b += align256(n);                       // kq
-  b += align256(4 * n);                   // cnt
-  b += align256(8 * n);                   // hq
-  b += align256(4 * (n + 2));             // lcnt
-  b += align256(4 * (n + 2));             // lev
-  b += align256(4 * n);                   // dep_g
-  b += align256(4 * n);                   // cnt_g
-  b += align256(4 * (n + 2));             // dhist
-  b += align256(8 * kAmTab);              // amtab
-  b += align256(8 * 3 * kAmTab);          // ftab
-  b += align256(8 * 3 * kAmTab);          // gtab
-  b += align256(4 * kHistCap);            // hist
-  b += align256(sizeof(Ctrl));            // ctrl
-  b += align256(4 * kScratchInts);        // scratch
-  return (size_t)b;
+void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w);
+
+size_t workspace_bytes(int64_t n, int64_t ngrids, int64_t ntiles) {
+  Work w;
+  carve(nullptr, n, ngrids, ntiles, &w);
+  return (size_t)(uintptr_t)w.scratch + (size_t)align256(4 * kScratchInts);
 }
 
-void carve(void* base, int64_t n, Work* w) {
+void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w) {
   char* p = (char*)base;
   auto take = [&](int64_t bytes) { char* r = p; p += align256(bytes); return (void*)r; };
   w->h2 = (double*)take(8 * n);
   w->rcode = (uint8_t*)take(n);
   w->dmask = (uint8_t*)take(n);
+  w->grids = (GridDev*)take((int64_t)sizeof(GridDev) * ngrids);
+  w->tiles = (int32_t*)take(4 * ntiles);
+  w->conv = (double*)take(8 * 2 * ngrids);
   w->q = (int32_t*)take(4 * n);
+  w->gq = (uint16_t*)take(2 * n);
   w->par = (int32_t*)take(4 * n);
   w->fc = (int32_t*)take(4 * n);
   w->mq = (uint8_t*)take(n);
@@ -968,16 +1016,16 @@ void carve(void* base, int64_t n, Work* w) {
   w->dep_g = (int32_t*)take(4 * n);
   w->cnt_g = (uint32_t*)take(4 * n);
   w->dhist = (int32_t*)take(4 * (n + 2));
-  w->amtab = (double*)take(8 * kAmTab);
-  w->ftab = (double*)take(8 * 3 * kAmTab);
-  w->gtab = (double*)take(8 * 3 * kAmTab);
+  w->amtab = (double*)take(8 * kAmTab * ngrids);
+  w->ftab = (double*)take(8 * 3 * kAmTab * ngrids);
+  w->gtab = (double*)take(8 * 3 * kAmTab * ngrids);
   w->hist = (int32_t*)take(4 * kHistCap);
   w->ctrl = (Ctrl*)take(sizeof(Ctrl));
   w->scratch = (int32_t*)take(4 * kScratchInts);
 }
 
 hipError_t launch_begin_run(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_begin_run, dim3(1), dim3(kAmTab), 0, s, a);
+  hipLaunchKernelGGL(k_begin_run, dim3((unsigned)a.ngrids), dim3(kAmTab), 0, s, a);
   return hipGetLastError();
 }
 
@@ -988,8 +1036,8 @@ hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user, hipStrea
 }
 
 hipError_t launch_tile_step(const StepArgs& a, hipStream_t s) {
-  const unsigned ntiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
-  hipLaunchKernelGGL(k_tile_step, dim3(ntiles), dim3(kTileThreads), 0, s, a);
+  if (a.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_step, dim3((unsigned)a.ntiles), dim3(kTileThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1000,12 +1048,22 @@ hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s) {
                                     0, s);
 }
 
-hipError_t launch_export(const StepArgs& a, int32_t* rec, int32_t* depth, uint32_t* count,
-                         hipStream_t s) {
+hipError_t launch_export(const StepArgs& a, int g, int64_t offset, int64_t cells, int32_t* rec,
+                         int32_t* depth, uint32_t* count, hipStream_t s) {
   hipLaunchKernelGGL(k_export_cross, dim3(1024), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_export_cells, dim3(2048), dim3(256), 0, s, a, rec, depth, count);
+  hipLaunchKernelGGL(k_export_cells, dim3(2048), dim3(256), 0, s, a, g, offset, cells, rec, depth,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_change(const StepArgs& a, int64_t total_cells, hipStream_t s) {
+  (void)total_cells;
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, a.w.conv, (int64_t)2 * a.ngrids);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_change, dim3(16, (unsigned)a.ngrids), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

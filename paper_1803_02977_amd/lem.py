@@ -20,8 +20,10 @@ LEM_F_VALIDATE, LEM_F_PHASE_TIMERS = 0x1, 0x2
 
 # Symbols declared in include/lem.h.
 EXPORTS = ("lem_workspace_bytes", "lem_create", "lem_run", "lem_run_fixed_routing",
-           "lem_sync", "lem_routing", "lem_level_history", "lem_stats", "lem_set_tuning",
-           "lem_get_tuning", "lem_destroy", "lem_status_str", "lem_last_error")
+           "lem_sync", "lem_routing", "lem_batch_workspace_bytes", "lem_batch_create",
+           "lem_batch_run", "lem_batch_run_to_steady", "lem_batch_routing",
+           "lem_level_history", "lem_stats", "lem_set_tuning", "lem_get_tuning", "lem_destroy",
+           "lem_status_str", "lem_last_error")
 
 
 class lem_params(C.Structure):
@@ -35,6 +37,12 @@ class lem_stats_t(C.Structure):
                 ("max_nlevels", C.c_int64), ("last_run_steps", C.c_int64),
                 ("phase_ms", C.c_double * 4), ("kernel_ms", C.c_double * 2),
                 ("crossing_last", C.c_int64), ("crossing_run", C.c_int64)]
+
+
+class lem_grid(C.Structure):
+    _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("dt", C.c_double), ("m", C.c_double), ("U", C.c_double), ("K", C.c_double),
+                ("offset", C.c_int64)]
 
 
 class lem_tuning(C.Structure):
@@ -76,6 +84,18 @@ def load(path: str = LIB_PATH):
     lib.lem_level_history.restype = C.c_int
     lib.lem_stats.argtypes = [_P, C.POINTER(lem_stats_t)]
     lib.lem_stats.restype = C.c_int
+    lib.lem_batch_workspace_bytes.argtypes = [C.POINTER(lem_grid), C.c_int32]
+    lib.lem_batch_workspace_bytes.restype = C.c_size_t
+    lib.lem_batch_create.argtypes = [C.POINTER(lem_grid), C.c_int32, C.c_uint32, _P, C.c_size_t,
+                                     _P, C.POINTER(_P)]
+    lib.lem_batch_create.restype = C.c_int
+    lib.lem_batch_run.argtypes = [_P, _P, C.c_int64]
+    lib.lem_batch_run.restype = C.c_int
+    lib.lem_batch_run_to_steady.argtypes = [_P, _P, C.c_double, C.c_int64, C.c_int64, _P]
+    lib.lem_batch_run_to_steady.restype = C.c_int
+    lib.lem_batch_routing.argtypes = [_P, C.c_int32, _P, _P, _P, _P, C.c_int64,
+                                      C.POINTER(C.c_int64)]
+    lib.lem_batch_routing.restype = C.c_int
     lib.lem_set_tuning.argtypes = [_P, C.POINTER(lem_tuning)]
     lib.lem_set_tuning.restype = C.c_int
     lib.lem_get_tuning.argtypes = [_P, C.POINTER(lem_tuning)]
@@ -134,6 +154,41 @@ def lem_routing(ctx: int, d_rec, d_depth, d_count, cap: int):
     return offsets[: nl.value + 1] if cap >= nl.value + 1 else None, nl.value
 
 
+def lem_batch_workspace_bytes(grids) -> int:
+    arr = (lem_grid * len(grids))(*grids)
+    return int(load().lem_batch_workspace_bytes(arr, len(grids)))
+
+
+def lem_batch_create(grids, flags: int, d_workspace: int, ws_bytes: int, hip_stream: int) -> int:
+    arr = (lem_grid * len(grids))(*grids)
+    ctx = _P()
+    _check(load().lem_batch_create(arr, len(grids), flags, d_workspace, ws_bytes, hip_stream,
+                                   C.byref(ctx)))
+    return ctx.value
+
+
+def lem_batch_run(ctx: int, d_h: int, steps: int) -> None:
+    _check(load().lem_batch_run(ctx, d_h, steps), ctx)
+
+
+def lem_batch_run_to_steady(ctx: int, d_h: int, rtol: float, check_every: int, max_steps: int,
+                            count: int):
+    import numpy as np
+    out = np.zeros(count, np.int64)
+    _check(load().lem_batch_run_to_steady(ctx, d_h, rtol, check_every, max_steps,
+                                          out.ctypes.data_as(_P)), ctx)
+    return out
+
+
+def lem_batch_routing(ctx: int, grid: int, d_rec, d_depth, d_count, cap: int):
+    import numpy as np
+    offsets = np.zeros(max(cap, 1), np.int64)
+    nl = C.c_int64(0)
+    _check(load().lem_batch_routing(ctx, grid, d_rec, d_depth, d_count,
+                                    offsets.ctypes.data_as(_P), cap, C.byref(nl)), ctx)
+    return offsets[: nl.value + 1] if cap >= nl.value + 1 else None, nl.value
+
+
 def lem_level_history(ctx: int, cap: int):
     import numpy as np
     out = np.zeros(max(cap, 1), np.int32)
@@ -176,6 +231,19 @@ def _dptr(t):
     return None if t is None else t.data_ptr()
 
 
+def _apply_tuning(obj, cells, tuning):
+    """tuning: None (library defaults), "auto" (tuning.json if present) or
+    a (global_workgroups, tail_level) pair."""
+    if tuning is None:
+        return
+    if tuning == "auto":
+        from . import tune
+        tuning = tune.lookup(cells)
+        if tuning is None:
+            return
+    obj.set_tuning(*tuning)
+
+
 class Solver:
     """A context plus its workspace, for torch tensors on one ROCm device.
 
@@ -184,7 +252,7 @@ class Solver:
     """
 
     def __init__(self, ny, nx, dx=100.0, dy=100.0, dt=1000.0, m=0.5, U=5e-4, K=1e-5,
-                 n=1.0, flags=0, device=None, stream=None):
+                 n=1.0, flags=0, device=None, stream=None, tuning="auto"):
         import torch
         self.torch = torch
         self.device = torch.device(device or "cuda")
@@ -197,6 +265,7 @@ class Solver:
         with torch.cuda.device(self.device):
             self.ctx = lem_create(self.params, self.workspace.data_ptr(), nbytes,
                                   self.stream.cuda_stream)
+        _apply_tuning(self, ny * nx, tuning)
 
     def _check_field(self, t, name):
         torch = self.torch
@@ -249,6 +318,96 @@ class Solver:
         lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level))
         t = lem_get_tuning(self.ctx)
         return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lem_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent grids advanced together (one context, one buffer).
+
+    ``grids`` is a list of dicts or objects with ny, nx, dx, dy, dt, m, U, K.
+    ``h`` is a float64 device tensor of ``total_cells`` elements holding the
+    grids back to back; ``view(h, g)`` returns grid g as an (ny, nx) view.
+    """
+
+    def __init__(self, grids, flags=0, device=None, stream=None, tuning="auto"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        descs, off = [], 0
+        for g in grids:
+            get = (lambda k: g[k]) if isinstance(g, dict) else (lambda k: getattr(g, k))
+            d = lem_grid(int(get("ny")), int(get("nx")), float(get("dx")), float(get("dy")),
+                         float(get("dt")), float(get("m")), float(get("U")), float(get("K")), off)
+            descs.append(d)
+            off += d.ny * d.nx
+        self.descs = descs
+        self.offsets = [d.offset for d in descs]
+        self.shapes = [(d.ny, d.nx) for d in descs]
+        self.total_cells = off
+        nbytes = lem_batch_workspace_bytes(descs)
+        if nbytes == 0:
+            raise LemError(LEM_E_ARG, "invalid grid descriptors")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.ctx = lem_batch_create(descs, flags, self.workspace.data_ptr(), nbytes,
+                                        self.stream.cuda_stream)
+        _apply_tuning(self, self.total_cells, tuning)
+
+    def _check_h(self, h):
+        torch = self.torch
+        if (h.dtype != torch.float64 or h.numel() != self.total_cells or not h.is_contiguous()
+                or h.device != self.device):
+            raise LemError(LEM_E_ARG, f"h must be a contiguous float64 tensor of "
+                                      f"{self.total_cells} elements on {self.device}")
+
+    def view(self, h, g):
+        ny, nx = self.shapes[g]
+        o = self.offsets[g]
+        return h.view(-1)[o: o + ny * nx].view(ny, nx)
+
+    def run(self, h, steps):
+        self._check_h(h)
+        lem_batch_run(self.ctx, h.data_ptr(), int(steps))
+
+    def run_to_steady(self, h, rtol=1e-6, check_every=10, max_steps=100000):
+        self._check_h(h)
+        return lem_batch_run_to_steady(self.ctx, h.data_ptr(), float(rtol), int(check_every),
+                                       int(max_steps), len(self.descs))
+
+    def sync(self):
+        lem_sync(self.ctx)
+
+    def routing(self, g):
+        torch = self.torch
+        if not 0 <= g < len(self.shapes):
+            lem_batch_routing(self.ctx, g, None, None, None, 0)  # raises LEM_E_ARG
+        shape = self.shapes[g]
+        rec = torch.empty(shape, dtype=torch.int32, device=self.device)
+        depth = torch.empty(shape, dtype=torch.int32, device=self.device)
+        count = torch.empty(shape, dtype=torch.int32, device=self.device)
+        _, nl = lem_batch_routing(self.ctx, g, rec.data_ptr(), depth.data_ptr(),
+                                  count.data_ptr(), 0)
+        offsets, _ = lem_batch_routing(self.ctx, g, None, None, None, nl + 1)
+        return dict(rec=rec, depth=depth, count=count, offsets=offsets, nlevels=nl)
+
+    def set_tuning(self, global_workgroups=0, tail_level=0):
+        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level))
+        t = lem_get_tuning(self.ctx)
+        return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level)
+
+    def stats(self) -> lem_stats_t:
+        return lem_stats(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

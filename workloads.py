@@ -117,3 +117,8 @@ def batch_realizations(count: int = 512, seed: int = 0, sizes=BATCH_SIZES,
         m = float(rng.uniform(0.35, 0.6))
         out.append(Realization(s, s, dx, dx, dt, m, u, k, seed * 100003 + i))
     return out
+
+
+def batch_initial_heights(realizations) -> np.ndarray:
+    """Initial heights of a batch, grid after grid (each from its own seed)."""
+    return np.concatenate([initial_heights(r.ny, r.nx, r.seed).ravel() for r in realizations])
