@@ -62,9 +62,17 @@ typedef enum lem_status {
  *           sqrt(dx*dx + dy*dy) apart;
  *   dt      time step in years (> 0);
  *   m       exponent of the drainage area, m-hat (>= 0, finite);
- *   n       exponent of the slope, n-hat: must be exactly 1.0;
+ *   n       exponent of the slope, n-hat (> 0, finite).  For n = 1 the
+ *           erosion of Step 7 uses the closed form (h0 + F*h_r)/(1 + F),
+ *           the point the Newton-Raphson loop of Algorithm 6 reaches in one
+ *           iteration; otherwise that loop runs per cell;
  *   U       uplift rate u-hat in m/yr, used where no U field is given;
  *   K       erodibility in 1/yr (>= 0), used where no K field is given;
+ *   eps     Newton tolerance epsilon of Algorithm 6 in metres (> 0 when
+ *           n != 1; ignored for n = 1): the loop stops once two iterates
+ *           differ by at most eps, or once the iterate is no longer above
+ *           the receiver;
+ *   max_newton  iteration limit of that loop (>= 1 when n != 1);
  *   flags   LEM_F_* bits.                                                    */
 typedef struct lem_params {
   int32_t ny, nx;
@@ -73,6 +81,8 @@ typedef struct lem_params {
   double m;
   double n;
   double U, K;
+  double eps;
+  int32_t max_newton;
   uint32_t flags;
 } lem_params;
 
@@ -161,6 +171,10 @@ typedef struct lem_grid {
   double dt;           /* time step [yr] > 0                                       */
   double m;            /* area exponent >= 0                                       */
   double U, K;         /* uplift rate [m/yr], erodibility [1/yr] >= 0 (scalars)    */
+  double n;            /* slope exponent > 0; as in lem_params                     */
+  double eps;          /* Newton tolerance (n != 1); as in lem_params              */
+  int32_t max_newton;  /* Newton iteration limit (n != 1); as in lem_params        */
+  int32_t pad;         /* unused                                                   */
   int64_t offset;      /* index of the grid's first cell in the batch buffer; must
                           equal the sum of ny*nx of the grids before it           */
 } lem_grid;
@@ -177,8 +191,10 @@ lem_status lem_batch_create(const lem_grid* grids, int32_t count, uint32_t flags
 
 /* Enqueues `steps` time steps of every grid of the batch on d_h (the batch
  * buffer, updated in place); each grid evolves exactly as it would alone.
- * Per-cell K or U fields are not available for batches. */
-lem_status lem_batch_run(lem_ctx* ctx, double* d_h, int64_t steps);
+ * d_K and d_U are optional per-cell fields laid out like d_h (NULL: each
+ * grid's scalar K, U). */
+lem_status lem_batch_run(lem_ctx* ctx, double* d_h, const double* d_K, const double* d_U,
+                         int64_t steps);
 
 /* Steps every grid until its heights stop changing: after every
  * `check_every` steps a grid whose last step changed no cell by more than
@@ -186,7 +202,8 @@ lem_status lem_batch_run(lem_ctx* ctx, double* d_h, int64_t steps);
  * are frozen or after max_steps steps.  h_steps[count] receives, per grid,
  * the number of steps it took (-1 if it did not converge).  Synchronizes the
  * stream. */
-lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, double rtol, int64_t check_every,
+lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
+                                   const double* d_U, double rtol, int64_t check_every,
                                    int64_t max_steps, int64_t* h_steps);
 
 /* lem_routing for grid `grid` of the batch (after lem_batch_run); d_rec,

@@ -51,7 +51,7 @@ lem_status hip_fail(lem_ctx* ctx, hipError_t e, const char* what) {
 
 // Checks one grid's problem statement.
 lem_status check_grid(int32_t ny, int32_t nx, double dx, double dy, double dt, double m, double n,
-                      double U, double K, std::string* why) {
+                      double U, double K, double eps, int32_t max_newton, std::string* why) {
   if (ny < 3 || nx < 3) { *why = "ny and nx must be >= 3"; return LEM_E_SIZE; }
   if ((int64_t)ny * (int64_t)nx > (int64_t)INT32_MAX - 2) {
     *why = "ny*nx must be below 2^31-2";
@@ -63,7 +63,11 @@ lem_status check_grid(int32_t ny, int32_t nx, double dx, double dy, double dt, d
   }
   if (!(dt > 0.0) || !std::isfinite(dt)) { *why = "dt must be finite and > 0"; return LEM_E_ARG; }
   if (!(m >= 0.0) || !std::isfinite(m)) { *why = "m must be finite and >= 0"; return LEM_E_ARG; }
-  if (n != 1.0) { *why = "only the slope exponent n = 1 is supported"; return LEM_E_ARG; }
+  if (!(n > 0.0) || !std::isfinite(n)) { *why = "n must be finite and > 0"; return LEM_E_ARG; }
+  if (n != 1.0 && (!(eps > 0.0) || !std::isfinite(eps) || max_newton < 1)) {
+    *why = "n != 1 needs a finite eps > 0 and max_newton >= 1";
+    return LEM_E_ARG;
+  }
   if (!std::isfinite(U)) { *why = "U must be finite"; return LEM_E_ARG; }
   if (!(K >= 0.0) || !std::isfinite(K)) { *why = "K must be finite and >= 0"; return LEM_E_ARG; }
   return LEM_OK;
@@ -71,14 +75,16 @@ lem_status check_grid(int32_t ny, int32_t nx, double dx, double dy, double dt, d
 
 lem_status check_params(const lem_params* p, std::string* why) {
   if (!p) { *why = "params is NULL"; return LEM_E_ARG; }
-  lem_status st = check_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->n, p->U, p->K, why);
+  lem_status st = check_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->n, p->U, p->K, p->eps,
+                             p->max_newton, why);
   if (st != LEM_OK) return st;
   if (p->flags & ~(LEM_F_VALIDATE | LEM_F_PHASE_TIMERS)) { *why = "unknown flag bits"; return LEM_E_ARG; }
   return LEM_OK;
 }
 
 lem::GridDev make_grid(int32_t ny, int32_t nx, double dx, double dy, double dt, double m, double U,
-                       double K, int64_t offset, int32_t tile_base) {
+                       double K, double n, double eps, int32_t max_newton, int64_t offset,
+                       int32_t tile_base) {
   lem::GridDev g{};
   g.offset = offset;
   g.ny = ny;
@@ -98,6 +104,12 @@ lem::GridDev make_grid(int32_t ny, int32_t nx, double dx, double dy, double dt, 
   g.inv_dx = 1.0 / dx;
   g.inv_dy = 1.0 / dy;
   g.inv_dd = 1.0 / g.ddiag;
+  const double d[3] = {dy, dx, g.ddiag};
+  g.newton = (n != 1.0) ? 1 : 0;
+  for (int c = 0; c < 3; ++c) g.dn[c] = g.newton ? std::pow(d[c], n) : d[c];
+  g.nexp = n;
+  g.eps = eps;
+  g.max_newton = max_newton;
   return g;
 }
 
@@ -115,10 +127,12 @@ lem_status build_batch(const lem_grid* gs, int32_t count, std::vector<lem::GridD
   int64_t off = 0, tiles = 0;
   for (int32_t i = 0; i < count; ++i) {
     const lem_grid& g = gs[i];
-    lem_status st = check_grid(g.ny, g.nx, g.dx, g.dy, g.dt, g.m, 1.0, g.U, g.K, why);
+    lem_status st = check_grid(g.ny, g.nx, g.dx, g.dy, g.dt, g.m, g.n, g.U, g.K, g.eps,
+                               g.max_newton, why);
     if (st != LEM_OK) return st;
     if (g.offset != off) { *why = "grid offsets must follow the grids back to back"; return LEM_E_ARG; }
-    lem::GridDev d = make_grid(g.ny, g.nx, g.dx, g.dy, g.dt, g.m, g.U, g.K, off, (int32_t)tiles);
+    lem::GridDev d = make_grid(g.ny, g.nx, g.dx, g.dy, g.dt, g.m, g.U, g.K, g.n, g.eps,
+                               g.max_newton, off, (int32_t)tiles);
     tiles += grid_tiles(d);
     off += (int64_t)g.ny * g.nx;
     if (off > (int64_t)INT32_MAX - 2) { *why = "a batch holds fewer than 2^31-2 cells"; return LEM_E_SIZE; }
@@ -314,7 +328,8 @@ extern "C" {
 size_t lem_workspace_bytes(const lem_params* p) {
   std::string why;
   if (check_params(p, &why) != LEM_OK) return 0;
-  lem::GridDev g = make_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->U, p->K, 0, 0);
+  lem::GridDev g = make_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->U, p->K, p->n, p->eps,
+                               p->max_newton, 0, 0);
   return lem::workspace_bytes((int64_t)p->ny * p->nx, 1, grid_tiles(g));
 }
 
@@ -331,7 +346,8 @@ lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes, v
   if (!ctx) return LEM_E_ARG;
   ctx->flags = p->flags;
   ctx->batch = false;
-  ctx->grids.push_back(make_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->U, p->K, 0, 0));
+  ctx->grids.push_back(make_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->U, p->K, p->n, p->eps,
+                               p->max_newton, 0, 0));
   ctx->cells = (int64_t)p->ny * p->nx;
   ctx->ntiles = grid_tiles(ctx->grids[0]);
   st = create_impl(ctx, d_workspace, ws_bytes, hip_stream);
@@ -376,16 +392,16 @@ lem_status lem_batch_create(const lem_grid* grids, int32_t count, uint32_t flags
 
 lem_status lem_run(lem_ctx* ctx, double* d_h, const double* d_K, const double* d_U,
                    int64_t steps) {
-  if (ctx && ctx->batch && (d_K || d_U))
-    return fail(ctx, LEM_E_ARG, "per-cell K or U fields need a single-grid context");
   return run_impl(ctx, d_h, nullptr, d_K, d_U, steps);
 }
 
-lem_status lem_batch_run(lem_ctx* ctx, double* d_h, int64_t steps) {
-  return run_impl(ctx, d_h, nullptr, nullptr, nullptr, steps);
+lem_status lem_batch_run(lem_ctx* ctx, double* d_h, const double* d_K, const double* d_U,
+                         int64_t steps) {
+  return run_impl(ctx, d_h, nullptr, d_K, d_U, steps);
 }
 
-lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, double rtol, int64_t check_every,
+lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
+                                   const double* d_U, double rtol, int64_t check_every,
                                    int64_t max_steps, int64_t* h_steps) {
   if (!ctx) return LEM_E_ARG;
   if (!d_h || !h_steps) return fail(ctx, LEM_E_ARG, "d_h and h_steps must not be NULL");
@@ -394,12 +410,12 @@ lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, double rtol, int64
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (ctx->flags & LEM_F_VALIDATE) {
-    lem_status st = validate_inputs(ctx, d_h, nullptr, nullptr);
+    lem_status st = validate_inputs(ctx, d_h, d_K, d_U);
     if (st != LEM_OK) return st;
   }
   const int32_t ng = (int32_t)ctx->grids.size();
   for (int32_t g = 0; g < ng; ++g) h_steps[g] = -1;
-  lem::StepArgs a = make_args(ctx, nullptr, nullptr);
+  lem::StepArgs a = make_args(ctx, d_K, d_U);
   e = lem::launch_begin_run(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "begin-run launch");
   const bool timers = (ctx->flags & LEM_F_PHASE_TIMERS) != 0;

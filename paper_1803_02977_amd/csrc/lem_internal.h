@@ -72,7 +72,10 @@ struct GridDev {
   double dx, dy, ddiag, dxdy;
   double dt, m, K, udt;
   double inv_dx, inv_dy, inv_dd;
-  double pad;
+  double dn[3];            // dist^n for the classes (dy, dx, diagonal); = dist for n = 1
+  double nexp, eps;        // slope exponent n and the Newton tolerance (n != 1)
+  int32_t newton;          // n != 1: the Newton-Raphson loop of Algorithm 6
+  int32_t max_newton;      // iteration limit of that loop
 };
 
 // Pointers into the workspace.

@@ -199,13 +199,37 @@ __device__ __forceinline__ void erosion_factor(const StepArgs& a, const GridDev&
     *g = a.w.gtab[(gi * 3 + cls) * kAmTab + count];
     return;
   }
-  const double d = cls == 0 ? G.dy : (cls == 1 ? G.dx : G.ddiag);
+  const double d = G.dn[cls];
   const double am = count < (uint32_t)kAmTab
                         ? a.w.amtab[gi * kAmTab + count]
                         : area_power_call((double)count * G.dxdy, G.use_sqrt, G.m);
   const double kc = a.Kf ? a.Kf[c] : G.K;
   *f = ((kc * G.dt) * am) / d;
   *g = 1.0 + *f;
+}
+
+// Step 7 for one cell: the implicit update of h0 (uplift included) towards
+// its already updated receiver height hr.  For n = 1 the Newton iteration of
+// Algorithm 6 started at h0 reaches (h0 + F*hr)/(1 + F) in one step, so that
+// closed form is used; otherwise the loop runs until two iterates differ by
+// at most eps, the iteration limit is reached, or the iterate no longer lies
+// above the receiver.
+__device__ __noinline__ double newton_height(double h0, double hr, double f, double nexp,
+                                             double eps, int max_iter) {
+  double hnew = h0, hp = h0, delta = 2.0 * eps;
+  for (int it = 0; fabs(delta) > eps && it < max_iter; ++it) {
+    const double gap = hnew - hr;
+    if (!(gap > 0.0)) break;
+    hnew = hnew - (hnew - h0 + f * pow(gap, nexp)) / (1.0 + f * nexp * pow(gap, nexp - 1.0));
+    delta = hnew - hp;
+    hp = hnew;
+  }
+  return hnew;
+}
+
+__device__ __forceinline__ double eroded_height(const GridDev& G, double h0, double hr, double f,
+                                                double g) {
+  return G.newton ? newton_height(h0, hr, f, G.nexp, G.eps, G.max_newton) : (h0 + f * hr) / g;
 }
 
 // Grid of a tile: the last grid whose first tile is at or before it.
@@ -520,7 +544,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
       double f, g;
       erosion_factor(a, G, gi, count, code, c, &f, &g);
       const double h0 = hs[hidx] + up;
-      hs[hidx] = (h0 + f * hs[hidx + code_dy(code) * kHW + code_dx(code)]) / g;
+      hs[hidx] = eroded_height(G, h0, hs[hidx + code_dy(code) * kHW + code_dx(code)], f, g);
     }
     __syncthreads();
   }
@@ -686,7 +710,7 @@ __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32
     double f, g;
     erosion_factor(a, G, gi, w.cnt[i], w.kq[i], c, &f, &g);
     const double h0 = a.h_in[c] + (a.Uf ? a.Uf[c] * G.dt : G.udt);
-    const double hn = (h0 + f * hr) / g;
+    const double hn = eroded_height(G, h0, hr, f, g);
     w.hq[i] = hn;
     a.h_out[c] = hn;
   }
@@ -857,9 +881,8 @@ __global__ void k_begin_run(StepArgs a) {
   if (i < kAmTab) {
     const double am = area_power((double)i * G.dxdy, G.use_sqrt, G.m);
     a.w.amtab[gi * kAmTab + i] = am;
-    const double d[3] = {G.dy, G.dx, G.ddiag};
     for (int c = 0; c < 3; ++c) {
-      const double f = ((G.K * G.dt) * am) / d[c];
+      const double f = ((G.K * G.dt) * am) / G.dn[c];
       a.w.ftab[(gi * 3 + c) * kAmTab + i] = f;
       a.w.gtab[(gi * 3 + c) * kAmTab + i] = 1.0 + f;
     }

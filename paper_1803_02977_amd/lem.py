@@ -29,7 +29,8 @@ EXPORTS = ("lem_workspace_bytes", "lem_create", "lem_run", "lem_run_fixed_routin
 class lem_params(C.Structure):
     _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
                 ("dt", C.c_double), ("m", C.c_double), ("n", C.c_double), ("U", C.c_double),
-                ("K", C.c_double), ("flags", C.c_uint32)]
+                ("K", C.c_double), ("eps", C.c_double), ("max_newton", C.c_int32),
+                ("flags", C.c_uint32)]
 
 
 class lem_stats_t(C.Structure):
@@ -42,7 +43,8 @@ class lem_stats_t(C.Structure):
 class lem_grid(C.Structure):
     _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
                 ("dt", C.c_double), ("m", C.c_double), ("U", C.c_double), ("K", C.c_double),
-                ("offset", C.c_int64)]
+                ("n", C.c_double), ("eps", C.c_double), ("max_newton", C.c_int32),
+                ("pad", C.c_int32), ("offset", C.c_int64)]
 
 
 class lem_tuning(C.Structure):
@@ -89,9 +91,9 @@ def load(path: str = LIB_PATH):
     lib.lem_batch_create.argtypes = [C.POINTER(lem_grid), C.c_int32, C.c_uint32, _P, C.c_size_t,
                                      _P, C.POINTER(_P)]
     lib.lem_batch_create.restype = C.c_int
-    lib.lem_batch_run.argtypes = [_P, _P, C.c_int64]
+    lib.lem_batch_run.argtypes = [_P, _P, _P, _P, C.c_int64]
     lib.lem_batch_run.restype = C.c_int
-    lib.lem_batch_run_to_steady.argtypes = [_P, _P, C.c_double, C.c_int64, C.c_int64, _P]
+    lib.lem_batch_run_to_steady.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int64, C.c_int64, _P]
     lib.lem_batch_run_to_steady.restype = C.c_int
     lib.lem_batch_routing.argtypes = [_P, C.c_int32, _P, _P, _P, _P, C.c_int64,
                                       C.POINTER(C.c_int64)]
@@ -167,15 +169,15 @@ def lem_batch_create(grids, flags: int, d_workspace: int, ws_bytes: int, hip_str
     return ctx.value
 
 
-def lem_batch_run(ctx: int, d_h: int, steps: int) -> None:
-    _check(load().lem_batch_run(ctx, d_h, steps), ctx)
+def lem_batch_run(ctx: int, d_h: int, d_K, d_U, steps: int) -> None:
+    _check(load().lem_batch_run(ctx, d_h, d_K, d_U, steps), ctx)
 
 
-def lem_batch_run_to_steady(ctx: int, d_h: int, rtol: float, check_every: int, max_steps: int,
-                            count: int):
+def lem_batch_run_to_steady(ctx: int, d_h: int, d_K, d_U, rtol: float, check_every: int,
+                            max_steps: int, count: int):
     import numpy as np
     out = np.zeros(count, np.int64)
-    _check(load().lem_batch_run_to_steady(ctx, d_h, rtol, check_every, max_steps,
+    _check(load().lem_batch_run_to_steady(ctx, d_h, d_K, d_U, rtol, check_every, max_steps,
                                           out.ctypes.data_as(_P)), ctx)
     return out
 
@@ -252,11 +254,12 @@ class Solver:
     """
 
     def __init__(self, ny, nx, dx=100.0, dy=100.0, dt=1000.0, m=0.5, U=5e-4, K=1e-5,
-                 n=1.0, flags=0, device=None, stream=None, tuning="auto"):
+                 n=1.0, flags=0, device=None, stream=None, tuning="auto", eps=1e-12,
+                 max_newton=100):
         import torch
         self.torch = torch
         self.device = torch.device(device or "cuda")
-        self.params = lem_params(ny, nx, dx, dy, dt, m, n, U, K, flags)
+        self.params = lem_params(ny, nx, dx, dy, dt, m, n, U, K, eps, max_newton, flags)
         nbytes = lem_workspace_bytes(self.params)
         if nbytes == 0:
             raise LemError(LEM_E_ARG, "invalid parameters")
@@ -345,9 +348,14 @@ class Batch:
         self.device = torch.device(device or "cuda")
         descs, off = [], 0
         for g in grids:
-            get = (lambda k: g[k]) if isinstance(g, dict) else (lambda k: getattr(g, k))
+            def get(k, default=None, g=g):
+                if isinstance(g, dict):
+                    return g.get(k, default)
+                return getattr(g, k, default)
             d = lem_grid(int(get("ny")), int(get("nx")), float(get("dx")), float(get("dy")),
-                         float(get("dt")), float(get("m")), float(get("U")), float(get("K")), off)
+                         float(get("dt")), float(get("m")), float(get("U")), float(get("K")),
+                         float(get("n", 1.0)), float(get("eps", 1e-12)),
+                         int(get("max_newton", 100)), 0, off)
             descs.append(d)
             off += d.ny * d.nx
         self.descs = descs
@@ -376,14 +384,20 @@ class Batch:
         o = self.offsets[g]
         return h.view(-1)[o: o + ny * nx].view(ny, nx)
 
-    def run(self, h, steps):
+    def run(self, h, steps, K=None, U=None):
         self._check_h(h)
-        lem_batch_run(self.ctx, h.data_ptr(), int(steps))
+        for f in (K, U):
+            if f is not None:
+                self._check_h(f)
+        lem_batch_run(self.ctx, h.data_ptr(), _dptr(K), _dptr(U), int(steps))
 
-    def run_to_steady(self, h, rtol=1e-6, check_every=10, max_steps=100000):
+    def run_to_steady(self, h, rtol=1e-6, check_every=10, max_steps=100000, K=None, U=None):
         self._check_h(h)
-        return lem_batch_run_to_steady(self.ctx, h.data_ptr(), float(rtol), int(check_every),
-                                       int(max_steps), len(self.descs))
+        for f in (K, U):
+            if f is not None:
+                self._check_h(f)
+        return lem_batch_run_to_steady(self.ctx, h.data_ptr(), _dptr(K), _dptr(U), float(rtol),
+                                       int(check_every), int(max_steps), len(self.descs))
 
     def sync(self):
         lem_sync(self.ctx)

@@ -344,7 +344,51 @@ def pin_newton_matches_closed_form(lib):
     assert np.allclose(a, b, rtol=1e-12, atol=1e-12)
 
 
+def pin_newton_channel_profile(lib):
+    """Slope exponent n != 1 (Algorithm 6's Newton loop): at steady state
+    K A^m S^n = U, so a 1-D channel reaches h_i = sum_{j<=i} dx (U/(K A_j^m))^(1/n)."""
+    ny, nx = 3, 30
+    U, K, m, dx, dy = 5e-4, 1e-5, 0.5, 100.0, 100.0
+    rec = np.arange(ny * nx, dtype=np.int32).reshape(ny, nx)
+    for x in range(1, nx - 1):
+        rec[1, x] = nx + x - 1
+    for nexp in (2.0, 1.5, 0.8):
+        p = oracle.Params(ny, nx, dx, dy, 1e4, m, nexp, U, K, eps=1e-10)
+        h = _run_to_steady(lib, np.zeros((ny, nx)), p, rec=rec)
+        expect = np.cumsum([dx * (U / (K * ((nx - 1 - j) * dx * dy) ** m)) ** (1.0 / nexp)
+                            for j in range(1, nx - 1)])
+        assert np.allclose(h[1, 1:-1], expect, rtol=1e-9, atol=0), (nexp, np.abs(h[1, 1:-1] - expect).max())
+
+
+def pin_newton_step_solves_the_implicit_equation(lib):
+    """One step with n = 2: every non-root cell satisfies the backward-Euler
+    equation h'_c = h_c + U dt - K dt A^m ((h'_c - h'_r)/d)^n up to the
+    Newton tolerance, with h'_r the receiver's new height."""
+    ny, nx = 20, 26
+    h = W.initial_heights(ny, nx, 6) * 50.0
+    dx, dy, nexp, eps = 40.0, 70.0, 2.0, 1e-12
+    p = oracle.Params(ny, nx, dx, dy, 2000.0, 0.45, nexp, 1e-3, 3e-5, eps=eps)
+    rec = oracle.receivers(h, dx, dy, lib=lib)
+    out = oracle.run_fixed_routing(h, rec, p, 1, lib=lib)
+    hn, cnt = out["h"].ravel(), out["count"].ravel()
+    recf, h0 = rec.ravel(), h.ravel()
+    checked = 0
+    for c in range(h0.size):
+        r = recf[c]
+        if r == c:
+            continue
+        d = _dist(c, r, nx, dx, dy)
+        f = p.K * p.dt * (cnt[c] * dx * dy) ** p.m / d ** nexp
+        gap = hn[c] - hn[r]
+        assert gap > 0, (c, gap)
+        res = hn[c] - (h0[c] + p.U * p.dt) + f * gap ** nexp
+        assert abs(res) <= 10 * eps * (1 + f * nexp * gap ** (nexp - 1)) + 1e-13 * abs(hn[c]), (c, res)
+        checked += 1
+    assert checked > 0
+
+
 ALL_PINS = [pin_table1, pin_receivers_special_cases, pin_receivers_brute_force,
             pin_levels_and_areas_brute_force, pin_forest_invariants, pin_one_step_dense_solve,
             pin_no_erosion_is_pure_uplift, pin_long_step_follows_receiver,
-            pin_steady_state_slope_area, pin_channel_profile, pin_newton_matches_closed_form]
+            pin_steady_state_slope_area, pin_channel_profile, pin_newton_matches_closed_form,
+            pin_newton_channel_profile, pin_newton_step_solves_the_implicit_equation]

@@ -36,9 +36,16 @@ def test_library_exports_every_declared_symbol():
 
 def _params(**kw):
     base = dict(ny=256, nx=256, dx=100.0, dy=100.0, dt=1000.0, m=0.5, n=1.0, U=5e-4, K=1e-5,
-                flags=0)
+                eps=1e-12, max_newton=100, flags=0)
     base.update(kw)
     return lem.lem_params(**base)
+
+
+def test_slope_exponent_is_accepted_with_a_tolerance():
+    assert lem.lem_workspace_bytes(_params(n=2.0)) > 0
+    assert lem.lem_workspace_bytes(_params(n=0.7, eps=1e-9, max_newton=5)) > 0
+    # n = 1 ignores eps and max_newton (closed form).
+    assert lem.lem_workspace_bytes(_params(eps=0.0, max_newton=0)) > 0
 
 
 def test_workspace_bytes():
@@ -54,7 +61,9 @@ def test_workspace_bytes():
     (dict(ny=50000, nx=50000), lem.LEM_E_SIZE),
     (dict(dx=0.0), lem.LEM_E_ARG), (dict(dy=-1.0), lem.LEM_E_ARG),
     (dict(dt=float("nan")), lem.LEM_E_ARG), (dict(m=-0.1), lem.LEM_E_ARG),
-    (dict(n=2.0), lem.LEM_E_ARG), (dict(K=-1e-5), lem.LEM_E_ARG),
+    (dict(n=0.0), lem.LEM_E_ARG), (dict(n=float("nan")), lem.LEM_E_ARG),
+    (dict(n=2.0, eps=0.0), lem.LEM_E_ARG), (dict(n=2.0, max_newton=0), lem.LEM_E_ARG),
+    (dict(K=-1e-5), lem.LEM_E_ARG),
     (dict(U=float("inf")), lem.LEM_E_ARG), (dict(flags=0x80), lem.LEM_E_ARG),
 ])
 def test_bad_parameters_are_rejected_on_the_host(kw, status):

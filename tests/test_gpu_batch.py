@@ -127,5 +127,30 @@ def test_batch_of_one_and_argument_errors():
     with pytest.raises(LemError):
         b.run(torch.zeros(10, dtype=torch.float64, device="cuda:0"), 1)
     b.close()
-    bad = [lem.lem_grid(10, 10, 1.0, 1.0, 1.0, 0.5, 0.0, 0.0, 5)]
+    bad = [lem.lem_grid(10, 10, 1.0, 1.0, 1.0, 0.5, 0.0, 0.0, 1.0, 1e-12, 100, 0, 5)]
     assert lem.lem_batch_workspace_bytes(bad) == 0
+
+
+def test_batch_with_fields_equals_each_grid_alone():
+    """Per-cell K and U fields laid out like the batch heights."""
+    torch = require_gpu()
+    grids = _grids()[2:6]
+    h0 = W.batch_initial_heights(grids)
+    rng = np.random.default_rng(5)
+    K = 1e-5 * np.exp(0.5 * rng.standard_normal(h0.size))
+    U = rng.uniform(1e-4, 2e-3, h0.size)
+    b = _batch(torch, grids)
+    h = torch.from_numpy(h0).to("cuda:0")
+    b.run(h, 10, K=torch.from_numpy(K).to("cuda:0"), U=torch.from_numpy(U).to("cuda:0"))
+    b.sync()
+    from paper_1803_02977_amd import Solver
+    for g, r in enumerate(grids):
+        o, n = b.offsets[g], r.ny * r.nx
+        hs = torch.from_numpy(W.initial_heights(r.ny, r.nx, r.seed)).to("cuda:0")
+        s = Solver(r.ny, r.nx, r.dx, r.dy, r.dt, r.m, r.U, r.K, device=torch.device("cuda:0"))
+        s.run(hs, 10, K=torch.from_numpy(K[o:o + n].reshape(r.ny, r.nx)).to("cuda:0"),
+              U=torch.from_numpy(U[o:o + n].reshape(r.ny, r.nx)).to("cuda:0"))
+        s.sync()
+        s.close()
+        assert np.array_equal(b.view(h, g).cpu().numpy(), hs.cpu().numpy()), g
+    b.close()

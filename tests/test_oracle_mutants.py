@@ -39,6 +39,11 @@ MUTANTS = [
      "if (h[c] > 0.5) h[c] = h[c] + (Ufield ? Ufield[c] * dt : udt);"),
     ("K field ignored", "const double kc = Kfield ? Kfield[c] : K;\n    const double f = ((kc",
      "const double kc = K;\n    const double f = ((kc"),
+    ("Newton divides by d, not d^n", "pow(area, m)) / pow(d, nexp);", "pow(area, m)) / d;"),
+    ("Newton residual with the wrong sign", "(hnew - h0 + f * pow(g, nexp))",
+     "(hnew - h0 - f * pow(g, nexp))"),
+    ("Newton stops after one iteration", "fabs(delta) > eps && it < max_iter",
+     "fabs(delta) > eps && it < 1"),
 ]
 
 
