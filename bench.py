@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=W.LARGE_10000.name,
-                    choices=sorted(W.WORKLOADS) + [BATCH_NAME])
+                    choices=sorted(W.WORKLOADS) + [BATCH_NAME, SWEEP_NAME])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=None)
@@ -61,6 +61,14 @@ def parse():
 
 
 BATCH_NAME = "batch-512-realizations-fp64"
+SWEEP_NAME = "size-sweep-100-16000"
+# Square edge lengths of the size sweep; the regions (upper edge length)
+# follow the GPU scaling table of the paper (section on GPU performance),
+# whose wall-time exponents x (wall ~ N^x) are quoted beside the fit.
+SWEEP_EDGES = (100, 141, 200, 283, 400, 500, 632, 800, 1000, 1250, 1581, 2000, 2500, 3536,
+               5000, 7071, 10000, 12649, 16000)
+SWEEP_REGIONS = (("A", 100, 400, 0.33), ("B", 400, 1000, 0.16), ("C", 1000, 2500, 0.42),
+                 ("D", 2500, 16000, 0.92))
 
 
 def bench_batch(args):
@@ -143,6 +151,62 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args):
+    """Wall time per step against grid size: seeded Uniform[0,1) square
+    rasters (100 m cells, U = 5e-4, K = 1e-5, m = 0.5, dt = 1000 yr), the
+    same number of steps at every size, and a least-squares fit of
+    log(ms per step) against log(cells) in each region."""
+    import torch
+
+    from paper_1803_02977_amd import Solver
+    dev = torch.device("cuda:0")
+    steps = args.steps or 50
+    rows = []
+    for e in SWEEP_EDGES:
+        h0 = torch.from_numpy(W.initial_heights(e, e, args.seed)).to(dev)
+        h = h0.clone()
+        s = Solver(e, e, 100.0, 100.0, 1000.0, 0.5, 5e-4, 1e-5, device=dev)
+        if args.warmup > 0:
+            s.run(h, args.warmup)
+            s.sync()
+        best = None
+        for _ in range(max(3, args.repeats)):
+            h.copy_(h0)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(s.stream)
+            s.run(h, steps)
+            ev1.record(s.stream)
+            s.sync()
+            ms = ev0.elapsed_time(ev1) / steps
+            best = ms if best is None else min(best, ms)
+        st = s.stats()
+        rows.append(dict(edge=e, cells=e * e, ms_per_step=round(best, 5),
+                         cell_updates_per_s=e * e / (best * 1e-3),
+                         max_levels=int(st.max_nlevels)))
+        print(f"[sweep] {e}x{e}: {best:.4f} ms/step, {e * e / (best * 1e-3):.3e} cell-updates/s",
+              file=sys.stderr, flush=True)
+        s.close()
+        del h, h0
+        torch.cuda.empty_cache()
+    fits = []
+    for name, lo, hi, paper_x in SWEEP_REGIONS:
+        pts = [(np.log(r["cells"]), np.log(r["ms_per_step"])) for r in rows if lo <= r["edge"] <= hi]
+        x = float(np.polyfit([p[0] for p in pts], [p[1] for p in pts], 1)[0]) if len(pts) >= 2 else None
+        fits.append(dict(region=name, edge_lo=lo, edge_hi=hi, x=None if x is None else round(x, 3),
+                         paper_x=paper_x, points=len(pts)))
+    big = rows[-1]
+    print(json.dumps({
+        "metric": "cell-updates/s", "value": big["cell_updates_per_s"], "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": big["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": SWEEP_NAME, "edges": list(SWEEP_EDGES), "dx": 100.0, "dt": 1000.0,
+                   "m": 0.5, "U": 5e-4, "K": 1e-5, "seed": args.seed},
+        "sweep": rows, "fit": fits, "roofline": None, "cpu_baseline": None}), flush=True)
+
+
 def cpu_baseline(w, h0, K, steps):
     """The serial oracle (one host thread) on ``steps`` steps of the workload."""
     import oracle
@@ -163,6 +227,9 @@ def main():
         sys.exit(2)
     if args.workload == BATCH_NAME:
         bench_batch(args)
+        return
+    if args.workload == SWEEP_NAME:
+        bench_sweep(args)
         return
     import torch
 

@@ -199,9 +199,11 @@ lem_status lem_batch_run(lem_ctx* ctx, double* d_h, const double* d_K, const dou
 /* Steps every grid until its heights stop changing: after every
  * `check_every` steps a grid whose last step changed no cell by more than
  * rtol * max|h| is frozen (it is no longer stepped).  Stops when all grids
- * are frozen or after max_steps steps.  h_steps[count] receives, per grid,
- * the number of steps it took (-1 if it did not converge).  Synchronizes the
- * stream. */
+ * are frozen or after max_steps steps.  h_steps[count] is read and written:
+ * a grid with h_steps[g] >= 0 on entry counts as steady already (it is not
+ * stepped and its entry is kept), which lets a long run continue over
+ * several calls; every other grid receives the number of steps this call
+ * took it to converge, or -1.  Synchronizes the stream. */
 lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
                                    const double* d_U, double rtol, int64_t check_every,
                                    int64_t max_steps, int64_t* h_steps);

@@ -414,19 +414,43 @@ lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
     if (st != LEM_OK) return st;
   }
   const int32_t ng = (int32_t)ctx->grids.size();
-  for (int32_t g = 0; g < ng; ++g) h_steps[g] = -1;
+  std::vector<char> done(ng, 0);
+  int64_t active_cells = ctx->cells;
+  for (int32_t g = 0; g < ng; ++g) {
+    if (h_steps[g] >= 0) {  // steady on entry: not stepped, entry kept
+      done[g] = 1;
+      active_cells -= (int64_t)ctx->grids[g].ny * ctx->grids[g].nx;
+    } else {
+      h_steps[g] = -1;
+    }
+  }
   lem::StepArgs a = make_args(ctx, d_K, d_U);
   e = lem::launch_begin_run(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "begin-run launch");
   const bool timers = (ctx->flags & LEM_F_PHASE_TIMERS) != 0;
   ctx->route_ms = ctx->order_ms = 0.0;
-  std::vector<char> done(ng, 0);
   std::vector<double> conv(2 * (size_t)ng);
-  int64_t active_cells = ctx->cells;
   int64_t s = 0;
   double* cur = d_h;  // buffer holding the latest heights
   double* other = ctx->w.h2;
   lem_status st = LEM_OK;
+  if (active_cells < ctx->cells) {
+    // Both buffers hold the heights of the grids that are already steady.
+    e = hipMemcpyAsync(other, d_h, sizeof(double) * (size_t)ctx->cells, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "initial copy");
+    ctx->active.clear();
+    for (int32_t g = 0; g < ng; ++g) {
+      if (done[g]) continue;
+      const lem::GridDev& G = ctx->grids[g];
+      for (int32_t t = 0; t < grid_tiles(G); ++t) ctx->active.push_back(G.tile_base + t);
+    }
+    if (active_cells > 0) {
+      st = upload_tiles(ctx, ctx->active);
+      a.ntiles = (int32_t)ctx->active.size();
+      a.n = (int32_t)active_cells;
+    }
+  }
   while (s < max_steps && active_cells > 0 && st == LEM_OK) {
     const int64_t k = (max_steps - s) < check_every ? (max_steps - s) : check_every;
     for (int64_t j = 0; j < k; ++j, ++s) {

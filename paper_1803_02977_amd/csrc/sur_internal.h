@@ -1,0 +1,78 @@
+// sur_internal.h -- launch interface of the warm-start network kernels
+// (sur_kernels.hip), used by the C ABI in sur_capi.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sur {
+
+// Reference scales of the features and of the output (heights in metres).
+constexpr double kKRef = 1e-5;
+constexpr double kURef = 1e-3;
+constexpr double kHRef = 100.0;
+constexpr double kLnKSigma = 0.5;
+constexpr int kInChannels = 32;   // three features, zero-padded
+constexpr int kHeadChannels = 32;
+
+// 3x3 convolution (zero padding 1) as an implicit GEMM on MFMA:
+// out[p, co] = bias[co] + sum_{tap, ci} x[p + tap offset, ci] * w[co, tap, ci],
+// optionally followed by ReLU.  x is bfloat16 NHWC with Cin channels
+// (a multiple of 32), w bfloat16 [Cout][9][Cin], out bfloat16 or float32
+// NHWC with Cout channels (a multiple of 32).
+struct ConvArgs {
+  const uint16_t* x;
+  const uint16_t* w;
+  const float* bias;   // may be null
+  uint16_t* outb;      // bfloat16 output (out_f32 == 0)
+  float* outf;         // float32 output (out_f32 == 1)
+  int B, H, W, Cin, Cout;
+  int relu, out_f32;
+};
+
+// Weight gradient partials: part[s][co][tap][ci] = sum over the pixels of
+// split s of dz[p, co] * x[p + tap offset, ci].
+struct WgradArgs {
+  const uint16_t* x;   // bfloat16 NHWC, Cin channels
+  const uint16_t* dz;  // bfloat16 NHWC, Cout channels
+  float* part;
+  int B, H, W, Cin, Cout, splits;
+};
+
+hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s);
+int wgrad_blocks_per_split(int Cin, int Cout);
+int wgrad_patches(int B, int H, int W);
+
+hipError_t launch_reduce_splits(const float* part, int splits, int64_t n, float* out,
+                                hipStream_t s);
+hipError_t launch_to_bf16(const float* p, uint16_t* pb, int64_t n, hipStream_t s);
+hipError_t launch_dgrad_weights(const uint16_t* w, uint16_t* wd, int Cin, int Cout,
+                                hipStream_t s);
+hipError_t launch_features(const double* K, const double* U, const double* h0, uint16_t* x0,
+                           int64_t P, hipStream_t s);
+hipError_t launch_pool(const uint16_t* x, uint16_t* out, int B, int Ho, int Wo, int C,
+                       hipStream_t s);
+hipError_t launch_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out, int B, int H,
+                        int W, int Cu, int Cs, hipStream_t s);
+hipError_t launch_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat,
+                         hipStream_t s);
+hipError_t launch_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
+                               float* out, int B, int H, int W, int C, hipStream_t s);
+hipError_t launch_relu_bwd(float* g, const uint16_t* y, uint16_t* dz, int64_t n, hipStream_t s);
+hipError_t launch_colsum(const float* g, int64_t P, int C, float* part, int splits,
+                         hipStream_t s);
+hipError_t launch_head(const uint16_t* d0, const uint16_t* wb, const float* bias, float* y,
+                       int64_t P, hipStream_t s);
+hipError_t launch_loss(const float* y, const double* target, const double* U, int B, int H,
+                       int W, float* dy, double* part, int nblk, hipStream_t s);
+hipError_t launch_reduce_f64(const double* part, int n, double scale, double* out,
+                             hipStream_t s);
+hipError_t launch_head_bwd(const float* dy, const uint16_t* d0, const uint16_t* wb, float* g,
+                           float* part, int nblk, int64_t P, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, int64_t n,
+                       float lr, float c1, float c2, hipStream_t s);
+hipError_t launch_heights(const float* y, const double* U, double* h, int B, int H, int W,
+                          hipStream_t s);
+
+}  // namespace sur

@@ -1,0 +1,593 @@
+// sur_kernels.hip -- kernels of the warm-start network (lem_surrogate.h) for
+// gfx950.  Convolutions are implicit GEMMs on the bfloat16 matrix cores
+// (v_mfma_f32_16x16x32_bf16: 16x16 tiles, K = 32, float32 accumulation);
+// everything else is elementwise or a reduction over pixels with a fixed
+// summation order, so results do not depend on the schedule.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sur_internal.h"
+
+namespace sur {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float32 -> bfloat16, round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// FP64 -> bfloat16 with one rounding: keep 8 significant bits, ties to even.
+__device__ __forceinline__ uint16_t d2bf(double v) {
+  int e;
+  const double m = frexp(v, &e);
+  return f2bf((float)ldexp(rint(m * 256.0) / 256.0, e));
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution.  A workgroup (4 waves) computes a 16x16-pixel tile for
+// COB output channels.  Per chunk of 32 input channels it stages the tile's
+// 18x18 input halo and the COB x 9 x 32 weights in LDS; for each of the nine
+// taps every wave multiplies weights (A: 16 output channels x 32 input
+// channels) by shifted input pixels (B: 32 input channels x 16 pixels of one
+// tile row).  Wave w owns tile rows 4w..4w+3.  The accumulator of a tile
+// holds 4 consecutive output channels of one pixel per lane, stored as one
+// 8-byte (bfloat16) or 16-byte (float32) write.
+constexpr int kT = 16;
+constexpr int kHalo = kT + 2;
+constexpr int kKC = 32;
+constexpr int kXP = 40;   // LDS pitch of one pixel's 32 channels (bank spread)
+constexpr int kWP = 40;   // LDS pitch of one (output channel, tap) row
+
+template <int COB>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t xs[kHalo * kHalo * kXP];
+  __shared__ __attribute__((aligned(16))) uint16_t ws[COB * 9 * kWP];
+  constexpr int MB = COB / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_x = (a.W + kT - 1) / kT, tiles_y = (a.H + kT - 1) / kT;
+  int t = blockIdx.x;
+  const int tx = t % tiles_x;
+  t /= tiles_x;
+  const int ty = t % tiles_y;
+  const int b = t / tiles_y;
+  const int co0 = blockIdx.y * COB;
+  const int y0 = ty * kT, x0 = tx * kT;
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+
+  f32x4 acc[MB][4];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int ci0 = 0; ci0 < a.Cin; ci0 += kKC) {
+    __syncthreads();
+    for (int i = tid; i < kHalo * kHalo * 4; i += 256) {
+      const int pix = i >> 2, part = i & 3;
+      const int gy = y0 + pix / kHalo - 1, gx = x0 + pix % kHalo - 1;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+        v = *reinterpret_cast<const uint4*>(
+            a.x + (((int64_t)b * a.H + gy) * a.W + gx) * a.Cin + ci0 + part * 8);
+      *reinterpret_cast<uint4*>(xs + pix * kXP + part * 8) = v;
+    }
+    for (int i = tid; i < COB * 9 * 4; i += 256) {
+      const int row = i >> 2, part = i & 3;  // row = co * 9 + tap
+      const uint4 v = *reinterpret_cast<const uint4*>(
+          a.w + ((int64_t)co0 * 9 + row) * a.Cin + ci0 + part * 8);
+      *reinterpret_cast<uint4*>(ws + row * kWP + part * 8) = v;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
+      bf16x8 av[MB], bv[4];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        av[mb] = *reinterpret_cast<const bf16x8*>(ws + ((mb * 16 + lr) * 9 + tap) * kWP + lk);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int py = wave * 4 + nb;
+        bv[nb] = *reinterpret_cast<const bf16x8*>(xs + ((py + ky) * kHalo + lr + kx) * kXP + lk);
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mfma(av[mb], bv[nb], acc[mb][nb]);
+    }
+  }
+
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int py = y0 + wave * 4 + nb, px = x0 + lr;
+    if (py >= a.H || px >= a.W) continue;
+    const int64_t p = ((int64_t)b * a.H + py) * a.W + px;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int co = co0 + mb * 16 + (lane >> 4) * 4;
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[j] = acc[mb][nb][j] + (a.bias ? a.bias[co + j] : 0.f);
+        if (a.relu) v[j] = fmaxf(v[j], 0.f);
+      }
+      if (a.out_f32) {
+        *reinterpret_cast<float4*>(a.outf + p * a.Cout + co) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        uint2 pk;
+        pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+        pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+        *reinterpret_cast<uint2*>(a.outb + p * a.Cout + co) = pk;
+      }
+    }
+  }
+}
+
+hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
+  if (a.Cin % 32 != 0 || a.Cout % 32 != 0 || a.B < 1 || a.H < 1 || a.W < 1)
+    return hipErrorInvalidValue;
+  const int tiles = a.B * ((a.H + kT - 1) / kT) * ((a.W + kT - 1) / kT);
+  if (a.Cout % 64 == 0)
+    hipLaunchKernelGGL(k_conv3x3<64>, dim3(tiles, a.Cout / 64), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_conv3x3<32>, dim3(tiles, a.Cout / 32), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of a 3x3 convolution for one tap per workgroup:
+// dW[co, tap, ci] = sum_p dz[p, co] * x[p + tap offset, ci], a GEMM with
+// M = output channels, N = input channels and K = pixels.  A workgroup owns
+// (tap, COB output channels, 32 input channels, split s) and loops over the
+// 16x16-pixel patches s, s + splits, ...; per patch it stages dz and the
+// tap-shifted x transposed (channel-major, pixels contiguous) in LDS and
+// runs eight K = 32 steps.  Results go to per-split partials, summed later
+// in split order.
+constexpr int kPP = 264;  // LDS pitch of one channel's 256 pixels
+
+int wgrad_blocks_per_split(int Cin, int Cout) {
+  const int cob = (Cout % 64 == 0) ? 64 : 32;
+  return 9 * (Cout / cob) * (Cin / 32);
+}
+
+int wgrad_patches(int B, int H, int W) {
+  return B * ((H + kT - 1) / kT) * ((W + kT - 1) / kT);
+}
+
+template <int COB>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t dzt[COB * kPP];
+  __shared__ __attribute__((aligned(16))) uint16_t xt[32 * kPP];
+  constexpr int NT = COB == 64 ? 2 : 1;  // tiles per wave
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+  int bid = blockIdx.x;
+  const int s = bid % a.splits;
+  bid /= a.splits;
+  const int ncit = a.Cin / 32;
+  const int cit = bid % ncit;
+  bid /= ncit;
+  const int ncot = a.Cout / COB;
+  const int cot = bid % ncot;
+  const int tap = bid / ncot;
+  const int ky = tap / 3 - 1, kx = tap % 3 - 1;
+  const int ci0 = cit * 32, co0 = cot * COB;
+  const int tiles_x = (a.W + kT - 1) / kT, tiles_y = (a.H + kT - 1) / kT;
+  const int npatch = a.B * tiles_x * tiles_y;
+  const int mb = COB == 64 ? wave : (wave >> 1);
+  const int nb0 = COB == 64 ? 0 : (wave & 1);
+
+  f32x4 acc[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int pt = s; pt < npatch; pt += a.splits) {
+    const int tx = pt % tiles_x, ty = (pt / tiles_x) % tiles_y, b = pt / (tiles_x * tiles_y);
+    const int y0 = ty * kT, x0 = tx * kT;
+    __syncthreads();
+    for (int i = tid; i < 256 * (COB / 8); i += 256) {
+      const int px = i / (COB / 8), part = i % (COB / 8);
+      const int gy = y0 + px / kT, gx = x0 + px % kT;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (gy < a.H && gx < a.W)
+        v = *reinterpret_cast<const uint4*>(
+            a.dz + (((int64_t)b * a.H + gy) * a.W + gx) * a.Cout + co0 + part * 8);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        dzt[(part * 8 + j) * kPP + px] = (uint16_t)(w4[j >> 1] >> ((j & 1) * 16));
+    }
+    for (int i = tid; i < 256 * 4; i += 256) {
+      const int px = i >> 2, part = i & 3;
+      const int oy = y0 + px / kT, ox = x0 + px % kT;
+      const int gy = oy + ky, gx = ox + kx;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (oy < a.H && ox < a.W && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+        v = *reinterpret_cast<const uint4*>(
+            a.x + (((int64_t)b * a.H + gy) * a.W + gx) * a.Cin + ci0 + part * 8);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        xt[(part * 8 + j) * kPP + px] = (uint16_t)(w4[j >> 1] >> ((j & 1) * 16));
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k0 = 0; k0 < 256; k0 += 32) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(dzt + (mb * 16 + lr) * kPP + k0 + lk);
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        const bf16x8 bv =
+            *reinterpret_cast<const bf16x8*>(xt + ((nb0 + i) * 16 + lr) * kPP + k0 + lk);
+        acc[i] = mfma(av, bv, acc[i]);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int ci = ci0 + (nb0 + i) * 16 + lr;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = co0 + mb * 16 + (lane >> 4) * 4 + j;
+      a.part[(((int64_t)s * a.Cout + co) * 9 + tap) * a.Cin + ci] = acc[i][j];
+    }
+  }
+}
+
+hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
+  if (a.Cin % 32 != 0 || a.Cout % 32 != 0 || a.splits < 1) return hipErrorInvalidValue;
+  const int blocks = wgrad_blocks_per_split(a.Cin, a.Cout) * a.splits;
+  if (a.Cout % 64 == 0)
+    hipLaunchKernelGGL(k_wgrad<64>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_wgrad<32>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reductions and elementwise kernels.
+
+// out[i] = sum over s = 0..splits-1, in that order, of part[s * n + i].
+__global__ void k_reduce_splits(const float* part, int splits, int64_t n, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.f;
+  for (int s = 0; s < splits; ++s) acc += part[(int64_t)s * n + i];
+  out[i] = acc;
+}
+
+hipError_t launch_reduce_splits(const float* part, int splits, int64_t n, float* out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                     splits, n, out);
+  return hipGetLastError();
+}
+
+__global__ void k_to_bf16(const float* p, uint16_t* pb, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    pb[i] = f2bf(p[i]);
+}
+
+hipError_t launch_to_bf16(const float* p, uint16_t* pb, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(2048), dim3(256), 0, s, p, pb, n);
+  return hipGetLastError();
+}
+
+// wd[ci][t][co] = w[co][8 - t][ci]: the input gradient of a 3x3 convolution
+// is the convolution of the output gradient with the spatially flipped,
+// channel-transposed kernel.
+__global__ void k_dgrad_weights(const uint16_t* w, uint16_t* wd, int Cin, int Cout) {
+  const int64_t n = (int64_t)Cin * 9 * Cout;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int co = (int)(i % Cout);
+    const int t = (int)((i / Cout) % 9);
+    const int ci = (int)(i / ((int64_t)Cout * 9));
+    wd[i] = w[((int64_t)co * 9 + (8 - t)) * Cin + ci];
+  }
+}
+
+hipError_t launch_dgrad_weights(const uint16_t* w, uint16_t* wd, int Cin, int Cout,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_dgrad_weights, dim3(512), dim3(256), 0, s, w, wd, Cin, Cout);
+  return hipGetLastError();
+}
+
+// Input features: (ln K - ln K_ref)/sigma, U/U_ref, h0, then zeros.
+__global__ void k_features(const double* K, const double* U, const double* h0, uint16_t* x0,
+                           int64_t P) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const double f0 = (log(K[p]) - log(kKRef)) / kLnKSigma;
+  const double f1 = U[p] / kURef;
+  const double f2 = h0[p];
+  uint4* dst = reinterpret_cast<uint4*>(x0 + p * kInChannels);
+  dst[0] = make_uint4((uint32_t)d2bf(f0) | ((uint32_t)d2bf(f1) << 16), (uint32_t)d2bf(f2), 0u, 0u);
+  dst[1] = make_uint4(0u, 0u, 0u, 0u);
+  dst[2] = make_uint4(0u, 0u, 0u, 0u);
+  dst[3] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_features(const double* K, const double* U, const double* h0, uint16_t* x0,
+                           int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, K, U, h0,
+                     x0, P);
+  return hipGetLastError();
+}
+
+// 2x2 average pool of bfloat16 maps (C channels; Ho x Wo output).
+__global__ void k_pool(const uint16_t* x, uint16_t* out, int B, int Ho, int Wo, int C) {
+  const int64_t n = (int64_t)B * Ho * Wo * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t q = i / C;
+    const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), b = (int)(q / ((int64_t)Wo * Ho));
+    const int W = 2 * Wo;
+    const int64_t r0 = ((int64_t)b * 2 * Ho + 2 * yo) * W + 2 * xo, r1 = r0 + W;
+    const float s = ((bf2f(x[r0 * C + c]) + bf2f(x[(r0 + 1) * C + c])) + bf2f(x[r1 * C + c])) +
+                    bf2f(x[(r1 + 1) * C + c]);
+    out[i] = f2bf(s * 0.25f);
+  }
+}
+
+hipError_t launch_pool(const uint16_t* x, uint16_t* out, int B, int Ho, int Wo, int C,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_pool, dim3(2048), dim3(256), 0, s, x, out, B, Ho, Wo, C);
+  return hipGetLastError();
+}
+
+// out = [nearest 2x upsample of low (Cu channels), skip (Cs channels)],
+// moved in 8-channel (16-byte) pieces.
+__global__ void k_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out, int B, int H,
+                        int W, int Cu, int Cs) {
+  const int C = Cu + Cs, pieces = C / 8;
+  const int64_t n = (int64_t)B * H * W * pieces;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % pieces) * 8;
+    const int64_t p = i / pieces;
+    uint4 v;
+    if (c < Cu) {
+      const int x = (int)(p % W), y = (int)((p / W) % H), b = (int)(p / ((int64_t)W * H));
+      const int64_t q = ((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2;
+      v = *reinterpret_cast<const uint4*>(low + q * Cu + c);
+    } else {
+      v = *reinterpret_cast<const uint4*>(skip + p * Cs + (c - Cu));
+    }
+    *reinterpret_cast<uint4*>(out + p * C + c) = v;
+  }
+}
+
+hipError_t launch_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out, int B, int H,
+                        int W, int Cu, int Cs, hipStream_t s) {
+  hipLaunchKernelGGL(k_upcat, dim3(2048), dim3(256), 0, s, low, skip, out, B, H, W, Cu, Cs);
+  return hipGetLastError();
+}
+
+// Gradient of the upsampled part of a concatenation: glow (H/2 x W/2, Cu
+// channels) = sum of the 2x2 block of gcat[..., 0:Cu] (H x W, Ccat channels).
+__global__ void k_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat) {
+  const int Ho = H / 2, Wo = W / 2;
+  const int64_t n = (int64_t)B * Ho * Wo * Cu;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % Cu);
+    const int64_t q = i / Cu;
+    const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), b = (int)(q / ((int64_t)Wo * Ho));
+    const int64_t r0 = ((int64_t)b * H + 2 * yo) * W + 2 * xo, r1 = r0 + W;
+    glow[i] = ((gcat[r0 * Ccat + c] + gcat[(r0 + 1) * Ccat + c]) + gcat[r1 * Ccat + c]) +
+              gcat[(r1 + 1) * Ccat + c];
+  }
+}
+
+hipError_t launch_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_up_bwd, dim3(2048), dim3(256), 0, s, gcat, glow, B, H, W, Cu, Ccat);
+  return hipGetLastError();
+}
+
+// Gradient of an encoder output: its skip part gcat[..., Cu:Cu+C] plus the
+// pooled path's gradient spread over each 2x2 block (a quarter each).
+__global__ void k_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
+                               float* out, int B, int H, int W, int C) {
+  const int64_t n = (int64_t)B * H * W * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t p = i / C;
+    const int x = (int)(p % W), y = (int)((p / W) % H), b = (int)(p / ((int64_t)W * H));
+    const int64_t q = ((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2;
+    out[i] = gcat[p * Ccat + Cu + c] + 0.25f * gsmall[q * C + c];
+  }
+}
+
+hipError_t launch_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
+                               float* out, int B, int H, int W, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_bwd_add, dim3(2048), dim3(256), 0, s, gcat, Cu, Ccat, gsmall, out, B,
+                     H, W, C);
+  return hipGetLastError();
+}
+
+// ReLU backward: g <- g where the stored output y > 0, else 0; dz = bf16(g).
+__global__ void k_relu_bwd(float* g, const uint16_t* y, uint16_t* dz, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = bf2f(y[i]) > 0.f ? g[i] : 0.f;
+    g[i] = v;
+    dz[i] = f2bf(v);
+  }
+}
+
+hipError_t launch_relu_bwd(float* g, const uint16_t* y, uint16_t* dz, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_relu_bwd, dim3(4096), dim3(256), 0, s, g, y, dz, n);
+  return hipGetLastError();
+}
+
+// Per-channel sums over pixels: split s sums pixels [s P/splits, (s+1) P/splits).
+__global__ void k_colsum(const float* g, int64_t P, int C, float* part, int splits) {
+  const int s = blockIdx.x;
+  const int64_t p0 = P * s / splits, p1 = P * (s + 1) / splits;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    float acc = 0.f;
+    for (int64_t p = p0; p < p1; ++p) acc += g[p * C + c];
+    part[(int64_t)s * C + c] = acc;
+  }
+}
+
+hipError_t launch_colsum(const float* g, int64_t P, int C, float* part, int splits,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum, dim3(splits), dim3(256), 0, s, g, P, C, part, splits);
+  return hipGetLastError();
+}
+
+// Head: y[p] = (sum_c w[c] d0[p, c]) + bias.
+__global__ void k_head(const uint16_t* d0, const uint16_t* wb, const float* bias, float* y,
+                       int64_t P) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  float acc = 0.f;
+#pragma unroll
+  for (int c = 0; c < kHeadChannels; ++c) acc += bf2f(wb[c]) * bf2f(d0[p * kHeadChannels + c]);
+  y[p] = acc + bias[0];
+}
+
+hipError_t launch_head(const uint16_t* d0, const uint16_t* wb, const float* bias, float* y,
+                       int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_head, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, d0, wb, bias, y,
+                     P);
+  return hipGetLastError();
+}
+
+// Loss: over interior cells, diff = y - h/((U/U_ref) H_ref); dy = 2 diff / N
+// and per-block partial sums of diff^2 (FP64).
+__global__ __launch_bounds__(256) void k_loss(const float* y, const double* target,
+                                              const double* U, int B, int H, int W, float* dy,
+                                              double* part) {
+  __shared__ double red[256];
+  const int64_t P = (int64_t)B * H * W;
+  const double n = (double)B * (H - 2) * (W - 2);
+  double acc = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(p % W), yy = (int)((p / W) % H);
+    double diff = 0.0;
+    if (x > 0 && x < W - 1 && yy > 0 && yy < H - 1)
+      diff = (double)y[p] - target[p] / ((U[p] / kURef) * kHRef);
+    dy[p] = (float)(2.0 * diff / n);
+    acc += diff * diff;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+hipError_t launch_loss(const float* y, const double* target, const double* U, int B, int H,
+                       int W, float* dy, double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, s, y, target, U, B, H, W, dy, part);
+  return hipGetLastError();
+}
+
+__global__ void k_reduce_f64(const double* part, int n, double scale, double* out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += part[i];
+  out[0] = acc * scale;
+}
+
+hipError_t launch_reduce_f64(const double* part, int n, double scale, double* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(64), 0, s, part, n, scale, out);
+  return hipGetLastError();
+}
+
+// Head backward: g[p, c] = dy[p] w[c]; per-block partials of
+// dw[c] = sum_p dy[p] d0[p, c] (part[blk][c]) and db = sum_p dy[p] (part[blk][32]).
+__global__ __launch_bounds__(256) void k_head_bwd(const float* dy, const uint16_t* d0,
+                                                  const uint16_t* wb, float* g, float* part,
+                                                  int nblk, int64_t P) {
+  __shared__ float red[8][kHeadChannels + 1];
+  const int c = threadIdx.x & 31, r = threadIdx.x >> 5;
+  const int64_t p0 = P * blockIdx.x / nblk, p1 = P * (blockIdx.x + 1) / nblk;
+  const float w = bf2f(wb[c]);
+  float acc = 0.f, accb = 0.f;
+  for (int64_t p = p0 + r; p < p1; p += 8) {
+    const float d = dy[p];
+    g[p * kHeadChannels + c] = d * w;
+    acc += d * bf2f(d0[p * kHeadChannels + c]);
+    if (c == 0) accb += d;
+  }
+  red[r][c] = acc;
+  if (c == 0) red[r][kHeadChannels] = accb;
+  __syncthreads();
+  if (threadIdx.x <= kHeadChannels) {
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) s += red[k][threadIdx.x];
+    part[(int64_t)blockIdx.x * (kHeadChannels + 1) + threadIdx.x] = s;
+  }
+}
+
+hipError_t launch_head_bwd(const float* dy, const uint16_t* d0, const uint16_t* wb, float* g,
+                           float* part, int nblk, int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(256), 0, s, dy, d0, wb, g, part, nblk, P);
+  return hipGetLastError();
+}
+
+// Adam with bias correction (c1 = 1 - beta1^t, c2 = 1 - beta2^t); refreshes
+// the bfloat16 copy of each parameter.
+__global__ void k_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, int64_t n,
+                       float lr, float c1, float c2) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+  }
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, int64_t n,
+                       float lr, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(2048), dim3(256), 0, s, p, g, m, v, pb, n, lr, c1, c2);
+  return hipGetLastError();
+}
+
+// Predicted heights: y (U/U_ref) H_ref inside the grid, 0 on its perimeter.
+__global__ void k_heights(const float* y, const double* U, double* h, int B, int H, int W) {
+  const int64_t P = (int64_t)B * H * W;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int x = (int)(p % W), yy = (int)((p / W) % H);
+  h[p] = (x > 0 && x < W - 1 && yy > 0 && yy < H - 1) ? (double)y[p] * ((U[p] / kURef) * kHRef)
+                                                       : 0.0;
+}
+
+hipError_t launch_heights(const float* y, const double* U, double* h, int B, int H, int W,
+                          hipStream_t s) {
+  const int64_t P = (int64_t)B * H * W;
+  hipLaunchKernelGGL(k_heights, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, y, U, h, B, H,
+                     W);
+  return hipGetLastError();
+}
+
+}  // namespace sur

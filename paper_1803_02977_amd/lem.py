@@ -174,9 +174,10 @@ def lem_batch_run(ctx: int, d_h: int, d_K, d_U, steps: int) -> None:
 
 
 def lem_batch_run_to_steady(ctx: int, d_h: int, d_K, d_U, rtol: float, check_every: int,
-                            max_steps: int, count: int):
+                            max_steps: int, count: int, steps_in=None):
     import numpy as np
-    out = np.zeros(count, np.int64)
+    out = (np.full(count, -1, np.int64) if steps_in is None
+           else np.ascontiguousarray(steps_in, np.int64).copy())
     _check(load().lem_batch_run_to_steady(ctx, d_h, d_K, d_U, rtol, check_every, max_steps,
                                           out.ctypes.data_as(_P)), ctx)
     return out
@@ -391,13 +392,35 @@ class Batch:
                 self._check_h(f)
         lem_batch_run(self.ctx, h.data_ptr(), _dptr(K), _dptr(U), int(steps))
 
-    def run_to_steady(self, h, rtol=1e-6, check_every=10, max_steps=100000, K=None, U=None):
+    def run_to_steady(self, h, rtol=1e-6, check_every=10, max_steps=100000, K=None, U=None,
+                      chunk=None, progress=None):
+        """Steps to convergence; returns steps per grid (-1: not converged).
+        With ``chunk`` the run is split into calls of at most that many
+        steps (grids that converged stay frozen) and ``progress(done_steps,
+        converged)`` is called after each."""
+        import numpy as np
         self._check_h(h)
         for f in (K, U):
             if f is not None:
                 self._check_h(f)
-        return lem_batch_run_to_steady(self.ctx, h.data_ptr(), _dptr(K), _dptr(U), float(rtol),
-                                       int(check_every), int(max_steps), len(self.descs))
+        n = len(self.descs)
+        if not chunk:
+            return lem_batch_run_to_steady(self.ctx, h.data_ptr(), _dptr(K), _dptr(U),
+                                           float(rtol), int(check_every), int(max_steps), n)
+        if chunk % check_every:
+            raise LemError(LEM_E_ARG, "chunk must be a multiple of check_every")
+        total = np.full(n, -1, np.int64)
+        done = 0
+        while done < max_steps and (total < 0).any():
+            k = min(int(chunk), int(max_steps) - done)
+            got = lem_batch_run_to_steady(self.ctx, h.data_ptr(), _dptr(K), _dptr(U),
+                                          float(rtol), int(check_every), k, n, steps_in=total)
+            new = (total < 0) & (got >= 0)
+            total[new] = got[new] + done
+            done += k
+            if progress:
+                progress(done, int((total >= 0).sum()))
+        return total
 
     def sync(self):
         lem_sync(self.ctx)

@@ -96,3 +96,37 @@ def test_null_context_calls():
     assert lib.lem_last_error(None) == b""
     for s in range(8):
         assert lib.lem_status_str(s).startswith(b"LEM_")
+
+
+def test_surrogate_layer_table_matches_the_reference_network():
+    from oracle import surrogate as S
+    from paper_1803_02977_amd import surrogate as sur
+    layout, total = S.param_layout()
+    assert sur.param_count() == total
+    for i, (name, cin, cout) in enumerate(S.layer_table()):
+        assert sur.layer(i) == (cin, cout, layout[name][0]), name
+    assert sur.layer(14) == (32, 1, layout["head"][0])
+    with pytest.raises(lem.LemError):
+        sur.layer(15)
+
+
+@pytest.mark.parametrize("shape", [(0, 64, 64), (1, 60, 64), (1, 64, 4), (2, 7, 8)])
+def test_surrogate_shapes_are_checked_on_the_host(shape):
+    from paper_1803_02977_amd import surrogate as sur
+    assert sur.workspace_bytes(*shape) == 0
+    lib = sur.load()
+    ctx = C.c_void_p()
+    assert lib.lem_sur_create(*shape, C.c_void_p(4096), 1 << 40, None, C.byref(ctx)) == lem.LEM_E_SIZE
+
+
+def test_surrogate_workspace_is_checked_before_the_device():
+    from paper_1803_02977_amd import surrogate as sur
+    lib = sur.load()
+    need = sur.workspace_bytes(2, 64, 64)
+    assert need > 0
+    ctx = C.c_void_p()
+    assert lib.lem_sur_create(2, 64, 64, None, need, None, C.byref(ctx)) == lem.LEM_E_WORKSPACE
+    assert lib.lem_sur_create(2, 64, 64, C.c_void_p(4096 + 8), need, None,
+                              C.byref(ctx)) == lem.LEM_E_WORKSPACE
+    assert lib.lem_sur_create(2, 64, 64, C.c_void_p(4096), need - 1, None,
+                              C.byref(ctx)) == lem.LEM_E_WORKSPACE

@@ -154,3 +154,24 @@ def test_batch_with_fields_equals_each_grid_alone():
         s.close()
         assert np.array_equal(b.view(h, g).cpu().numpy(), hs.cpu().numpy()), g
     b.close()
+
+
+def test_run_to_steady_in_chunks_equals_one_call():
+    """A run split over calls (grids steady on entry are skipped) gives the
+    same heights and step counts as one call."""
+    torch = require_gpu()
+    grids = [W.Realization(s, s, 100.0, 100.0, 2e4, m, 1e-3, k, 17 + i)
+             for i, (s, m, k) in enumerate([(20, 0.5, 5e-5), (33, 0.45, 1e-4), (48, 0.5, 2e-4),
+                                            (17, 0.6, 5e-4)])]
+    h0 = W.batch_initial_heights(grids)
+    b = _batch(torch, grids)
+    h1 = torch.from_numpy(h0).to("cuda:0")
+    one = b.run_to_steady(h1, rtol=1e-6, check_every=5, max_steps=20000)
+    h2 = torch.from_numpy(h0).to("cuda:0")
+    seen = []
+    many = b.run_to_steady(h2, rtol=1e-6, check_every=5, max_steps=20000, chunk=15,
+                           progress=lambda s, c: seen.append((s, c)))
+    assert np.array_equal(one, many), (one, many)
+    assert torch.equal(h1, h2)
+    assert seen and seen[-1][1] == len(grids)
+    b.close()

@@ -1,0 +1,234 @@
+"""GPU: the warm-start network's MFMA forward pass, gradients and Adam step
+through the C ABI against the FP64 CPU reference (``oracle.surrogate``) with
+bfloat16 rounding at the same points.
+
+Tolerance.  Both sides round the same values to bfloat16, but the GPU sums in
+float32 and the reference in FP64, so a value lying within float32 error of
+a bfloat16 rounding boundary can round the other way: one bfloat16 step
+(2^-8 relative) in that element, which then spreads through later layers.
+Such flips are rare (float32 error ~1e-6 relative against a 4e-3 spacing),
+so whole tensors agree to well under 1e-2 in relative L2 norm (measured:
+2e-3 to 7e-3 for the output after fourteen layers); the bounds below are set
+there.  The layer-by-layer test is the tight one: each layer recomputed by
+the reference from the GPU's own bfloat16 input must match except for
+one-step rounding flips in under 1% of the elements.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+REL_Y = 1e-2       # relative L2 error of the network output
+REL_GRAD = 2e-2    # relative L2 error of each parameter block's gradient
+COS_GRAD = 0.9995  # cosine of the whole gradient vector
+
+
+def _problem(seed, B, H, W):
+    rng = np.random.default_rng(seed)
+    from paper_1803_02977_amd import surrogate as sur
+    p = sur.init_params(seed)
+    # Nonzero biases so that they matter in the forward pass.
+    layout, _ = S.param_layout()
+    for name, cin, cout in S.layer_table():
+        off = layout[name][0] + cout * 9 * cin
+        p[off:off + cout] = (rng.standard_normal(cout) * 0.05).astype(np.float32)
+    p[layout["head"][0] + 32] = np.float32(0.7)
+    K = 1e-5 * np.exp(0.5 * rng.standard_normal((B, H, W)))
+    U = np.repeat(rng.uniform(1e-4, 2e-3, B), H * W).reshape(B, H, W)
+    h0 = rng.random((B, H, W))
+    yy, xx = np.mgrid[0:H, 0:W]
+    dome = np.minimum.reduce([yy, xx, H - 1 - yy, W - 1 - xx]).astype(np.float64)
+    ht = (U / 1e-3) * 100.0 * (0.1 * dome[None] + 0.2 * rng.random((B, H, W)))
+    return p, K, U, h0, ht
+
+
+def _net(torch, B, H, W):
+    from paper_1803_02977_amd.surrogate import Surrogate
+    return Surrogate(B, H, W, device=torch.device("cuda:0"))
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+SHAPES = [(2, 32, 48), (1, 64, 80), (3, 16, 16)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_forward_matches_reference(shape):
+    torch = require_gpu()
+    B, H, W = shape
+    print(f"[gpu] surrogate forward {shape}", flush=True)
+    p, K, U, h0, _ = _problem(1, B, H, W)
+    net = _net(torch, B, H, W)
+    net.set_params(p)
+    h, y = net.predict(_dev(torch, K), _dev(torch, U), _dev(torch, h0), want_y=True)
+    net.sync()
+    y = y.cpu().numpy().astype(np.float64)
+    ref = S.forward(p.astype(np.float64), K, U, h0, bf16=True)["y"]
+    assert _rel(y, ref) < REL_Y, _rel(y, ref)
+    # Heights from the GPU's own output follow the stated formula exactly.
+    assert np.array_equal(h.cpu().numpy(), S.heights(y, U))
+    net.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES[:2], ids=lambda s: "x".join(map(str, s)))
+def test_gradients_match_reference(shape):
+    torch = require_gpu()
+    B, H, W = shape
+    print(f"[gpu] surrogate gradients {shape}", flush=True)
+    p, K, U, h0, ht = _problem(2, B, H, W)
+    net = _net(torch, B, H, W)
+    net.set_params(p)
+    args = [_dev(torch, a) for a in (K, U, h0, ht)]
+    loss, g = net.loss_grad(*args)
+    loss2, g2 = net.loss_grad(*args)
+    g = g.cpu().numpy().astype(np.float64)
+    assert loss == loss2 and np.array_equal(g, g2.cpu().numpy()), "not deterministic"
+    ref_loss, ref_g = S.loss_and_grad(p.astype(np.float64), K, U, h0, ht, bf16=True)
+    assert abs(loss - ref_loss) <= REL_Y * ref_loss, (loss, ref_loss)
+    layout, _ = S.param_layout()
+    blocks = [(n, layout[n][0], ci, co) for n, ci, co in S.layer_table()]
+    for name, off, cin, cout in blocks:
+        nw = cout * 9 * cin
+        for part, (a, b) in (("w", (off, off + nw)), ("b", (off + nw, off + nw + cout))):
+            r = _rel(g[a:b], ref_g[a:b])
+            assert r < REL_GRAD, (name, part, r)
+    ho = layout["head"][0]
+    assert _rel(g[ho:], ref_g[ho:]) < REL_GRAD
+    cos = float(g @ ref_g / (np.linalg.norm(g) * np.linalg.norm(ref_g)))
+    assert cos > COS_GRAD, cos
+    # Padded input channels have exactly zero gradient.
+    w0 = g[:32 * 9 * 32].reshape(32, 3, 3, 32)
+    assert np.all(w0[..., 3:] == 0.0)
+    net.close()
+
+
+def _ulp_bf16(x):
+    """Spacing of bfloat16 numbers at |x| (8 significant bits)."""
+    x = np.abs(x)
+    e = np.floor(np.log2(np.where(x > 0, x, 1.0)))
+    return np.where(x > 0, 2.0 ** (e - 7), 0.0)
+
+
+def _check_rounded(got, ref, what, max_frac=1e-2):
+    """got (GPU, bfloat16 values) against ref (exact, rounded to bfloat16
+    once): equal except where float32 summation put the value on the other
+    side of a rounding boundary, which moves it by one bfloat16 step (or
+    across zero by a negligible amount after ReLU)."""
+    diff = np.abs(got - ref)
+    bad = diff > 0
+    scale = float(np.sqrt(np.mean(ref * ref))) + 1e-30
+    big = np.maximum(np.abs(got), np.abs(ref))
+    allowed = np.maximum(_ulp_bf16(big) * 1.0000001, 1e-5 * scale)
+    assert np.all(diff <= allowed), (what, float((diff / np.maximum(allowed, 1e-300)).max()))
+    frac = float(bad.mean())
+    assert frac <= max_frac, (what, frac)
+    return frac
+
+
+@pytest.mark.parametrize("shape", [(2, 32, 48), (1, 64, 80)], ids=lambda s: "x".join(map(str, s)))
+def test_each_layer_matches_reference_on_the_gpus_own_inputs(shape):
+    """Every map of the forward pass recomputed by the reference from the
+    GPU's own bfloat16 input of that layer: convolutions (with bias and
+    ReLU), pooling, upsampling with concatenation, the head and the
+    features."""
+    torch = require_gpu()
+    B, H, W = shape
+    print(f"[gpu] surrogate layer by layer {shape}", flush=True)
+    p, K, U, h0, _ = _problem(5, B, H, W)
+    net = _net(torch, B, H, W)
+    net.set_params(p)
+    _, y = net.predict(_dev(torch, K), _dev(torch, U), _dev(torch, h0), want_y=True)
+    net.sync()
+    act = {i: net.activation(i, B).astype(np.float64) for i in range(21)}
+    P = S.unpack(p.astype(np.float64))
+    r = S.bf16_round
+    fracs = {}
+    fracs["features"] = _check_rounded(act[0], r(S.features(K, U, h0)), "features", 1e-3)
+
+    def conv_check(name, src, dst):
+        w, b = P[name]
+        ref = r(np.maximum(S.conv3x3(act[src], r(w), b), 0.0))
+        fracs[name] = _check_rounded(act[dst], ref, name)
+
+    for level in range(4):
+        conv_check(f"enc{level}a", 0 if level == 0 else 8 + level, 1 + 2 * level)
+        conv_check(f"enc{level}b", 1 + 2 * level, 2 + 2 * level)
+        if level < 3:
+            fracs[f"pool{level}"] = _check_rounded(act[9 + level], r(S.pool2(act[2 + 2 * level])),
+                                                   f"pool{level}", 1e-3)
+    for k, level in enumerate((2, 1, 0)):
+        low = act[8] if level == 2 else act[14 + 3 * (k - 1)]
+        cat = np.concatenate([S.up2(low), act[2 + 2 * level]], axis=-1)
+        assert np.array_equal(act[12 + 3 * k], cat), f"concatenation at level {level}"
+        conv_check(f"dec{level}a", 12 + 3 * k, 13 + 3 * k)
+        conv_check(f"dec{level}b", 13 + 3 * k, 14 + 3 * k)
+    wh, bh = P["head"]
+    yref = act[20] @ r(wh) + bh[0]
+    yg = y.cpu().numpy().astype(np.float64)
+    assert np.allclose(yg, yref, rtol=1e-5, atol=1e-5 * np.abs(yref).max())
+    print(f"[gpu] mismatch fractions {fracs}", flush=True)
+    net.close()
+
+
+def test_adam_steps_match_reference():
+    """Two Adam steps on the GPU against the reference Adam fed the GPU's own
+    gradients (the update rule alone: bias correction, moments, step)."""
+    torch = require_gpu()
+    B, H, W = 2, 32, 32
+    p, K, U, h0, ht = _problem(3, B, H, W)
+    net = _net(torch, B, H, W)
+    net.set_params(p)
+    args = [_dev(torch, a) for a in (K, U, h0, ht)]
+    lr = 1e-3
+    m = np.zeros(p.size)
+    v = np.zeros(p.size)
+    cur = p.astype(np.float64)
+    for t in (1, 2):
+        _, g = net.loss_grad(*args)
+        g = g.cpu().numpy().astype(np.float64)
+        net.train_step(*args, lr=lr)
+        got = net.get_params().cpu().numpy().astype(np.float64)
+        ref, m, v = S.adam(cur, g, m, v, t, lr)
+        err = np.abs(got - ref)
+        assert np.all(err <= 1e-6 * np.abs(ref) + 2e-3 * lr), (t, float(err.max()))
+        cur = got
+    net.close()
+
+
+def test_training_reduces_the_loss():
+    torch = require_gpu()
+    B, H, W = 4, 32, 32
+    p, K, U, h0, ht = _problem(4, B, H, W)
+    net = _net(torch, B, H, W)
+    net.set_params(p)
+    args = [_dev(torch, a) for a in (K, U, h0, ht)]
+    first = net.train_step(*args, lr=2e-3)
+    for _ in range(60):
+        last = net.train_step(*args, lr=2e-3)
+    assert np.isfinite(last) and last < 0.3 * first, (first, last)
+    net.close()
+
+
+def test_argument_errors():
+    torch = require_gpu()
+    from paper_1803_02977_amd import LemError
+    net = _net(torch, 2, 16, 16)
+    K = torch.ones((3, 16, 16), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(LemError):
+        net.predict(K, K, K)          # batch above the context's
+    with pytest.raises(LemError):
+        net.predict(K[:, :8], K[:, :8], K[:, :8])
+    with pytest.raises(LemError):
+        net.set_params(np.zeros(10, np.float32))
+    net.close()

@@ -122,3 +122,30 @@ def batch_realizations(count: int = 512, seed: int = 0, sizes=BATCH_SIZES,
 def batch_initial_heights(realizations) -> np.ndarray:
     """Initial heights of a batch, grid after grid (each from its own seed)."""
     return np.concatenate([initial_heights(r.ny, r.nx, r.seed).ravel() for r in realizations])
+
+
+# Learned warm start: 256 x 256 grids, 100 m cells, m = 0.5, dt = 1000 yr,
+# per-cell K lognormal (median 1e-5, sigma_ln 0.5), U ~ Uniform[1e-4, 2e-3]
+# per grid (a uniform field), h0 ~ Uniform[0,1) with the perimeter at 0.
+# Training realizations use seeds from WARMSTART_TRAIN_SEED, held-out ones
+# from WARMSTART_TEST_SEED.
+WARMSTART_SIDE = 256
+WARMSTART_TRAIN_SEED = 1_000_000
+WARMSTART_TEST_SEED = 9_000_000
+
+
+def warmstart_inputs(count: int, first_seed: int, ny: int = WARMSTART_SIDE,
+                     nx: int = WARMSTART_SIDE):
+    """(K, U, h0), each float64 [count, ny, nx], for realizations
+    first_seed, first_seed + 1, ...; realization s draws K and U from
+    default_rng(s) and h0 from initial_heights(ny, nx, s)."""
+    K = np.empty((count, ny, nx))
+    U = np.empty((count, ny, nx))
+    h0 = np.empty((count, ny, nx))
+    for i in range(count):
+        s = first_seed + i
+        rng = np.random.default_rng(s)
+        K[i] = 1e-5 * np.exp(0.5 * rng.standard_normal((ny, nx)))
+        U[i] = rng.uniform(1e-4, 2e-3)
+        h0[i] = initial_heights(ny, nx, s)
+    return K, U, h0
