@@ -49,7 +49,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=W.LARGE_10000.name,
-                    choices=sorted(W.WORKLOADS) + [BATCH_NAME, SWEEP_NAME])
+                    choices=sorted(W.WORKLOADS) + [BATCH_NAME, SWEEP_NAME, WARM_NAME])
+    ap.add_argument("--grids", type=int, default=100, help="held-out grids (warm-start workload)")
+    ap.add_argument("--plain-sample", type=int, default=10,
+                    help="warm-start workload: realizations timed through the plain solver")
+    ap.add_argument("--level-pass", type=int, default=0,
+                    help="batch workload: 0 automatic, 1 one device-wide pass, 2 one workgroup "
+                         "per grid")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=None)
@@ -62,6 +68,7 @@ def parse():
 
 BATCH_NAME = "batch-512-realizations-fp64"
 SWEEP_NAME = "size-sweep-100-16000"
+WARM_NAME = "warmstart-100x256x256-fp64"
 # Square edge lengths of the size sweep; the regions (upper edge length)
 # follow the GPU scaling table of the paper (section on GPU performance),
 # whose wall-time exponents x (wall ~ N^x) are quoted beside the fit.
@@ -71,19 +78,27 @@ SWEEP_REGIONS = (("A", 100, 400, 0.33), ("B", 400, 1000, 0.16), ("C", 1000, 2500
                  ("D", 2500, 16000, 0.92))
 
 
+def _batch_tuning():
+    """The tuned launch settings for a batch of this size (tuning.json)."""
+    from paper_1803_02977_amd import tune
+    t = tune.lookup(sum(r.ny * r.nx for r in W.batch_realizations(512)))
+    return {} if t is None else {"global_workgroups": t[0], "tail_level": t[1]}
+
+
 def bench_batch(args):
     """512 independent realizations (sizes 128..1024, per-realization K, U, m)
     advanced together for 500 steps; compared with the same grids run one by
     one through the single-grid path on the same GPU."""
     import torch
 
-    from paper_1803_02977_amd import Batch, Solver
+    from paper_1803_02977_amd import LEM_F_PHASE_TIMERS, Batch, Solver
     reals = W.batch_realizations(512, seed=args.seed)
     steps = args.steps or 500
     dev = torch.device("cuda:0")
     h0 = torch.from_numpy(W.batch_initial_heights(reals)).to(dev)
     h = h0.clone()
     b = Batch(reals, device=dev)
+    mode = b.set_tuning(**{**_batch_tuning(), "level_pass": args.level_pass})["level_pass"]
     if args.warmup > 0:
         b.run(h, args.warmup)
         b.sync()
@@ -102,6 +117,29 @@ def bench_batch(args):
     b.close()
     cells = sum(r.ny * r.nx for r in reals)
     value = cells * steps / (ms / 1e3)
+    # Kernel times with the library's HIP events on its stream: a second run
+    # of the same steps with phase timers (slower by one sync per step).
+    bt = Batch(reals, flags=LEM_F_PHASE_TIMERS, device=dev)
+    bt.set_tuning(**{**_batch_tuning(), "level_pass": args.level_pass})
+    h.copy_(h0)
+    bt.run(h, steps)
+    bt.sync()
+    stt = bt.stats()
+    bt.close()
+    tile_ms = stt.kernel_ms[0] / steps
+    level_ms = stt.kernel_ms[1] / steps
+    cross = stt.crossing_run / steps
+    if level_ms >= tile_ms:
+        roof = {"bound": "hbm", "kernel": "k_grid_levels" if mode == 2 else "k_global_levels",
+                "achieved": ALG_BYTES_GLOBAL * cross / (level_ms * 1e-3) / 1e9,
+                "alg_bytes": f"{ALG_BYTES_GLOBAL} B per crossing-tree cell",
+                "avg_launch_ms": level_ms}
+    else:
+        roof = {"bound": "hbm", "kernel": "k_tile_step",
+                "achieved": ALG_BYTES_TILE * cells / (tile_ms * 1e-3) / 1e9,
+                "alg_bytes": f"{ALG_BYTES_TILE} B per cell", "avg_launch_ms": tile_ms}
+    roof.update(peak=HBM_PEAK_GBS, unit="GB/s", frac=roof["achieved"] / HBM_PEAK_GBS,
+                traffic=None)
     # The same grids one at a time through the single-grid path (fewer steps).
     one_steps = max(1, min(steps, 20))
     solvers = [Solver(r.ny, r.nx, r.dx, r.dy, r.dt, r.m, r.U, r.K, device=dev) for r in reals]
@@ -131,7 +169,10 @@ def bench_batch(args):
                          "note": "same realizations, one single-grid context each, run "
                                  "one after another on the same GPU"},
         "batch_speedup_vs_grid_by_grid": round(value / one_value, 2),
-        "roofline": None,
+        "level_pass": "one workgroup per grid" if mode == 2 else "one device-wide pass",
+        "kernel_ms_per_step": {"k_tile_step": tile_ms,
+                               ("k_grid_levels" if mode == 2 else "k_global_levels"): level_ms},
+        "roofline": roof,
     }
     if not args.no_cpu:
         import oracle
@@ -207,6 +248,97 @@ def bench_sweep(args):
         "sweep": rows, "fit": fits, "roofline": None, "cpu_baseline": None}), flush=True)
 
 
+def bench_warmstart(args):
+    """Time to steady state (no cell changing by more than 1e-6 of its
+    grid's largest height in one step, dt = 1000 yr) of held-out 256 x 256
+    realizations, as one batch, from the noise surface (the plain solver) and
+    from the network's prediction (warm start, prediction time included);
+    plus the network's own throughput: a training step (forward, backward,
+    Adam) and a forward pass at batch 16, whose convolutions run on MFMA."""
+    import torch
+
+    from paper_1803_02977_amd import warmstart as WS
+    from paper_1803_02977_amd.surrogate import Surrogate, layer, load_params
+    dev = torch.device("cuda:0")
+    side = W.WARMSTART_SIDE
+    net = Surrogate(16, side, side, device=dev)
+    net.set_params(load_params(WS.WEIGHTS_PATH))
+    r = WS.evaluate(net, args.grids, batch=16, chunk=2000, plain_sample=args.plain_sample)
+    plain_s = r["plain"]["s_per_realization"] * args.grids
+    # Network throughput at batch 16 (training changes the parameters, so
+    # it runs after the evaluation).
+    B = 16
+    levels = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0]
+    fwd = sum(2.0 * B * (side >> lv) ** 2 * 9 * layer(i)[0] * layer(i)[1]
+              for i, lv in enumerate(levels))
+    bwd = 2 * fwd - 2.0 * B * side * side * 9 * layer(0)[0] * layer(0)[1]
+    K, U, h0 = WS.make_dataset(B, W.WARMSTART_TEST_SEED, dev)
+    tgt = h0 * 100.0
+    stream = net.stream
+    for _ in range(3):
+        net.train_step(K, U, h0, tgt, lr=1e-6, want_loss=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        net.predict(K, U, h0)
+    e1.record(stream)
+    net.sync()
+    ms_fwd = e0.elapsed_time(e1) / 20
+    e0.record(stream)
+    for _ in range(20):
+        net.train_step(K, U, h0, tgt, lr=1e-6, want_loss=False)
+    e1.record(stream)
+    net.sync()
+    ms_train = e0.elapsed_time(e1) / 20
+    net.close()
+    fwd_tflops = fwd / (ms_fwd * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        Kc, Uc, hc = W.warmstart_inputs(1, W.WARMSTART_TEST_SEED)
+        p = oracle.Params(side, side, WS.DX, WS.DX, WS.DT, WS.M, 1.0, float(Uc[0, 0, 0]), 1e-5)
+        steps = args.cpu_steps or 300
+        t0 = time.perf_counter()
+        oracle.run(hc[0], p, steps, K=Kc[0], U=Uc[0])
+        dt = time.perf_counter() - t0
+        cpu = {"value": side * side * steps / dt, "unit": "cell-updates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{steps} cold-start steps of held-out realization 0 ({side}x{side}, "
+                         f"K and U fields), serial C oracle, {dt:.2f} s; the cold runs above "
+                         f"take {r['cold_steps_mean']:.0f} steps per grid on average"}
+    print(json.dumps({
+        "metric": "time to steady state", "value": r["warm_s"], "unit": "s",
+        "n_gpus": 1, "steps": int(np.sum(r["warm_steps"])), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 solver, bf16/f32 network", "data": "synthetic",
+        "config": {"workload": WARM_NAME, "grids": args.grids, "side": side, "dt": WS.DT,
+                   "rtol": WS.RTOL, "K": "lognormal per cell, median 1e-5, sigma_ln 0.5",
+                   "U": "Uniform[1e-4,2e-3] per grid", "m": WS.M, "dx": WS.DX,
+                   "seeds": f"{W.WARMSTART_TEST_SEED}+ (held out)"},
+        "plain_solver_s": plain_s, "speedup_vs_plain": plain_s / r["warm_s"],
+        "plain_solver": {"s_per_realization": r["plain"]["s_per_realization"],
+                         "sample": f"first {args.plain_sample} realizations from the noise "
+                                   "surface, one after another through the single-grid path "
+                                   f"(a batch of one), scaled to {args.grids}",
+                         "steps_equal_batched": r["plain"]["steps_match_batch"]},
+        "batched_cold_s": r["cold_s"], "batched_warm_s": r["warm_s"],
+        "surrogate_speedup_in_batch": r["cold_s"] / r["warm_s"],
+        "steps_mean": {"cold": r["cold_steps_mean"], "warm": r["warm_steps_mean"]},
+        "steps_pct_10_50_90_100": {"cold": r["cold_steps_pct"], "warm": r["warm_steps_pct"]},
+        "steps_ratio_warm_over_cold": r["steps_ratio_warm_over_cold"],
+        "warm_fewer_steps_frac": r["warm_fewer_steps_frac"],
+        "all_converged": r["all_converged"], "predict_s": r["predict_s"],
+        "prediction_rel_l2_vs_cold_steady": r["prediction_rel_l2_vs_cold_steady"],
+        "noise_rel_l2_vs_cold_steady": r["noise_rel_l2_vs_cold_steady"],
+        "network": {"batch": B, "forward_ms": ms_fwd, "train_step_ms": ms_train,
+                    "conv_gflop_forward": fwd / 1e9,
+                    "train_tflops": (fwd + bwd) / (ms_train * 1e-3) / 1e12},
+        "roofline": {"bound": "mfma", "achieved": fwd_tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": fwd_tflops / 2500.0, "traffic": None,
+                     "kernel": "k_conv3x3 (forward pass, all fourteen convolutions)"},
+        "cpu_baseline": cpu}), flush=True)
+
+
 def cpu_baseline(w, h0, K, steps):
     """The serial oracle (one host thread) on ``steps`` steps of the workload."""
     import oracle
@@ -230,6 +362,9 @@ def main():
         return
     if args.workload == SWEEP_NAME:
         bench_sweep(args)
+        return
+    if args.workload == WARM_NAME:
+        bench_warmstart(args)
         return
     import torch
 

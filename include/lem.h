@@ -227,10 +227,22 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out);
  * cooperative level kernel for trees that cross tile edges (0 = default,
  * clamped to what the device can keep resident); tail_level: levels with
  * fewer cells than this are handled by one workgroup without grid-wide
- * barriers (0 = default, >= 1). */
+ * barriers (0 = default, >= 1); level_pass: how a batch orders the trees
+ * that cross tile edges (Steps 4-7): LEM_LEVELS_GLOBAL, one cooperative
+ * pass over the whole batch with device-wide barriers between levels, or
+ * LEM_LEVELS_PER_GRID, one workgroup per grid with workgroup barriers only,
+ * the grids running concurrently; 0 = automatic (per grid for batches of
+ * two or more grids of at most 2^21 cells each, else global);
+ * level_threads: threads of each per-grid workgroup, 256 or 1024 (0 =
+ * automatic: 256 when every grid has at most 2^18 cells, else 1024). */
+#define LEM_LEVELS_AUTO 0
+#define LEM_LEVELS_GLOBAL 1
+#define LEM_LEVELS_PER_GRID 2
 typedef struct lem_tuning {
   int32_t global_workgroups;
   int32_t tail_level;
+  int32_t level_pass;
+  int32_t level_threads;
 } lem_tuning;
 
 /* Applies *t to later runs on ctx.  LEM_E_ARG for negative fields. */

@@ -26,6 +26,9 @@ struct lem_ctx {
   int grid;                         // workgroups of the cooperative level kernel
   int grid_max;                     // most that stay resident on this device
   int tail_level;
+  int level_pass;                   // LEM_LEVELS_* as set (0 = automatic)
+  bool pergrid;                     // level pass in use: one workgroup per grid
+  int level_threads;                // threads per workgroup of that pass (0 = automatic)
   int device;
   double tick_khz;                  // device wall-clock rate
   int64_t steps_done;
@@ -154,6 +157,7 @@ lem::StepArgs make_args(const lem_ctx* ctx, const double* d_K, const double* d_U
   a.Uf = d_U;
   a.w = ctx->w;
   a.tail_level = ctx->tail_level;
+  a.pergrid = ctx->pergrid ? 1 : 0;
   return a;
 }
 
@@ -176,14 +180,34 @@ lem_status validate_inputs(lem_ctx* ctx, const double* d_h, const double* d_K, c
   return LEM_OK;
 }
 
+// Automatic choice of the level pass: one workgroup per grid pays off when
+// there are several grids to run side by side and none is so large that its
+// one workgroup would dominate the step.
+bool auto_pergrid(const lem_ctx* ctx) {
+  if (ctx->grids.size() < 2) return false;
+  for (const lem::GridDev& g : ctx->grids)
+    if ((int64_t)g.ny * g.nx > (int64_t(1) << 21)) return false;
+  return true;
+}
+
+// Threads per workgroup of the per-grid level pass: small grids have small
+// levels, where fewer threads mean cheaper workgroup barriers.
+int pergrid_threads(const lem_ctx* ctx) {
+  if (ctx->level_threads) return ctx->level_threads;
+  for (const lem::GridDev& g : ctx->grids)
+    if ((int64_t)g.ny * g.nx > (int64_t(1) << 18)) return lem::kBlock;
+  return 256;
+}
+
 // One step: the tile pass, then the global level pass for crossing trees.
 lem_status step(lem_ctx* ctx, lem::StepArgs& a, bool timers) {
   if (timers) (void)hipEventRecord(ctx->ev0, ctx->stream);
   hipError_t e = lem::launch_tile_step(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "tile launch");
   if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
-  e = lem::launch_global_levels(a, ctx->grid, ctx->stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "global-level launch");
+  e = ctx->pergrid ? lem::launch_grid_levels(a, pergrid_threads(ctx), ctx->stream)
+                   : lem::launch_global_levels(a, ctx->grid, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "level-pass launch");
   if (timers) {
     (void)hipEventRecord(ctx->ev2, ctx->stream);
     e = hipEventSynchronize(ctx->ev2);
@@ -272,6 +296,9 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
   ctx->grid_max = cus * per_cu;
   ctx->grid = ctx->grid_max < lem::kGlobalMaxWGs ? ctx->grid_max : lem::kGlobalMaxWGs;
   ctx->tail_level = lem::kTailLevel;
+  ctx->level_pass = LEM_LEVELS_AUTO;
+  ctx->pergrid = auto_pergrid(ctx);
+  ctx->level_threads = 0;
   ctx->tick_khz = (double)rate;
   e = hipMemsetAsync(ctx->w.ctrl, 0, sizeof(lem::Ctrl), ctx->stream);
   if (e == hipSuccess)
@@ -591,11 +618,17 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out) {
 
 lem_status lem_set_tuning(lem_ctx* ctx, const lem_tuning* t) {
   if (!ctx || !t) return LEM_E_ARG;
-  if (t->global_workgroups < 0 || t->tail_level < 0)
-    return fail(ctx, LEM_E_ARG, "tuning fields must be >= 0");
+  if (t->global_workgroups < 0 || t->tail_level < 0 || t->level_pass < 0 || t->level_pass > 2 ||
+      (t->level_threads != 0 && t->level_threads != 256 && t->level_threads != lem::kBlock))
+    return fail(ctx, LEM_E_ARG,
+                "tuning fields must be >= 0 (level_pass 0, 1 or 2; level_threads 0, 256 or 1024)");
+  ctx->level_threads = t->level_threads;
   int g = t->global_workgroups ? t->global_workgroups : lem::kGlobalMaxWGs;
   ctx->grid = g < ctx->grid_max ? g : ctx->grid_max;
   ctx->tail_level = t->tail_level ? t->tail_level : lem::kTailLevel;
+  ctx->level_pass = t->level_pass;
+  ctx->pergrid = t->level_pass == LEM_LEVELS_PER_GRID ||
+                 (t->level_pass == LEM_LEVELS_AUTO && auto_pergrid(ctx));
   return LEM_OK;
 }
 
@@ -603,6 +636,8 @@ lem_status lem_get_tuning(const lem_ctx* ctx, lem_tuning* out) {
   if (!ctx || !out) return LEM_E_ARG;
   out->global_workgroups = ctx->grid;
   out->tail_level = ctx->tail_level;
+  out->level_pass = ctx->pergrid ? LEM_LEVELS_PER_GRID : LEM_LEVELS_GLOBAL;
+  out->level_threads = pergrid_threads(ctx);
   return LEM_OK;
 }
 

@@ -103,6 +103,9 @@ struct Work {
   double* ftab;      // [ngrids*3*kAmTab] F = K*dt*A^m/d per distance class (scalar K)
   double* gtab;      // [ngrids*3*kAmTab] 1 + F
   int32_t* hist;     // [kHistCap] level count per step of the current run
+  int32_t* gcnt;     // [ngrids] per-grid level pass: crossing roots queued per grid
+  int32_t* gnl;      // [ngrids] per-grid level pass: levels of the crossing trees
+  int32_t* gtot;     // [ngrids] per-grid level pass: cells of the crossing trees
   Ctrl* ctrl;
   int32_t* scratch;  // [kScratchInts] reductions (validation)
 };
@@ -126,7 +129,7 @@ struct StepArgs {
   int32_t fixed;         // receivers come from w.rcode (fixed routing)
   int32_t export_routing;  // write per-cell codes, levels and counts
   int32_t tail_level;    // levels smaller than this run in one workgroup
-  int32_t pad;
+  int32_t pergrid;       // crossing trees: one workgroup per grid (else the global pass)
 };
 
 size_t workspace_bytes(int64_t n, int64_t ngrids, int64_t ntiles);
@@ -136,6 +139,7 @@ hipError_t launch_begin_run(const StepArgs& a, hipStream_t s);
 hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user_rcode, hipStream_t s);
 hipError_t launch_tile_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s);
+hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s);
 // Routing export of grid g (its cells [offset, offset + ny*nx)).
 hipError_t launch_export(const StepArgs& a, int g, int64_t offset, int64_t cells, int32_t* rec,
                          int32_t* depth, uint32_t* count, hipStream_t s);

@@ -578,9 +578,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   atomicAdd(&s_clean, my_clean);
   int tot;
   const int pre = block_exclusive_scan<kTileThreads>(my_roots, wsum, &tot);
-  if (tid == 0) s_base = tot ? atomicAdd(&w.lcnt[0], tot) : 0;
+  if (tid == 0)
+    s_base = tot ? atomicAdd(a.pergrid ? &w.gcnt[gi] : &w.lcnt[0], tot) : 0;
   __syncthreads();
-  int pos = s_base + pre;
+  int pos = (a.pergrid ? (int)off : 0) + s_base + pre;
   while (root_bits) {
     const int t = __ffs(root_bits) - 1;
     root_bits &= root_bits - 1;
@@ -682,10 +683,11 @@ __device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t 
 }
 
 // Step 5 for queue positions [a0, a1): count = 1 + the donors' counts.
+template <int NT = kBlock>
 __device__ __forceinline__ void accumulate_level(const Work& w, int32_t a0, int32_t a1, int wg,
                                                  int nwg) {
-  for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1;
-       i += (int64_t)nwg * kBlock) {
+  for (int64_t i = a0 + (int64_t)wg * NT + threadIdx.x; i < a1;
+       i += (int64_t)nwg * NT) {
     const uint32_t m = w.mq[i];
     uint32_t s = 1u;
     if (m) {
@@ -698,11 +700,12 @@ __device__ __forceinline__ void accumulate_level(const Work& w, int32_t a0, int3
 }
 
 // Steps 6-7 for queue positions [a0, a1) of a level >= 1.
+template <int NT = kBlock>
 __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32_t a1, int wg,
                                             int nwg) {
   const Work& w = a.w;
-  for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1;
-       i += (int64_t)nwg * kBlock) {
+  for (int64_t i = a0 + (int64_t)wg * NT + threadIdx.x; i < a1;
+       i += (int64_t)nwg * NT) {
     const int32_t c = w.q[i];
     const int gi = w.gq[i];
     const GridDev& G = a.grids[gi];
@@ -873,6 +876,179 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Crossing trees of a batch, one workgroup per grid.  Each grid's roots sit
+// in its own region of the queue ([offset, offset + cells), appended by the
+// tile pass), and its levels are separated by workgroup barriers only, so
+// grids proceed independently and no device-wide barrier is needed.  Level
+// offsets go to lev[offset + 2*grid ...] (at most cells + 1 of them).
+
+// Breadth-first expansion of positions [lo, hi) by one workgroup: donors are
+// appended at *s_next, which advances.
+template <int NT>
+__device__ void expand_level_wg(const StepArgs& a, int32_t lo, int32_t hi, int* wsum,
+                                int32_t* s_next) {
+  const Work& w = a.w;
+  const int tid = threadIdx.x;
+  for (int64_t base = lo; base < hi; base += (int64_t)NT * kItems) {
+    int32_t cs[kItems];
+    uint32_t ms[kItems];
+    int cntv = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = base + (int64_t)j * NT + tid;
+      cs[j] = 0;
+      ms[j] = 0;
+      if (i < hi) {
+        cs[j] = w.q[i];
+        const uint32_t m = w.dmask[cs[j]];
+        ms[j] = m | ((uint32_t)w.gq[i] << 8);
+        cntv += __popc(m);
+      }
+    }
+    int tot;
+    const int pre = block_exclusive_scan<NT>(cntv, wsum, &tot);
+    const int32_t start = *s_next;
+    int32_t pos = start + pre;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = base + (int64_t)j * NT + tid;
+      if (i < hi) {
+        uint32_t m = ms[j] & 0xFFu;
+        const uint32_t gi = ms[j] >> 8;
+        w.mq[i] = (uint8_t)m;
+        w.fc[i] = pos;
+        if (m) {
+          const int nx = a.grids[gi].nx;
+          while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1;
+            w.q[pos] = (int32_t)(cs[j] + neighbour_offset(b, nx));
+            w.gq[pos] = (uint16_t)gi;
+            w.par[pos] = (int32_t)i;
+            w.kq[pos] = (uint8_t)(7 - b);
+            ++pos;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) *s_next = start + tot;
+    __syncthreads();
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
+  __shared__ int wsum[NT / 64];
+  __shared__ int32_t s_next;
+  const Work w = a.w;
+  const int gi = blockIdx.x;
+  const int tid = threadIdx.x;
+  const GridDev& G = a.grids[gi];
+  const int32_t nroots = w.gcnt[gi];
+  if (nroots == 0) {
+    if (tid == 0) {
+      w.gnl[gi] = 0;
+      w.gtot[gi] = 0;
+    }
+    return;
+  }
+  const int32_t base = (int32_t)G.offset;
+  int32_t* lev = w.lev + G.offset + 2 * (int64_t)gi;
+  int32_t lo = base, hi = base + nroots, L = 0;
+  if (tid == 0) {
+    lev[0] = lo;
+    s_next = hi;
+  }
+  __syncthreads();
+  // Step 4: levels from the roots outward.
+  while (true) {
+    if (tid == 0) lev[L + 1] = hi;
+    expand_level_wg<NT>(a, lo, hi, wsum, &s_next);
+    const int32_t nh = s_next;
+    if (nh == hi) break;
+    lo = hi;
+    hi = nh;
+    ++L;
+  }
+  __syncthreads();
+  // Step 5: counts, deepest level first.
+  for (int32_t l = L; l >= 0; --l) {
+    accumulate_level<NT>(w, lev[l], lev[l + 1], 0, 1);
+    __syncthreads();
+  }
+  // Level 0: uplift of the interior roots (perimeter roots keep their height).
+  for (int32_t i = lev[0] + tid; i < lev[1]; i += NT) {
+    const int32_t c = w.q[i];
+    double hv = a.h_in[c];
+    if (w.kq[i] == kSink) hv = hv + (a.Uf ? a.Uf[c] * G.dt : G.udt);
+    a.h_out[c] = hv;
+    w.hq[i] = hv;
+  }
+  __syncthreads();
+  // Steps 6-7, levels 1 and up.
+  for (int32_t l = 1; l <= L; ++l) {
+    erode_level<NT>(a, lev[l], lev[l + 1], 0, 1);
+    __syncthreads();
+  }
+  if (a.export_routing) {
+    for (int32_t l = 0; l <= L; ++l)
+      for (int32_t i = lev[l] + tid; i < lev[l + 1]; i += NT) {
+        const int32_t c = w.q[i];
+        w.dep_g[c] = l;
+        w.cnt_g[c] = w.cnt[i];
+      }
+  }
+  if (tid == 0) {
+    w.gcnt[gi] = 0;
+    w.gnl[gi] = L + 1;
+    w.gtot[gi] = hi - base;
+  }
+}
+
+// After the per-grid level pass: the step's statistics (as the global pass
+// records them) from the per-grid results.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_grid_levels_finish(StepArgs a) {
+  __shared__ int32_t smax[1024];
+  __shared__ long long ssum[1024];
+  const Work w = a.w;
+  int32_t mx = 0;
+  long long sum = 0;
+  for (int g = threadIdx.x; g < a.ngrids; g += 1024) {
+    mx = max(mx, w.gnl[g]);
+    sum += w.gtot[g];
+  }
+  smax[threadIdx.x] = mx;
+  ssum[threadIdx.x] = sum;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + s]);
+      ssum[threadIdx.x] += ssum[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Ctrl* ct = w.ctrl;
+    const int32_t clean = ct->clean;
+    const int32_t nl_clean = clean ? ct->clean_maxdepth + 1 : 0;
+    const int32_t nl_cross = smax[0];
+    const int64_t total = ssum[0];
+    const int32_t nl = nl_clean > nl_cross ? nl_clean : nl_cross;
+    ct->nlevels = nl;
+    ct->dirty_total = (int32_t)total;
+    ct->dirty_nlevels = nl_cross;
+    ct->crossing_run += total;
+    if (nl > ct->max_nlevels) ct->max_nlevels = nl;
+    if (a.step < kHistCap) w.hist[a.step] = nl;
+    ct->steps = a.step + 1;
+    if ((int64_t)clean + total != (int64_t)a.n) atomicMax(&ct->status, 5);
+    ct->clean = 0;
+    ct->clean_maxdepth = 0;
+  }
+}
+
 // Start of a run: tabulate A^m, F and 1 + F per grid (block g does grid g)
 // and reset the control block.
 __global__ void k_begin_run(StepArgs a) {
@@ -887,6 +1063,7 @@ __global__ void k_begin_run(StepArgs a) {
       a.w.gtab[(gi * 3 + c) * kAmTab + i] = 1.0 + f;
     }
   }
+  if (i == 0) a.w.gcnt[gi] = 0;
   if (i == 0 && gi == 0) {
     Ctrl* ct = a.w.ctrl;
     ct->max_nlevels = 0;
@@ -927,7 +1104,8 @@ __global__ __launch_bounds__(256) void k_fixed_routing(StepArgs a, const uint8_t
 __global__ __launch_bounds__(256) void k_export_cross(StepArgs a) {
   const Work w = a.w;
   const int32_t nlev = w.ctrl->dirty_nlevels;
-  const int32_t total = w.ctrl->dirty_total;
+  // The per-grid level pass writes levels and counts itself.
+  const int32_t total = a.pergrid ? 0 : w.ctrl->dirty_total;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
     int32_t lo = 0, hi = nlev;  // largest l with lev[l] <= i
@@ -1035,7 +1213,7 @@ void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w) {
   w->cnt = (uint32_t*)take(4 * n);
   w->hq = (double*)take(8 * n);
   w->lcnt = (int32_t*)take(4 * (n + 2));
-  w->lev = (int32_t*)take(4 * (n + 2));
+  w->lev = (int32_t*)take(4 * (n + 2 * ngrids + 2));
   w->dep_g = (int32_t*)take(4 * n);
   w->cnt_g = (uint32_t*)take(4 * n);
   w->dhist = (int32_t*)take(4 * (n + 2));
@@ -1043,6 +1221,9 @@ void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w) {
   w->ftab = (double*)take(8 * 3 * kAmTab * ngrids);
   w->gtab = (double*)take(8 * 3 * kAmTab * ngrids);
   w->hist = (int32_t*)take(4 * kHistCap);
+  w->gcnt = (int32_t*)take(4 * ngrids);
+  w->gnl = (int32_t*)take(4 * ngrids);
+  w->gtot = (int32_t*)take(4 * ngrids);
   w->ctrl = (Ctrl*)take(sizeof(Ctrl));
   w->scratch = (int32_t*)take(4 * kScratchInts);
 }
@@ -1061,6 +1242,17 @@ hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user, hipStrea
 hipError_t launch_tile_step(const StepArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_step, dim3((unsigned)a.ntiles), dim3(kTileThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s) {
+  if (threads == 256)
+    hipLaunchKernelGGL(k_grid_levels<256>, dim3((unsigned)a.ngrids), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_grid_levels<kBlock>, dim3((unsigned)a.ngrids), dim3(kBlock), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grid_levels_finish, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 

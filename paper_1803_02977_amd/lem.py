@@ -47,8 +47,12 @@ class lem_grid(C.Structure):
                 ("pad", C.c_int32), ("offset", C.c_int64)]
 
 
+LEM_LEVELS_AUTO, LEM_LEVELS_GLOBAL, LEM_LEVELS_PER_GRID = 0, 1, 2
+
+
 class lem_tuning(C.Structure):
-    _fields_ = [("global_workgroups", C.c_int32), ("tail_level", C.c_int32)]
+    _fields_ = [("global_workgroups", C.c_int32), ("tail_level", C.c_int32),
+                ("level_pass", C.c_int32), ("level_threads", C.c_int32)]
 
 
 class LemError(RuntimeError):
@@ -236,7 +240,7 @@ def _dptr(t):
 
 def _apply_tuning(obj, cells, tuning):
     """tuning: None (library defaults), "auto" (tuning.json if present) or
-    a (global_workgroups, tail_level) pair."""
+    a (global_workgroups, tail_level[, level_pass]) tuple."""
     if tuning is None:
         return
     if tuning == "auto":
@@ -318,10 +322,12 @@ class Solver:
     def stats(self) -> lem_stats_t:
         return lem_stats(self.ctx)
 
-    def set_tuning(self, global_workgroups=0, tail_level=0):
-        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level))
+    def set_tuning(self, global_workgroups=0, tail_level=0, level_pass=0, level_threads=0):
+        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level, level_pass,
+                                            level_threads))
         t = lem_get_tuning(self.ctx)
-        return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level)
+        return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level,
+                    level_pass=t.level_pass, level_threads=t.level_threads)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -438,10 +444,12 @@ class Batch:
         offsets, _ = lem_batch_routing(self.ctx, g, None, None, None, nl + 1)
         return dict(rec=rec, depth=depth, count=count, offsets=offsets, nlevels=nl)
 
-    def set_tuning(self, global_workgroups=0, tail_level=0):
-        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level))
+    def set_tuning(self, global_workgroups=0, tail_level=0, level_pass=0, level_threads=0):
+        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level, level_pass,
+                                            level_threads))
         t = lem_get_tuning(self.ctx)
-        return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level)
+        return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level,
+                    level_pass=t.level_pass, level_threads=t.level_threads)
 
     def stats(self) -> lem_stats_t:
         return lem_stats(self.ctx)

@@ -111,6 +111,34 @@ def init_params(seed: int = 0, input_features: int = 3) -> np.ndarray:
     return p
 
 
+def bias_mask() -> np.ndarray:
+    """True at the bias entries of the parameter vector."""
+    mask = np.zeros(param_count(), bool)
+    for i in range(NUM_LAYERS):
+        cin, cout, off = layer(i)
+        nw = cin if i == NUM_LAYERS - 1 else cout * 9 * cin
+        mask[off + nw:off + nw + cout] = True
+    return mask
+
+
+def save_params(path, params):
+    """Stores parameters as the network uses them: weights as bfloat16
+    (nearest, ties to even) and biases as float32.  Loading gives a vector
+    whose predictions equal those of the float32 original."""
+    p = np.asarray(params, np.float32)
+    u = p.view(np.uint32).astype(np.uint64)
+    bits = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    mask = bias_mask()
+    np.savez_compressed(path, weights_bf16=bits, biases=p[mask])
+
+
+def load_params(path) -> np.ndarray:
+    z = np.load(path, allow_pickle=False)
+    p = (z["weights_bf16"].astype(np.uint32) << 16).view(np.float32).copy()
+    p[bias_mask()] = z["biases"]
+    return p
+
+
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 

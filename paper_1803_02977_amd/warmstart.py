@@ -4,8 +4,8 @@ comparison.  Every step runs in the library's kernels (the batch solver of
 ``lem.h`` and the network of ``lem_surrogate.h``); this module only moves
 arrays and drives the loops.
 
-    python -m paper_1803_02977_amd.warmstart train --samples 20000 --out weights.npy
-    python -m paper_1803_02977_amd.warmstart evaluate --weights weights.npy --grids 100
+    python -m paper_1803_02977_amd.warmstart train --samples 20000 --out weights.npz
+    python -m paper_1803_02977_amd.warmstart evaluate --weights weights.npz --grids 100
 
 Training targets are steady states of the solver (runs stepped until no cell
 changes by more than 1e-6 of the grid's largest height in one step) from
@@ -33,14 +33,14 @@ if ROOT not in sys.path:
 import workloads as W  # noqa: E402
 
 from .lem import Batch  # noqa: E402
-from .surrogate import Surrogate, init_params  # noqa: E402
+from .surrogate import Surrogate, init_params, load_params, save_params  # noqa: E402
 
 DX = 100.0
 M = 0.5
 DT = 1000.0
 GEN_DT = 1e4
 RTOL = 1e-6
-WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_weights.npy")
+WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_weights.npz")
 
 
 def _log(msg):
@@ -71,6 +71,71 @@ def steady_states(K, U, h0, dt=GEN_DT, check_every=10, max_steps=200000, chunk=N
     torch.cuda.synchronize()
     b.close()
     return h.reshape(K.shape), steps
+
+
+def steady_states_queue(K, U, h_init, slots, dt=DT, check_every=10, chunk=500,
+                        max_steps=200000, label="queue"):
+    """Runs many realizations to steady state through a batch of `slots`
+    identical grids: whenever a grid converges its slot is refilled with the
+    next realization (heights, K and U fields), so the batch stays full and
+    the run's time follows the total number of steps rather than the
+    slowest realization.  Each realization evolves exactly as it would
+    alone (grids of a batch are independent), so results and step counts
+    equal those of steady_states().  Returns (h, steps per realization)."""
+    import torch
+
+    from .lem import lem_batch_run_to_steady
+    n, ny, nx = K.shape
+    if chunk % check_every:
+        raise ValueError("chunk must be a multiple of check_every")
+    S = min(slots, n)
+    cells = ny * nx
+    b = Batch(_grids(np.full(S, 1e-3), ny, nx, dt), device=K.device)
+    hs = torch.zeros(S * cells, dtype=torch.float64, device=K.device)
+    Ks = torch.full_like(hs, 1e-5)
+    Us = torch.zeros_like(hs)
+    hv, Kv, Uv = hs.view(S, ny, nx), Ks.view(S, ny, nx), Us.view(S, ny, nx)
+    state = np.zeros(S, np.int64)   # >= 0: idle or converged (not stepped); -1: running
+    item = np.full(S, -1)
+    age = np.zeros(S, np.int64)
+    steps = np.full(n, -1, np.int64)
+    h_out = torch.empty_like(K)
+    nxt = 0
+    t0 = time.perf_counter()
+
+    def load(g):
+        nonlocal nxt
+        hv[g].copy_(h_init[nxt])
+        Kv[g].copy_(K[nxt])
+        Uv[g].copy_(U[nxt])
+        item[g], age[g], state[g] = nxt, 0, -1
+        nxt += 1
+
+    for g in range(S):
+        load(g)
+    rounds = 0
+    while (state < 0).any():
+        got = lem_batch_run_to_steady(b.ctx, hs.data_ptr(), Ks.data_ptr(), Us.data_ptr(), RTOL,
+                                      check_every, chunk, S, steps_in=state)
+        for g in range(S):
+            if state[g] >= 0:
+                continue
+            if got[g] >= 0 or age[g] + chunk >= max_steps:
+                steps[item[g]] = age[g] + got[g] if got[g] >= 0 else -1
+                h_out[item[g]].copy_(hv[g])
+                if nxt < n:
+                    load(g)
+                else:
+                    state[g] = 0
+            else:
+                age[g] += chunk
+        rounds += 1
+        if rounds % 8 == 0:
+            _log(f"{label}: {int((steps >= 0).sum())}/{n} steady, "
+                 f"{time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    b.close()
+    return h_out, steps
 
 
 def make_dataset(count, first_seed, device, piece=1000):
@@ -128,10 +193,14 @@ def predict(net, K, U, h0, batch):
 
 
 def evaluate(net, grids, first_seed=W.WARMSTART_TEST_SEED, batch=16, dt=DT, check_every=10,
-             max_steps=200000, chunk=2000, device="cuda:0"):
+             max_steps=200000, chunk=2000, device="cuda:0", slots=None, plain_sample=0):
     """Steps and device time to steady state from the noise surface (cold)
     and from the network's prediction (warm), on held-out realizations, with
-    the same solver, dt and stopping rule."""
+    the same solver, dt and stopping rule.  slots=None runs all realizations
+    as one batch (time = slowest realization); otherwise a batch of `slots`
+    grids is refilled as realizations converge (steady_states_queue).
+    plain_sample > 0 also runs that many realizations from the noise surface
+    one after another through the single-grid path (the plain solver)."""
     import torch
     dev = torch.device(device)
     K, U, h0 = make_dataset(grids, first_seed, dev)
@@ -140,20 +209,43 @@ def evaluate(net, grids, first_seed=W.WARMSTART_TEST_SEED, batch=16, dt=DT, chec
     hp = predict(net, K, U, h0, batch)
     torch.cuda.synchronize()
     t_pred = time.perf_counter() - t
+
+    def run(h_start, label):
+        if slots:
+            return steady_states_queue(K, U, h_start, slots, dt=dt, check_every=check_every,
+                                       chunk=min(chunk, 500), max_steps=max_steps, label=label)
+        return steady_states(K, U, h_start, dt=dt, check_every=check_every,
+                             max_steps=max_steps, chunk=chunk, label=label)
+
     t = time.perf_counter()
-    h_cold, s_cold = steady_states(K, U, h0, dt=dt, check_every=check_every,
-                                   max_steps=max_steps, chunk=chunk, label="cold")
+    h_cold, s_cold = run(h0, "cold")
     t_cold = time.perf_counter() - t
     t = time.perf_counter()
-    h_warm, s_warm = steady_states(K, U, hp, dt=dt, check_every=check_every,
-                                   max_steps=max_steps, chunk=chunk, label="warm")
+    h_warm, s_warm = run(hp, "warm")
     t_warm = time.perf_counter() - t
+    plain = None
+    if plain_sample:
+        t = time.perf_counter()
+        ps = []
+        for i in range(plain_sample):
+            _, st = steady_states(K[i:i + 1].contiguous(), U[i:i + 1].contiguous(),
+                                  h0[i:i + 1].contiguous(), dt=dt, check_every=check_every,
+                                  max_steps=max_steps, chunk=chunk, label=f"plain {i}")
+            ps.append(int(st[0]))
+        t_plain = time.perf_counter() - t
+        plain = {"realizations": plain_sample, "s": t_plain,
+                 "s_per_realization": t_plain / plain_sample,
+                 "steps_match_batch": ps == [int(v) for v in s_cold[:plain_sample]]}
     rel = lambda a, b: float((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item())
     return {
+        "plain": plain,
         "grids": grids, "side": int(K.shape[1]), "dt": dt, "rtol": RTOL,
         "check_every": check_every,
         "cold_steps": s_cold.tolist(), "warm_steps": s_warm.tolist(),
+        "slots": slots or grids,
         "cold_steps_mean": float(np.mean(s_cold)), "warm_steps_mean": float(np.mean(s_warm)),
+        "cold_steps_pct": [int(v) for v in np.percentile(s_cold, [10, 50, 90, 100])],
+        "warm_steps_pct": [int(v) for v in np.percentile(s_warm, [10, 50, 90, 100])],
         "steps_ratio_warm_over_cold": float(np.sum(s_warm) / np.sum(s_cold)),
         "warm_fewer_steps_frac": float(np.mean(s_warm < s_cold)),
         "all_converged": bool((s_cold >= 0).all() and (s_warm >= 0).all()),
@@ -207,7 +299,7 @@ def main():
                        seed=args.seed)
         t_train = time.perf_counter() - t0
         p = net.get_params().cpu().numpy()
-        np.save(args.out, p)
+        save_params(args.out, p)
         report = {"samples": args.samples, "converged": int(ok.sum()), "gen_dt": args.gen_dt,
                   "gen_steps_mean": float(steps[ok].mean()), "gen_s": t_gen,
                   "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
@@ -216,7 +308,7 @@ def main():
         _log(json.dumps(report))
     else:
         net = Surrogate(16, side, side, device=dev)
-        net.set_params(np.load(args.weights))
+        net.set_params(load_params(args.weights))
         report = evaluate(net, args.grids)
         _log(json.dumps({k: v for k, v in report.items() if not isinstance(v, list)}))
     if args.report:

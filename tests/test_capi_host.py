@@ -7,6 +7,9 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+import torch
+
 import pytest
 
 import paper_1803_02977_amd as pkg
@@ -130,3 +133,20 @@ def test_surrogate_workspace_is_checked_before_the_device():
                               C.byref(ctx)) == lem.LEM_E_WORKSPACE
     assert lib.lem_sur_create(2, 64, 64, C.c_void_p(4096), need - 1, None,
                               C.byref(ctx)) == lem.LEM_E_WORKSPACE
+
+
+def test_surrogate_parameters_round_trip_through_storage(tmp_path):
+    from paper_1803_02977_amd import surrogate as sur
+    p = sur.init_params(3)
+    p[sur.bias_mask()] = np.linspace(-1, 1, int(sur.bias_mask().sum()), dtype=np.float32)
+    sur.save_params(str(tmp_path / "w.npz"), p)
+    q = sur.load_params(str(tmp_path / "w.npz"))
+    m = sur.bias_mask()
+    assert np.array_equal(q[m], p[m])
+    assert np.array_equal(q[~m], torch.from_numpy(p[~m]).to(torch.bfloat16).float().numpy())
+
+
+def test_stored_warm_start_weights_have_the_network_shape():
+    from paper_1803_02977_amd import surrogate as sur, warmstart as WS
+    p = sur.load_params(WS.WEIGHTS_PATH)
+    assert p.shape == (sur.param_count(),) and np.all(np.isfinite(p))

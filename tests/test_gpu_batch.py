@@ -175,3 +175,35 @@ def test_run_to_steady_in_chunks_equals_one_call():
     assert torch.equal(h1, h2)
     assert seen and seen[-1][1] == len(grids)
     b.close()
+
+
+def test_level_pass_modes_give_identical_results():
+    """The crossing trees of a batch ordered by one device-wide pass or by
+    one workgroup per grid: heights, routing and level history identical."""
+    torch = require_gpu()
+    from paper_1803_02977_amd import LEM_LEVELS_GLOBAL, LEM_LEVELS_PER_GRID
+    grids = _grids()
+    h0 = W.batch_initial_heights(grids)
+    out = {}
+    configs = [(LEM_LEVELS_GLOBAL, 0), (LEM_LEVELS_PER_GRID, 1024), (LEM_LEVELS_PER_GRID, 256)]
+    for mode, threads in configs:
+        print(f"[gpu] batch level pass mode {mode} threads {threads}", flush=True)
+        b = _batch(torch, grids)
+        got = b.set_tuning(level_pass=mode, level_threads=threads)
+        assert got["level_pass"] == mode
+        h = torch.from_numpy(h0).to("cuda:0")
+        b.run(h, 25)
+        b.sync()
+        routes = [b.routing(g) for g in range(len(grids))]
+        out[(mode, threads)] = (h.cpu().numpy(), routes, b.stats().max_nlevels)
+        b.close()
+    ha, ra, la = out[configs[0]]
+    for cfg in configs[1:]:
+        hb, rb, lb = out[cfg]
+        assert np.array_equal(ha, hb), cfg
+        assert la == lb, cfg
+        for g in range(len(grids)):
+            for k in ("rec", "depth", "count"):
+                assert torch.equal(ra[g][k], rb[g][k]), (cfg, g, k)
+            assert ra[g]["nlevels"] == rb[g]["nlevels"]
+            assert np.array_equal(np.asarray(ra[g]["offsets"]), np.asarray(rb[g]["offsets"]))

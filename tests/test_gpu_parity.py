@@ -169,7 +169,7 @@ def test_zero_steps_is_a_no_op():
     s.close()
 
 
-@pytest.mark.parametrize("tuning", [(0, 0), (1, 1), (16, 1 << 30), (256, 64), (3, 5000)])
+@pytest.mark.parametrize("tuning", [(0, 0), (1, 1), (16, 1 << 30), (256, 64), (3, 5000), (0, 0, 2)])
 def test_tuning_does_not_change_results(tuning):
     """Workgroup count and the one-workgroup level threshold of the global
     pass change only the schedule: heights and routing stay bit-identical."""
