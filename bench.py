@@ -43,13 +43,34 @@ ALG_BYTES_GLOBAL = 55
 ALG_BYTES_FIELD = 8
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm-traffic-plain-10000x10000.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1803_02977_amd", "csrc", "lem_kernels.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source has
+    changed since the counters were taken (the summary records its hash)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        data = json.loads(block)
+        digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("source_sha256") != digest:
+        return None
+    return data.get("bytes_per_launch", {}).get(kernel)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=W.LARGE_10000.name,
-                    choices=sorted(W.WORKLOADS) + [BATCH_NAME, SWEEP_NAME, WARM_NAME])
+                    choices=sorted(W.WORKLOADS) + [BATCH_NAME, SWEEP_NAME, WARM_NAME, NET_NAME])
     ap.add_argument("--grids", type=int, default=100, help="held-out grids (warm-start workload)")
     ap.add_argument("--plain-sample", type=int, default=10,
                     help="warm-start workload: realizations timed through the plain solver")
@@ -69,6 +90,7 @@ def parse():
 BATCH_NAME = "batch-512-realizations-fp64"
 SWEEP_NAME = "size-sweep-100-16000"
 WARM_NAME = "warmstart-100x256x256-fp64"
+NET_NAME = "warmstart-network-b16-256x256-bf16"
 # Square edge lengths of the size sweep; the regions (upper edge length)
 # follow the GPU scaling table of the paper (section on GPU performance),
 # whose wall-time exponents x (wall ~ N^x) are quoted beside the fit.
@@ -248,6 +270,72 @@ def bench_sweep(args):
         "sweep": rows, "fit": fits, "roofline": None, "cpu_baseline": None}), flush=True)
 
 
+def _network_throughput(net, dev, side, steps=20):
+    """Forward pass and training step (forward, backward, Adam) of the
+    warm-start network at its context's batch, timed with HIP events on its
+    stream; FLOPs count the fourteen 3x3 convolutions (2 per multiply-add),
+    the backward pass twice the forward minus the skipped input gradient of
+    the first layer."""
+    import torch
+
+    from paper_1803_02977_amd import warmstart as WS
+    from paper_1803_02977_amd.surrogate import layer
+    B = net.batch
+    levels = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0]
+    fwd = sum(2.0 * B * (side >> lv) ** 2 * 9 * layer(i)[0] * layer(i)[1]
+              for i, lv in enumerate(levels))
+    bwd = 2 * fwd - 2.0 * B * side * side * 9 * layer(0)[0] * layer(0)[1]
+    K, U, h0 = WS.make_dataset(B, W.WARMSTART_TEST_SEED, dev)
+    tgt = h0 * 100.0
+    stream = net.stream
+    for _ in range(3):
+        net.train_step(K, U, h0, tgt, lr=1e-6, want_loss=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        net.predict(K, U, h0)
+    e1.record(stream)
+    net.sync()
+    ms_fwd = e0.elapsed_time(e1) / steps
+    e0.record(stream)
+    for _ in range(steps):
+        net.train_step(K, U, h0, tgt, lr=1e-6, want_loss=False)
+    e1.record(stream)
+    net.sync()
+    ms_train = e0.elapsed_time(e1) / steps
+    return {"batch": B, "forward_ms": ms_fwd, "train_step_ms": ms_train, "fwd_flop": fwd,
+            "bwd_flop": bwd}
+
+
+def bench_network(args):
+    """The warm-start network alone: training steps and forward passes at
+    batch 16 on 256 x 256 inputs (the convolutions run on MFMA)."""
+    import torch
+
+    from paper_1803_02977_amd import warmstart as WS
+    from paper_1803_02977_amd.surrogate import Surrogate, load_params
+    dev = torch.device("cuda:0")
+    side = W.WARMSTART_SIDE
+    net = Surrogate(16, side, side, device=dev)
+    net.set_params(load_params(WS.WEIGHTS_PATH))
+    nt = _network_throughput(net, dev, side, steps=args.steps or 20)
+    net.close()
+    train_tf = (nt["fwd_flop"] + nt["bwd_flop"]) / (nt["train_step_ms"] * 1e-3) / 1e12
+    fwd_tf = nt["fwd_flop"] / (nt["forward_ms"] * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "conv TFLOP/s (training step)", "value": train_tf, "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps or 20, "warmup": 3, "ms_per_step": nt["train_step_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+        "config": {"workload": NET_NAME, "batch": 16, "side": side},
+        "forward_ms": nt["forward_ms"], "forward_tflops": fwd_tf,
+        "conv_gflop": {"forward": nt["fwd_flop"] / 1e9, "backward": nt["bwd_flop"] / 1e9},
+        "roofline": {"bound": "mfma", "achieved": fwd_tf, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": fwd_tf / 2500.0, "traffic": None,
+                     "kernel": "k_conv3x3 (forward pass, all fourteen convolutions)"},
+        "cpu_baseline": None}), flush=True)
+
+
 def bench_warmstart(args):
     """Time to steady state (no cell changing by more than 1e-6 of its
     grid's largest height in one step, dt = 1000 yr) of held-out 256 x 256
@@ -265,32 +353,12 @@ def bench_warmstart(args):
     net.set_params(load_params(WS.WEIGHTS_PATH))
     r = WS.evaluate(net, args.grids, batch=16, chunk=2000, plain_sample=args.plain_sample)
     plain_s = r["plain"]["s_per_realization"] * args.grids
-    # Network throughput at batch 16 (training changes the parameters, so
-    # it runs after the evaluation).
-    B = 16
-    levels = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0]
-    fwd = sum(2.0 * B * (side >> lv) ** 2 * 9 * layer(i)[0] * layer(i)[1]
-              for i, lv in enumerate(levels))
-    bwd = 2 * fwd - 2.0 * B * side * side * 9 * layer(0)[0] * layer(0)[1]
-    K, U, h0 = WS.make_dataset(B, W.WARMSTART_TEST_SEED, dev)
-    tgt = h0 * 100.0
-    stream = net.stream
-    for _ in range(3):
-        net.train_step(K, U, h0, tgt, lr=1e-6, want_loss=False)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(20):
-        net.predict(K, U, h0)
-    e1.record(stream)
-    net.sync()
-    ms_fwd = e0.elapsed_time(e1) / 20
-    e0.record(stream)
-    for _ in range(20):
-        net.train_step(K, U, h0, tgt, lr=1e-6, want_loss=False)
-    e1.record(stream)
-    net.sync()
-    ms_train = e0.elapsed_time(e1) / 20
+    # Network throughput (training changes the parameters, so it runs after
+    # the evaluation).
+    nt = _network_throughput(net, dev, side)
     net.close()
+    ms_fwd, ms_train, fwd, bwd = nt["forward_ms"], nt["train_step_ms"], nt["fwd_flop"], nt["bwd_flop"]
+    B = nt["batch"]
     fwd_tflops = fwd / (ms_fwd * 1e-3) / 1e12
     cpu = None
     if not args.no_cpu:
@@ -366,6 +434,9 @@ def main():
     if args.workload == WARM_NAME:
         bench_warmstart(args)
         return
+    if args.workload == NET_NAME:
+        bench_network(args)
+        return
     import torch
 
     from paper_1803_02977_amd import LEM_F_PHASE_TIMERS, Solver
@@ -431,7 +502,8 @@ def main():
         per_unit = f"{ALG_BYTES_GLOBAL} B per crossing-tree cell"
     achieved = kbytes / (kms / 1e3) / 1e9
     roofline = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(kname) if w.name == W.LARGE_10000.name else None,
                     alg_bytes=per_unit, avg_launch_ms=round(kms, 4))
     out = {
         "metric": "cell-updates/s",

@@ -234,7 +234,7 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out);
  * the grids running concurrently; 0 = automatic (per grid for batches of
  * two or more grids of at most 2^21 cells each, else global);
  * level_threads: threads of each per-grid workgroup, 256 or 1024 (0 =
- * automatic: 256 when every grid has at most 2^18 cells, else 1024). */
+ * automatic: 1024). */
 #define LEM_LEVELS_AUTO 0
 #define LEM_LEVELS_GLOBAL 1
 #define LEM_LEVELS_PER_GRID 2

@@ -190,13 +190,13 @@ bool auto_pergrid(const lem_ctx* ctx) {
   return true;
 }
 
-// Threads per workgroup of the per-grid level pass: small grids have small
-// levels, where fewer threads mean cheaper workgroup barriers.
+// Threads per workgroup of the per-grid level pass.  1024 by default: even
+// for 256 x 256 grids the levels of evolved landscapes are wide enough that
+// more loads in flight beat the cheaper barriers of smaller workgroups
+// (measured on MI355X: 100 grids to steady state, 24 s with 1024 threads,
+// 29 s with 256).
 int pergrid_threads(const lem_ctx* ctx) {
-  if (ctx->level_threads) return ctx->level_threads;
-  for (const lem::GridDev& g : ctx->grids)
-    if ((int64_t)g.ny * g.nx > (int64_t(1) << 18)) return lem::kBlock;
-  return 256;
+  return ctx->level_threads ? ctx->level_threads : lem::kBlock;
 }
 
 // One step: the tile pass, then the global level pass for crossing trees.

@@ -199,7 +199,9 @@ __device__ __forceinline__ void erosion_factor(const StepArgs& a, const GridDev&
     *g = a.w.gtab[(gi * 3 + cls) * kAmTab + count];
     return;
   }
-  const double d = G.dn[cls];
+  // A select, not an index: a runtime index into a local copy of the
+  // descriptor would move that copy to scratch memory.
+  const double d = cls == 0 ? G.dn[0] : (cls == 1 ? G.dn[1] : G.dn[2]);
   const double am = count < (uint32_t)kAmTab
                         ? a.w.amtab[gi * kAmTab + count]
                         : area_power_call((double)count * G.dxdy, G.use_sqrt, G.m);
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   const Work w = a.w;
   const int tile = w.tiles[xcd_tile(blockIdx.x, a.ntiles)];
   const int gi = grid_of_tile(a.grids, a.ngrids, tile);
-  const GridDev G = a.grids[gi];
+  const GridDev& G = a.grids[gi];  // read through the scalar cache, not copied
   const int lt = tile - G.tile_base;
   const int y0 = (lt / G.tiles_x) * kTH, x0 = (lt % G.tiles_x) * kTW;
   const int ny = G.ny, nx = G.nx;

@@ -436,18 +436,30 @@ hipError_t launch_relu_bwd(float* g, const uint16_t* y, uint16_t* dz, int64_t n,
 }
 
 // Per-channel sums over pixels: split s sums pixels [s P/splits, (s+1) P/splits).
-__global__ void k_colsum(const float* g, int64_t P, int C, float* part, int splits) {
+// C divides 256: the 256 threads form 256/C rows of C channels, so each
+// iteration reads 256 consecutive floats; the rows are then summed in LDS in
+// a fixed order.
+__global__ __launch_bounds__(256) void k_colsum(const float* g, int64_t P, int C, float* part,
+                                                int splits) {
+  __shared__ float red[256];
   const int s = blockIdx.x;
+  const int R = 256 / C;
+  const int r = threadIdx.x / C, c = threadIdx.x % C;
   const int64_t p0 = P * s / splits, p1 = P * (s + 1) / splits;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    float acc = 0.f;
-    for (int64_t p = p0; p < p1; ++p) acc += g[p * C + c];
-    part[(int64_t)s * C + c] = acc;
+  float acc = 0.f;
+  for (int64_t p = p0 + r; p < p1; p += R) acc += g[p * C + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (r == 0) {
+    float t = 0.f;
+    for (int k = 0; k < R; ++k) t += red[k * C + c];
+    part[(int64_t)s * C + c] = t;
   }
 }
 
 hipError_t launch_colsum(const float* g, int64_t P, int C, float* part, int splits,
                          hipStream_t s) {
+  if (C < 1 || C > 256 || 256 % C != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_colsum, dim3(splits), dim3(256), 0, s, g, P, C, part, splits);
   return hipGetLastError();
 }
