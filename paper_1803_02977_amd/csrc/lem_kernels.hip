@@ -62,13 +62,14 @@ constexpr uint32_t kSpinLimit = 1u << 26;  // about 2 s of polling
 static_assert(kTileCells % kTileThreads == 0, "tile cells must split evenly over threads");
 static_assert(kCellsPerThread <= 32, "root bit mask holds 32 cells per thread");
 
-__device__ __forceinline__ int code_dy(int k) { return (k < 3) ? -1 : (k < 5 ? 0 : 1); }
-__device__ __forceinline__ int code_dx(int k) {
-  return (k == 0 || k == 3 || k == 5) ? -1 : ((k == 1 || k == 6) ? 0 : 1);
-}
+// Row and column offsets of neighbour k, as 2-bit fields (offset + 1) packed
+// in one word so that a run-time k costs a shift and a mask, not branches:
+// dy + 1 = 0 0 0 1 1 2 2 2 and dx + 1 = 0 1 2 0 2 0 1 2 for k = 0..7.
+__device__ __forceinline__ int code_dy(int k) { return (int)((0xA940u >> (2 * k)) & 3u) - 1; }
+__device__ __forceinline__ int code_dx(int k) { return (int)((0x9224u >> (2 * k)) & 3u) - 1; }
 // Distance class of a receiver code: 0 vertical (dy), 1 horizontal (dx), 2 diagonal.
 __device__ __forceinline__ int code_class(int k) {
-  return (k == 1 || k == 6) ? 0 : ((k == 3 || k == 4) ? 1 : 2);
+  return (int)((0x8962u >> (2 * k)) & 3u);  // 2 0 2 1 1 2 0 2 for k = 0..7
 }
 
 __device__ __forceinline__ int64_t neighbour_offset(int k, int nx) {
@@ -291,12 +292,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   __shared__ double hs[kHH * kHW];            // heights, tile + 2-cell halo
   __shared__ uint16_t nxt[kTileCells];        // pointer jumping: ends as the local root
   __shared__ uint32_t clw[kTileCells / 2];    // upstream counts, two 16-bit halves a word
-  __shared__ uint16_t lst[kTileCells];        // resolved cells sorted by level
   __shared__ uint8_t rc[kRH * kRW];           // receiver codes, tile + ring
   __shared__ uint8_t dm[kTileCells];          // donor masks
   __shared__ uint8_t dp[kTileCells];          // level within the tile
+  __shared__ double ftl[3 * kAmTab];          // F for small counts (scalar K), per distance class
   __shared__ uint8_t crossing[kTileCells];    // per local root: tree leaves/enters the tile
-  __shared__ int lvl[kLocalDepthCap + 2];     // per-level counts, then offsets
   __shared__ int wsum[kTileThreads / 64];
   __shared__ int s_flag[2];
   __shared__ int s_all, s_clean, s_cmax, s_base;
@@ -318,8 +318,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     s_clean = 0;
     s_cmax = 0;
   }
-  for (int i = tid; i < kLocalDepthCap + 2; i += kTileThreads) lvl[i] = 0;
   for (int i = tid; i < kTileCells / 2; i += kTileThreads) clw[i] = 0u;
+  if (!a.Kf)
+    for (int i = tid; i < 3 * kAmTab; i += kTileThreads) ftl[i] = w.ftab[gi * 3 * kAmTab + i];
   // Heights of the tile and a 2-cell halo (positions outside the grid hold 0
   // and are never used).  All loads are issued before the LDS stores.
   {
@@ -450,67 +451,31 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     const int r = nxt[i];
     const int rcode = rc[(r / kTW + 1) * kRW + (r % kTW + 1)];
     if (rcode < kSink && !crossing[r]) s_all = 1;
-    uint32_t m = dm[i];
+    // A donor outside the tile: only border cells have neighbours outside,
+    // in the directions 0-2 (top row), 5-7 (bottom row), 0, 3, 5 (left
+    // column) and 2, 4, 7 (right column).
     const int ly = i / kTW, lx = i % kTW;
-    bool entry = false;
-    while (m) {
-      const int k = __ffs(m) - 1;
-      m &= m - 1;
-      const int dy_ = ly + code_dy(k), dx_ = lx + code_dx(k);
-      entry |= (dy_ < 0 || dy_ >= kTH || dx_ < 0 || dx_ >= kTW);
-    }
-    if (entry) crossing[nxt[i]] = 1;
+    const uint32_t out = (ly == 0 ? 0x07u : 0u) | (ly == kTH - 1 ? 0xE0u : 0u) |
+                         (lx == 0 ? 0x29u : 0u) | (lx == kTW - 1 ? 0x94u : 0u);
+    if (dm[i] & out) crossing[r] = 1;
   }
   __syncthreads();
   const bool all_cross = s_all != 0;
 
-  // Cells of trees that stay in the tile ("clean"), bucketed by level.
+  // Cells of trees that stay in the tile ("clean") and their deepest level.
   uint32_t clean_bits = 0;
+  int my_max = -1;
 #pragma unroll
   for (int t = 0; t < kCellsPerThread; ++t) {
     const int i = tid + t * kTileThreads;
     const int ly = i / kTW, lx = i % kTW;
     if (all_cross || y0 + ly >= ny || x0 + lx >= nx || crossing[nxt[i]]) continue;
     clean_bits |= 1u << t;
-    atomicAdd(&lvl[dp[i]], 1);
+    my_max = max(my_max, (int)dp[i]);
   }
-  __syncthreads();
-  // Exclusive prefix over the level counts (wave 0, four bins per lane).
-  if (tid < 64) {
-    int c4[4], s = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = tid * 4 + q;
-      c4[q] = b <= kLocalDepthCap ? lvl[b] : 0;
-      s += c4[q];
-    }
-    const int inc = wave_inclusive_scan(s);
-    int run = inc - s;
-    int top = -1;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = tid * 4 + q;
-      if (b <= kLocalDepthCap) lvl[b] = run;
-      if (c4[q]) top = b;
-      run += c4[q];
-    }
-    // Deepest non-empty level (wave-wide maximum).
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) top = max(top, __shfl_xor(top, d, 64));
-    if (tid == 0) {
-      s_cmax = top;
-      lvl[kLocalDepthCap + 1] = inc;  // unused slot keeps the total for reference
-    }
-  }
-  __syncthreads();
-  const int cmax = s_cmax;
-  // Scatter: afterwards lvl[l] is the end of level l in lst.
-#pragma unroll
-  for (int t = 0; t < kCellsPerThread; ++t) {
-    if (!(clean_bits & (1u << t))) continue;
-    const int i = tid + t * kTileThreads;
-    lst[atomicAdd(&lvl[dp[i]], 1)] = (uint16_t)i;
-  }
+  for (int d = 32; d >= 1; d >>= 1) my_max = max(my_max, __shfl_xor(my_max, d, 64));
+  if ((tid & 63) == 0 && my_max >= 0) atomicMax(&s_cmax, my_max);
   // Step 5: each clean cell adds one to the count of every cell on its path
   // to the root (itself included): count = number of upstream cells.
 #pragma unroll
@@ -527,16 +492,32 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   __syncthreads();
 
   // Steps 6-7 for clean trees: uplift of interior roots (level 0), then the
-  // implicit update level by level from the root.
+  // implicit update level by level from the root.  Each thread keeps its own
+  // cells; F comes from the grid's table staged in LDS (scalar K, counts
+  // below kAmTab) or is computed as in erosion_factor.
+  const int cmax = s_cmax;
+  // Levels of this thread's cells, one byte each, so that finding the cells
+  // of a level takes register arithmetic only.
+  static_assert(kCellsPerThread <= 8, "one byte per cell in a 64-bit word");
+  uint64_t my_levels = 0;
+#pragma unroll
+  for (int t = 0; t < kCellsPerThread; ++t)
+    my_levels |= (uint64_t)dp[tid + t * kTileThreads] << (8 * t);
   for (int l = 0; l <= cmax; ++l) {
-    const int lo = l == 0 ? 0 : lvl[l - 1], hi = lvl[l];
-    for (int j = lo + tid; j < hi; j += kTileThreads) {
-      const int i = lst[j];
+    uint32_t at_l = 0;
+#pragma unroll
+    for (int t = 0; t < kCellsPerThread; ++t)
+      at_l |= (uint32_t)(((my_levels >> (8 * t)) & 0xFFu) == (uint64_t)l) << t;
+    at_l &= clean_bits;
+    while (at_l) {
+      const int t = __ffs(at_l) - 1;
+      at_l &= at_l - 1;
+      const int i = tid + t * kTileThreads;
       const int ly = i / kTW, lx = i % kTW;
-      const int64_t c = off + (int64_t)(y0 + ly) * nx + (x0 + lx);
-      const int hidx = (ly + 2) * kHW + (lx + 2);
       const int code = rc[(ly + 1) * kRW + (lx + 1)];
       if (code == kBase) continue;
+      const int64_t c = off + (int64_t)(y0 + ly) * nx + (x0 + lx);
+      const int hidx = (ly + 2) * kHW + (lx + 2);
       const double up = a.Uf ? a.Uf[c] * G.dt : G.udt;
       if (code == kSink) {
         hs[hidx] = hs[hidx] + up;
@@ -544,7 +525,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
       }
       const uint32_t count = (clw[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
       double f, g;
-      erosion_factor(a, G, gi, count, code, c, &f, &g);
+      if (!a.Kf && count < (uint32_t)kAmTab) {
+        f = ftl[code_class(code) * kAmTab + count];
+        g = 1.0 + f;
+      } else {
+        erosion_factor(a, G, gi, count, code, c, &f, &g);
+      }
       const double h0 = hs[hidx] + up;
       hs[hidx] = eroded_height(G, h0, hs[hidx + code_dy(code) * kHW + code_dx(code)], f, g);
     }
