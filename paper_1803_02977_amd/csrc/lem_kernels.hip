@@ -288,7 +288,7 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
+__global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
   __shared__ double hs[kHH * kHW];            // heights, tile + 2-cell halo
   __shared__ uint16_t nxt[kTileCells];        // pointer jumping: ends as the local root
   __shared__ uint32_t clw[kTileCells / 2];    // upstream counts, two 16-bit halves a word
@@ -319,8 +319,6 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     s_cmax = 0;
   }
   for (int i = tid; i < kTileCells / 2; i += kTileThreads) clw[i] = 0u;
-  if (!a.Kf)
-    for (int i = tid; i < 3 * kAmTab; i += kTileThreads) ftl[i] = w.ftab[gi * 3 * kAmTab + i];
   // Heights of the tile and a 2-cell halo (positions outside the grid hold 0
   // and are never used).  All loads are issued before the LDS stores.
   {
@@ -367,6 +365,15 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   }
   __syncthreads();
 
+  // The grid's F table goes to LDS; its loads are issued here and stored at
+  // the end of this phase, so that their latency hides behind its work.
+  static_assert(3 * kAmTab <= 2 * kTileThreads, "at most two table entries per thread");
+  const bool has_ft0 = tid < 3 * kAmTab, has_ft1 = tid + kTileThreads < 3 * kAmTab;
+  double ft0 = 0.0, ft1 = 0.0;
+  if (!a.Kf) {
+    if (has_ft0) ft0 = w.ftab[gi * 3 * kAmTab + tid];
+    if (has_ft1) ft1 = w.ftab[gi * 3 * kAmTab + tid + kTileThreads];
+  }
   // Donor masks.  Tile-local roots (cells without a receiver, and cells
   // whose receiver is outside the tile) point to themselves at distance 0;
   // every other cell points to its receiver at distance 1.
@@ -400,6 +407,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     }
     nxt[i] = (uint16_t)target;
     dp[i] = (uint8_t)dist;
+  }
+  if (!a.Kf) {
+    if (has_ft0) ftl[tid] = ft0;
+    if (has_ft1) ftl[tid + kTileThreads] = ft1;
   }
   __syncthreads();
 
@@ -495,10 +506,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
   // implicit update level by level from the root.  Each thread keeps its own
   // cells; F comes from the grid's table staged in LDS (scalar K, counts
   // below kAmTab) or is computed as in erosion_factor.
-  const int cmax = s_cmax;
+  const int cmax = min(s_cmax, kLocalDepthCap);
   // Levels of this thread's cells, one byte each, so that finding the cells
   // of a level takes register arithmetic only.
   static_assert(kCellsPerThread <= 8, "one byte per cell in a 64-bit word");
+  uint16_t* wlist = nxt + (tid >> 6) * (64 * kCellsPerThread);
   uint64_t my_levels = 0;
 #pragma unroll
   for (int t = 0; t < kCellsPerThread; ++t)
@@ -509,10 +521,20 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_step(StepArgs a) {
     for (int t = 0; t < kCellsPerThread; ++t)
       at_l |= (uint32_t)(((my_levels >> (8 * t)) & 0xFFu) == (uint64_t)l) << t;
     at_l &= clean_bits;
+    // The wave's cells of level l, compacted into its slice of nxt (free by
+    // now) and spread over its 64 lanes.
+    const int cnt = __popc(at_l);
+    const int incl = wave_inclusive_scan(cnt);
+    const int total = __shfl(incl, 63, 64);
+    int pos = incl - cnt;
     while (at_l) {
       const int t = __ffs(at_l) - 1;
       at_l &= at_l - 1;
-      const int i = tid + t * kTileThreads;
+      wlist[pos++] = (uint16_t)(tid + t * kTileThreads);
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int j = (tid & 63); j < total; j += 64) {
+      const int i = wlist[j];
       const int ly = i / kTW, lx = i % kTW;
       const int code = rc[(ly + 1) * kRW + (lx + 1)];
       if (code == kBase) continue;
