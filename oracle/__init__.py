@@ -68,6 +68,9 @@ def _declare(lib):
                                            _P, _P]
     lib.lemo_run_fixed_routing.restype = C.c_int
     lib.lemo_routing.argtypes = [C.POINTER(_Params), _P, _P, _P, _P, _P, C.c_int64, _P]
+    lib.lemo_mfd_run.argtypes = [C.POINTER(_Params), C.c_double, _P, _P, _P, C.c_int64, _P, _P,
+                                 _P]
+    lib.lemo_mfd_run.restype = C.c_int
     lib.lemo_routing.restype = C.c_int
     return lib
 
@@ -246,3 +249,21 @@ def routing(h, params: Params, lib=None):
                             _ptr(offsets), offsets.size, C.byref(nlev)))
     return dict(rec=rec, depth=depth, count=count,
                 offsets=offsets[: nlev.value + 1].copy(), nlevels=nlev.value)
+
+
+def mfd_run(h0, params: Params, steps: int, pexp: float = 1.0, K=None, U=None, lib=None):
+    """``steps`` time steps with multiple-flow-direction routing (section
+    "Multiple Flow Directions"): every strictly lower neighbour receives a
+    share of the flow proportional to slope**pexp.  Returns ``h`` and the last
+    step's drainage ``area`` (m^2), ``level`` (longest path to a root) and
+    ``nlevels``."""
+    lib = lib or load()
+    h = np.array(h0, dtype=np.float64, copy=True, order="C")
+    ny, nx = h.shape
+    area = np.empty((ny, nx), np.float64)
+    level = np.empty((ny, nx), np.int32)
+    nlev = C.c_int64(0)
+    p = params.c()
+    _check(lib.lemo_mfd_run(C.byref(p), float(pexp), _ptr(h), _ptr(_f64(K)), _ptr(_f64(U)),
+                            int(steps), _ptr(area), _ptr(level), C.byref(nlev)))
+    return dict(h=h, area=area, level=level, nlevels=nlev.value)

@@ -436,3 +436,156 @@ int lemo_routing(const lemo_params* p, const double* h, int32_t* rec_out,
   lemo_work_free(&w);
   return LEMO_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Multiple flow directions (section "Multiple Flow Directions", figure
+ * "Multiple-flow directions").  Every strictly lower neighbour of an
+ * interior cell is one of its receivers, and a cell can be processed only
+ * after all of its receivers.  The paper gives no rule for sharing the flow
+ * and keeps the multiple-receiver form of the stream power law out of its
+ * printed text; the readings taken here (also in the design notes):
+ *  - receiver k of cell c gets the share s_k = S_k^p / sum_j S_j^p of the
+ *    flow, S_k = (h_c - h_k)/dist_k (p = 1: in proportion to the slope);
+ *  - the drainage area of c is its own cell area plus, from every donor d,
+ *    d's share towards c times d's drainage area;
+ *  - erosion for n = 1 is backward Euler of dh_c/dt = U - sum_k K (s_k A_c)^m
+ *    S_k over the receivers, i.e. h_c' = (h0 + sum_k F_k h_k') /
+ *    (1 + sum_k F_k) with F_k = K dt (s_k A_c)^m / dist_k, the sums taken in
+ *    neighbour order;
+ *  - the level of a cell is 0 without receivers and otherwise one more than
+ *    the deepest level among its receivers (the longest path to a root), so
+ *    that every receiver lies on an earlier level.
+ * Flow only descends, so the oracle simply takes the cells in order of
+ * height: ascending puts every receiver before its donors, descending every
+ * donor before its receivers.
+ */
+static const double* lemo_sort_h;
+
+static int lemo_cmp_height(const void* a, const void* b) {
+  const int32_t i = *(const int32_t*)a, j = *(const int32_t*)b;
+  const double hi = lemo_sort_h[i], hj = lemo_sort_h[j];
+  if (hi < hj) return -1;
+  if (hi > hj) return 1;
+  return (i > j) - (i < j);
+}
+
+static double lemo_slope_pow(double s, double pexp) { return pexp == 1.0 ? s : pow(s, pexp); }
+
+static double lemo_area_pow(double a, double m) {
+  return m == 0.5 ? sqrt(a) : (m == 1.0 ? a : pow(a, m));
+}
+
+int lemo_mfd_step(const lemo_params* p, double pexp, double* h, const double* K,
+                  const double* U, double* area, int32_t* level, int64_t* nlevels_out) {
+  const int32_t ny = p->ny, nx = p->nx;
+  const int64_t n = (int64_t)ny * nx;
+  double dist[8];
+  lemo_distances(p->dx, p->dy, dist);
+  const double dxdy = p->dx * p->dy;
+  double* h0 = (double*)malloc(sizeof(double) * (size_t)n);
+  double* wsum = (double*)malloc(sizeof(double) * (size_t)n);
+  int32_t* nrec = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* ord = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!h0 || !wsum || !nrec || !ord) {
+    free(h0); free(wsum); free(nrec); free(ord);
+    return LEMO_E_ALLOC;
+  }
+  memcpy(h0, h, sizeof(double) * (size_t)n);
+  /* Receivers and the sum of their weights, from the step's starting heights. */
+  for (int32_t y = 0; y < ny; ++y)
+    for (int32_t x = 0; x < nx; ++x) {
+      const int64_t c = (int64_t)y * nx + x;
+      wsum[c] = 0.0;
+      nrec[c] = 0;
+      if (lemo_is_perimeter(ny, nx, y, x)) continue;
+      for (int k = 0; k < 8; ++k) {
+        const int64_t r = (int64_t)(y + LEMO_DY[k]) * nx + (x + LEMO_DX[k]);
+        if (h0[c] - h0[r] > 0.0) {
+          wsum[c] += lemo_slope_pow((h0[c] - h0[r]) / dist[k], pexp);
+          nrec[c] += 1;
+        }
+      }
+    }
+  for (int64_t i = 0; i < n; ++i) ord[i] = (int32_t)i;
+  lemo_sort_h = h0;
+  qsort(ord, (size_t)n, sizeof(int32_t), lemo_cmp_height);
+  /* Levels, ascending height. */
+  int32_t deepest = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t c = ord[i], y = c / nx, x = c % nx;
+    int32_t l = 0;
+    if (nrec[c] > 0)
+      for (int k = 0; k < 8; ++k) {
+        const int64_t r = (int64_t)(y + LEMO_DY[k]) * nx + (x + LEMO_DX[k]);
+        if (h0[c] - h0[r] > 0.0 && level[r] + 1 > l) l = level[r] + 1;
+      }
+    level[c] = l;
+    if (l > deepest) deepest = l;
+  }
+  /* Drainage areas, descending height: each cell pulls from its donors. */
+  for (int64_t i = n - 1; i >= 0; --i) {
+    const int32_t c = ord[i], y = c / nx, x = c % nx;
+    double acc = dxdy;
+    for (int k = 0; k < 8; ++k) {
+      const int32_t yy = y + LEMO_DY[k], xx = x + LEMO_DX[k];
+      if (yy < 0 || yy >= ny || xx < 0 || xx >= nx) continue;
+      if (lemo_is_perimeter(ny, nx, yy, xx)) continue;
+      const int64_t d = (int64_t)yy * nx + xx;
+      if (h0[d] - h0[c] > 0.0) {
+        const double share = lemo_slope_pow((h0[d] - h0[c]) / dist[k], pexp) / wsum[d];
+        acc += share * area[d];
+      }
+    }
+    area[c] = acc;
+  }
+  /* Uplift and erosion, ascending height (receivers first). */
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t c = ord[i], y = c / nx, x = c % nx;
+    if (lemo_is_perimeter(ny, nx, y, x)) continue;
+    const double hup = h0[c] + (U ? U[c] * p->dt : p->U * p->dt);
+    if (nrec[c] == 0) {
+      h[c] = hup;
+      continue;
+    }
+    const double kc = K ? K[c] : p->K;
+    double sumf = 0.0, sumfh = 0.0;
+    for (int k = 0; k < 8; ++k) {
+      const int64_t r = (int64_t)(y + LEMO_DY[k]) * nx + (x + LEMO_DX[k]);
+      if (h0[c] - h0[r] > 0.0) {
+        const double share = lemo_slope_pow((h0[c] - h0[r]) / dist[k], pexp) / wsum[c];
+        const double f = ((kc * p->dt) * lemo_area_pow(share * area[c], p->m)) / dist[k];
+        sumf += f;
+        sumfh += f * h[r];
+      }
+    }
+    h[c] = (hup + sumfh) / (1.0 + sumf);
+  }
+  if (nlevels_out) *nlevels_out = (int64_t)deepest + 1;
+  free(h0); free(wsum); free(nrec); free(ord);
+  return LEMO_OK;
+}
+
+int lemo_mfd_run(const lemo_params* p, double pexp, double* h, const double* K,
+                 const double* U, int64_t steps, double* area_out, int32_t* level_out,
+                 int64_t* nlevels_out) {
+  int st = lemo_check(p);
+  if (st != LEMO_OK) return st;
+  if (!h || steps < 0 || !(pexp > 0.0) || !isfinite(pexp) || p->n != 1.0) return LEMO_E_ARG;
+  const int64_t n = (int64_t)p->ny * p->nx;
+  double* area = (double*)malloc(sizeof(double) * (size_t)n);
+  int32_t* level = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!area || !level) {
+    free(area); free(level);
+    return LEMO_E_ALLOC;
+  }
+  int64_t nl = 0;
+  for (int64_t s = 0; s < steps && st == LEMO_OK; ++s)
+    st = lemo_mfd_step(p, pexp, h, K, U, area, level, &nl);
+  if (st == LEMO_OK && steps > 0) {
+    if (area_out) memcpy(area_out, area, sizeof(double) * (size_t)n);
+    if (level_out) memcpy(level_out, level, sizeof(int32_t) * (size_t)n);
+    if (nlevels_out) *nlevels_out = nl;
+  }
+  free(area); free(level);
+  return st;
+}

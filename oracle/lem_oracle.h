@@ -62,6 +62,15 @@ int lemo_routing(const lemo_params* p, const double* h, int32_t* rec_out,
                  int32_t* depth_out, uint32_t* count_out, int64_t* offsets_out,
                  int64_t offsets_cap, int64_t* nlevels_out);
 
+/* Multiple flow directions (section "Multiple Flow Directions"): one step
+ * and a run of `steps` steps with flow shared in proportion to slope^pexp;
+ * n must be 1.  area_out (m^2) and level_out describe the last step. */
+int lemo_mfd_step(const lemo_params* p, double pexp, double* h, const double* K,
+                  const double* U, double* area, int32_t* level, int64_t* nlevels_out);
+int lemo_mfd_run(const lemo_params* p, double pexp, double* h, const double* K,
+                 const double* U, int64_t steps, double* area_out, int32_t* level_out,
+                 int64_t* nlevels_out);
+
 #ifdef __cplusplus
 }
 #endif

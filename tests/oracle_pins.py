@@ -387,8 +387,105 @@ def pin_newton_step_solves_the_implicit_equation(lib):
     assert checked > 0
 
 
+def _mfd_receivers(h, dx, dy, pexp):
+    """Receivers and shares of every interior cell by the definition:
+    strictly lower neighbours, share proportional to slope**pexp."""
+    ny, nx = h.shape
+    out = {}
+    for y in range(1, ny - 1):
+        for x in range(1, nx - 1):
+            c = y * nx + x
+            recs = []
+            for k, (oy, ox) in enumerate(_NB):
+                r = (y + oy) * nx + (x + ox)
+                if h.flat[c] - h.flat[r] > 0:
+                    d = _dist(c, r, nx, dx, dy)
+                    recs.append((r, ((h.flat[c] - h.flat[r]) / d) ** pexp, d))
+            tot = sum(w for _, w, _ in recs)
+            out[c] = [(r, w / tot, d) for r, w, d in recs]
+    return out
+
+
+_NB = [(-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 1), (1, -1), (1, 0), (1, 1)]
+
+
+def pin_mfd_area_conservation_and_dense_solve(lib):
+    """Multiple flow directions: every cell's area ends at a cell without
+    receivers (shares sum to one), and the areas solve the linear system
+    A_c = dx dy + sum_d s_{d->c} A_d whatever the processing order."""
+    for seed, quant in ((1, None), (2, 3)):
+        ny, nx = 7, 9
+        h = (W.initial_heights(ny, nx, seed) if quant is None
+             else W.quantised_heights(ny, nx, quant, seed))
+        dx, dy, pexp = 30.0, 45.0, (1.0 if quant else 1.3)
+        p = oracle.Params(ny, nx, dx, dy, 1000.0, 0.5, 1.0, 1e-3, 0.0)
+        r = oracle.mfd_run(h, p, 1, pexp=pexp, lib=lib)
+        A = r["area"].ravel()
+        recs = _mfd_receivers(h, dx, dy, pexp)
+        roots = [c for c in range(ny * nx) if not recs.get(c)]
+        total = ny * nx * dx * dy
+        assert abs(sum(A[c] for c in roots) - total) <= 1e-12 * total
+        M = np.eye(ny * nx)
+        for d, lst in recs.items():
+            for c, s, _ in lst:
+                M[c, d] -= s
+        ref = np.linalg.solve(M, np.full(ny * nx, dx * dy))
+        assert np.allclose(A, ref, rtol=1e-12, atol=0)
+
+
+def pin_mfd_levels_are_longest_paths(lib):
+    """The level of a cell is the length of the longest descending path from
+    it to a cell without receivers (brute-force relaxation)."""
+    ny, nx = 8, 8
+    h = W.quantised_heights(ny, nx, 5, 9)
+    p = oracle.Params(ny, nx)
+    lev = oracle.mfd_run(h, p, 1, lib=lib)["level"].ravel()
+    recs = _mfd_receivers(h, 100.0, 100.0, 1.0)
+    ref = np.zeros(ny * nx, int)
+    for _ in range(ny * nx):
+        for c, lst in recs.items():
+            for r, _, _ in lst:
+                ref[c] = max(ref[c], ref[r] + 1)
+    assert np.array_equal(lev, ref)
+
+
+def pin_mfd_step_solves_the_implicit_system(lib):
+    """One step with K > 0: the new heights solve (1 + sum F) h_c - sum F_k
+    h_k = h_c + U dt (dense solve), F_k = K dt (s_k A_c)^m / d_k; cells
+    without receivers are only uplifted and the perimeter stays put."""
+    ny, nx = 7, 8
+    h = W.initial_heights(ny, nx, 4) * 20.0
+    dx, dy, pexp, m = 50.0, 40.0, 1.1, 0.45
+    p = oracle.Params(ny, nx, dx, dy, 3000.0, m, 1.0, 2e-3, 3e-5)
+    r = oracle.mfd_run(h, p, 1, pexp=pexp, lib=lib)
+    A = r["area"].ravel()
+    recs = _mfd_receivers(h, dx, dy, pexp)
+    n = ny * nx
+    M = np.eye(n)
+    rhs = h.ravel().copy()
+    for c, lst in recs.items():
+        rhs[c] += p.U * p.dt
+        for rr, s, d in lst:
+            f = p.K * p.dt * (s * A[c]) ** m / d
+            M[c, c] += f
+            M[c, rr] -= f
+    ref = np.linalg.solve(M, rhs)
+    assert np.allclose(r["h"].ravel(), ref, rtol=1e-12, atol=1e-12)
+
+
+def pin_mfd_without_erosion_is_pure_uplift(lib):
+    h = W.initial_heights(9, 11, 5)
+    p = oracle.Params(9, 11, K=0.0, U=2e-3)
+    got = oracle.mfd_run(h, p, 3, lib=lib)["h"]
+    ref = h.copy()
+    ref[1:-1, 1:-1] += 3 * (2e-3 * 1000.0)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12)
+
+
 ALL_PINS = [pin_table1, pin_receivers_special_cases, pin_receivers_brute_force,
             pin_levels_and_areas_brute_force, pin_forest_invariants, pin_one_step_dense_solve,
             pin_no_erosion_is_pure_uplift, pin_long_step_follows_receiver,
             pin_steady_state_slope_area, pin_channel_profile, pin_newton_matches_closed_form,
-            pin_newton_channel_profile, pin_newton_step_solves_the_implicit_equation]
+            pin_newton_channel_profile, pin_newton_step_solves_the_implicit_equation,
+            pin_mfd_area_conservation_and_dense_solve, pin_mfd_levels_are_longest_paths,
+            pin_mfd_step_solves_the_implicit_system, pin_mfd_without_erosion_is_pure_uplift]

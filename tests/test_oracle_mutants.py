@@ -44,6 +44,10 @@ MUTANTS = [
      "(hnew - h0 - f * pow(g, nexp))"),
     ("Newton stops after one iteration", "fabs(delta) > eps && it < max_iter",
      "fabs(delta) > eps && it < 1"),
+    ("MFD shares not normalised", "pexp) / wsum[d];", "pexp);"),
+    ("MFD erosion with the old receiver height", "sumfh += f * h[r];", "sumfh += f * h0[r];"),
+    ("MFD levels by the shallowest receiver", "if (h0[c] - h0[r] > 0.0 && level[r] + 1 > l) l = level[r] + 1;",
+     "if (h0[c] - h0[r] > 0.0 && (l == 0 || level[r] + 1 < l)) l = level[r] + 1;"),
 ]
 
 
