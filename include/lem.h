@@ -123,6 +123,33 @@ size_t lem_workspace_bytes(const lem_params* p);
 lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes,
                       void* hip_stream, lem_ctx** out);
 
+/* Multiple flow directions (section "Multiple Flow Directions"; figure
+ * "Multiple-flow directions").  Every strictly lower neighbour of an
+ * interior cell is one of its receivers and gets the share S^p / sum_j S_j^p
+ * of the cell's flow, S = (h_c - h_k)/dist_k the slope towards it and p =
+ * `exponent` (> 0; 1 shares in proportion to the slope).  A cell's level is
+ * the longest descending path from it to a cell without receivers, so every
+ * receiver is processed before its donors.  Drainage area: own cell area
+ * plus each donor's share of its area.  Erosion (n = 1 only): backward Euler
+ * of dh_c/dt = U - sum_k K (s_k A_c)^m S_k over the receivers, i.e.
+ * h_c' = (h0 + sum_k F_k h_k') / (1 + sum_k F_k), F_k = K dt (s_k A_c)^m /
+ * dist_k, sums in neighbour order.  The paper gives no sharing rule; this
+ * one follows the slope-weighted routers it cites.
+ *
+ * lem_mfd_workspace_bytes: as lem_workspace_bytes (0 also for n != 1).
+ * lem_mfd_create: as lem_create for a single grid routed this way; lem_run
+ *   (with optional K and U fields), lem_sync, lem_stats, lem_set_tuning and
+ *   lem_destroy work on it; lem_run_fixed_routing and lem_routing return
+ *   LEM_E_ARG.  LEM_E_ARG for n != 1 or an exponent that is not finite and > 0.
+ * lem_mfd_export: drainage area (m^2, FP64, ny*nx) and level per cell of the
+ *   last step to device arrays (either may be NULL); *h_nlevels (may be NULL)
+ *   receives the number of levels.  Synchronizes the stream.  LEM_E_STATE
+ *   before the first step, LEM_E_ARG on a D8 context. */
+size_t lem_mfd_workspace_bytes(const lem_params* p);
+lem_status lem_mfd_create(const lem_params* p, double exponent, void* d_workspace,
+                          size_t ws_bytes, void* hip_stream, lem_ctx** out);
+lem_status lem_mfd_export(lem_ctx* ctx, double* d_area, int32_t* d_level, int64_t* h_nlevels);
+
 /* Enqueues `steps` time steps (Steps 2 to 7, repeated) on d_h, updated in
  * place.  d_K and d_U are optional per-cell fields (NULL: use p->K, p->U),
  * read-only, ny*nx doubles each.  Each step routes flow on the heights it

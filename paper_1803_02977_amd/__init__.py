@@ -5,4 +5,4 @@ The computation lives in hand-written HIP kernels behind the C ABI declared in
 ``include/lem.h`` (``liblem.so``); ``lem`` is its ctypes binding.
 """
 from .lem import *  # noqa: F401,F403
-from .lem import Batch, Solver, LemError, load, EXPORTS  # noqa: F401
+from .lem import Batch, MfdSolver, Solver, LemError, load, EXPORTS  # noqa: F401

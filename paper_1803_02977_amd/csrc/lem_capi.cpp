@@ -16,6 +16,8 @@
 struct lem_ctx {
   uint32_t flags;
   bool batch;                       // created by lem_batch_create
+  bool mfd;                         // created by lem_mfd_create (multiple flow directions)
+  double mfd_p;                     // exponent of the slope in the flow shares
   std::vector<lem::GridDev> grids;  // host copy of the grid descriptors
   std::vector<int32_t> tiles;       // all tiles, in order
   std::vector<int32_t> active;      // tiles of unfinished grids (steady-state driver)
@@ -158,6 +160,8 @@ lem::StepArgs make_args(const lem_ctx* ctx, const double* d_K, const double* d_U
   a.w = ctx->w;
   a.tail_level = ctx->tail_level;
   a.pergrid = ctx->pergrid ? 1 : 0;
+  a.mfd = ctx->mfd ? 1 : 0;
+  a.mfd_p = ctx->mfd_p;
   return a;
 }
 
@@ -201,6 +205,20 @@ int pergrid_threads(const lem_ctx* ctx) {
 
 // One step: the tile pass, then the global level pass for crossing trees.
 lem_status step(lem_ctx* ctx, lem::StepArgs& a, bool timers) {
+  if (ctx->mfd) {
+    if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
+    hipError_t e = lem::launch_mfd_step(a, ctx->grid, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "multiple-flow-direction launch");
+    if (timers) {
+      (void)hipEventRecord(ctx->ev2, ctx->stream);
+      e = hipEventSynchronize(ctx->ev2);
+      if (e != hipSuccess) return hip_fail(ctx, e, "timer event");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ctx->ev1, ctx->ev2);
+      ctx->order_ms += ms;
+    }
+    return LEM_OK;
+  }
   if (timers) (void)hipEventRecord(ctx->ev0, ctx->stream);
   hipError_t e = lem::launch_tile_step(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "tile launch");
@@ -236,6 +254,8 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
   if (!d_h) return fail(ctx, LEM_E_ARG, "d_h is NULL");
   if (steps < 0) return fail(ctx, LEM_E_ARG, "steps must be >= 0");
   if (steps == 0) return LEM_OK;
+  if (ctx->mfd && d_rcode)
+    return fail(ctx, LEM_E_ARG, "fixed routing needs a D8 context");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (ctx->flags & LEM_F_VALIDATE) {
@@ -277,15 +297,20 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
 lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* hip_stream) {
   const int64_t ng = (int64_t)ctx->grids.size();
   if (!d_workspace || ((uintptr_t)d_workspace & 255u) != 0) return LEM_E_WORKSPACE;
-  if (ws_bytes < lem::workspace_bytes(ctx->cells, ng, ctx->ntiles)) return LEM_E_WORKSPACE;
+  if (ws_bytes < lem::workspace_bytes(ctx->cells, ng, ctx->ntiles, ctx->mfd)) return LEM_E_WORKSPACE;
   ctx->stream = (hipStream_t)hip_stream;
-  lem::carve(d_workspace, ctx->cells, ng, ctx->ntiles, &ctx->w);
+  lem::carve(d_workspace, ctx->cells, ng, ctx->ntiles, &ctx->w, ctx->mfd);
   ctx->tiles.resize(ctx->ntiles);
   for (int32_t t = 0; t < ctx->ntiles; ++t) ctx->tiles[t] = t;
   hipError_t e = hipGetDevice(&ctx->device);
   int cus = 0, per_cu = 0, rate = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
   if (e == hipSuccess) e = lem::global_kernel_occupancy(&per_cu);
+  if (e == hipSuccess && ctx->mfd) {
+    int per_cu_mfd = 0;
+    e = lem::mfd_kernel_occupancy(&per_cu_mfd);
+    if (per_cu_mfd < per_cu) per_cu = per_cu_mfd;
+  }
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, ctx->device);
   if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
   if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
@@ -316,6 +341,7 @@ lem_status routing_impl(lem_ctx* ctx, int32_t g, int32_t* d_rec, int32_t* d_dept
                         uint32_t* d_count, int64_t* h_level_offsets, int64_t cap,
                         int64_t* h_nlevels) {
   if (!ctx) return LEM_E_ARG;
+  if (ctx->mfd) return fail(ctx, LEM_E_ARG, "multiple-flow-direction routing: use lem_mfd_export");
   if (!ctx->has_routing) return fail(ctx, LEM_E_STATE, "no lem_run/lem_batch_run step yet");
   if (cap < 0) return fail(ctx, LEM_E_ARG, "cap must be >= 0");
   if (g < 0 || g >= (int32_t)ctx->grids.size()) return fail(ctx, LEM_E_ARG, "no such grid");
@@ -577,6 +603,65 @@ lem_status lem_batch_routing(lem_ctx* ctx, int32_t grid, int32_t* d_rec, int32_t
                              uint32_t* d_count, int64_t* h_level_offsets, int64_t cap,
                              int64_t* h_nlevels) {
   return routing_impl(ctx, grid, d_rec, d_depth, d_count, h_level_offsets, cap, h_nlevels);
+}
+
+size_t lem_mfd_workspace_bytes(const lem_params* p) {
+  std::string why;
+  if (check_params(p, &why) != LEM_OK || p->n != 1.0) return 0;
+  lem::GridDev g = make_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->U, p->K, p->n, p->eps,
+                             p->max_newton, 0, 0);
+  return lem::workspace_bytes((int64_t)p->ny * p->nx, 1, grid_tiles(g), true);
+}
+
+lem_status lem_mfd_create(const lem_params* p, double exponent, void* d_workspace,
+                          size_t ws_bytes, void* hip_stream, lem_ctx** out) {
+  if (!out) return LEM_E_ARG;
+  *out = nullptr;
+  std::string why;
+  lem_status st = check_params(p, &why);
+  if (st != LEM_OK) return st;
+  if (p->n != 1.0) return LEM_E_ARG;
+  if (!(exponent > 0.0) || !std::isfinite(exponent)) return LEM_E_ARG;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255u) != 0) return LEM_E_WORKSPACE;
+  if (ws_bytes < lem_mfd_workspace_bytes(p)) return LEM_E_WORKSPACE;
+  lem_ctx* ctx = new (std::nothrow) lem_ctx();
+  if (!ctx) return LEM_E_ARG;
+  ctx->flags = p->flags;
+  ctx->batch = false;
+  ctx->mfd = true;
+  ctx->mfd_p = exponent;
+  ctx->grids.push_back(make_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->U, p->K, p->n,
+                                 p->eps, p->max_newton, 0, 0));
+  ctx->cells = (int64_t)p->ny * p->nx;
+  ctx->ntiles = grid_tiles(ctx->grids[0]);
+  st = create_impl(ctx, d_workspace, ws_bytes, hip_stream);
+  if (st != LEM_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return LEM_OK;
+}
+
+lem_status lem_mfd_export(lem_ctx* ctx, double* d_area, int32_t* d_level, int64_t* h_nlevels) {
+  if (!ctx) return LEM_E_ARG;
+  if (!ctx->mfd) return fail(ctx, LEM_E_ARG, "not a multiple-flow-direction context");
+  if (!ctx->has_routing) return fail(ctx, LEM_E_STATE, "no lem_run step yet");
+  hipError_t e = hipSetDevice(ctx->device);
+  const size_t n = (size_t)ctx->cells;
+  if (e == hipSuccess && d_area)
+    e = hipMemcpyAsync(d_area, ctx->w.area, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+  if (e == hipSuccess && d_level)
+    e = hipMemcpyAsync(d_level, ctx->w.dep_g, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+  lem::Ctrl ct;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&ct, ctx->w.ctrl, sizeof(ct), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "export");
+  if (h_nlevels) *h_nlevels = ct.nlevels;
+  return LEM_OK;
 }
 
 lem_status lem_level_history(lem_ctx* ctx, int32_t* h_levels, int64_t cap, int64_t* h_n) {

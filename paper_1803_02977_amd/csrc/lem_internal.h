@@ -106,6 +106,7 @@ struct Work {
   int32_t* gcnt;     // [ngrids] per-grid level pass: crossing roots queued per grid
   int32_t* gnl;      // [ngrids] per-grid level pass: levels of the crossing trees
   int32_t* gtot;     // [ngrids] per-grid level pass: cells of the crossing trees
+  double* area;      // [N] multiple flow directions: drainage area (null otherwise)
   Ctrl* ctrl;
   int32_t* scratch;  // [kScratchInts] reductions (validation)
 };
@@ -130,16 +131,23 @@ struct StepArgs {
   int32_t export_routing;  // write per-cell codes, levels and counts
   int32_t tail_level;    // levels smaller than this run in one workgroup
   int32_t pergrid;       // crossing trees: one workgroup per grid (else the global pass)
+  int32_t mfd;           // multiple flow directions (single grid)
+  int32_t pad2;
+  double mfd_p;          // exponent of the slope in the flow shares
 };
 
-size_t workspace_bytes(int64_t n, int64_t ngrids, int64_t ntiles);
-void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w);
+size_t workspace_bytes(int64_t n, int64_t ngrids, int64_t ntiles, bool mfd = false);
+void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w, bool mfd = false);
 
 hipError_t launch_begin_run(const StepArgs& a, hipStream_t s);
 hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user_rcode, hipStream_t s);
 hipError_t launch_tile_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s);
+// Multiple flow directions: routing, then levels, areas and heights in one
+// cooperative launch of `grid` workgroups.
+hipError_t launch_mfd_step(const StepArgs& a, int grid, hipStream_t s);
+hipError_t mfd_kernel_occupancy(int* blocks_per_cu);
 // Routing export of grid g (its cells [offset, offset + ny*nx)).
 hipError_t launch_export(const StepArgs& a, int g, int64_t offset, int64_t cells, int32_t* rec,
                          int32_t* depth, uint32_t* count, hipStream_t s);

@@ -1059,6 +1059,223 @@ __global__ __launch_bounds__(1024) void k_grid_levels_finish(StepArgs a) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Multiple flow directions (section "Multiple Flow Directions"): every
+// strictly lower neighbour is a receiver and gets the share
+// S^p / sum_j S_j^p of the flow (S = slope to it); a cell is processed only
+// after all of its receivers, so its level is the longest path to a root.
+// Single grid, global memory, level-synchronous.  Workspace reuse: par holds
+// the receivers still to be processed per cell, hq the sum of the weights
+// per cell (both in grid order), area the drainage area.
+
+__device__ __forceinline__ double slope_pow(double s, double p) { return p == 1.0 ? s : pow(s, p); }
+
+__device__ __forceinline__ double class_dist(const GridDev& G, int k) {
+  const int cls = code_class(k);
+  return cls == 0 ? G.dy : (cls == 1 ? G.dx : G.ddiag);
+}
+
+// Receivers, weight sums and counters; roots (no receiver) queued as level 0.
+__global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
+  __shared__ int wsum[256 / 64];
+  __shared__ int s_base;
+  const Work w = a.w;
+  const GridDev& G = a.grids[0];
+  const int ny = G.ny, nx = G.nx;
+  const int64_t n = (int64_t)ny * nx;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+    const int64_t c = base + threadIdx.x;
+    int root = 0;
+    if (c < n) {
+      const int y = (int)(c / nx), x = (int)(c % nx);
+      double wsum_c = 0.0;
+      int nrec = 0;
+      if (y > 0 && x > 0 && y < ny - 1 && x < nx - 1) {
+        const double hc = a.h_in[c];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const double hr = a.h_in[c + neighbour_offset(k, nx)];
+          if (hc - hr > 0.0) {
+            wsum_c += slope_pow((hc - hr) / class_dist(G, k), a.mfd_p);
+            ++nrec;
+          }
+        }
+      }
+      w.par[c] = nrec;
+      w.hq[c] = wsum_c;
+      root = nrec == 0;
+      if (root && a.export_routing) w.dep_g[c] = 0;
+    }
+    int tot;
+    const int pre = block_exclusive_scan<256>(root, wsum, &tot);
+    if (threadIdx.x == 0) s_base = tot ? atomicAdd(&w.lcnt[0], tot) : 0;
+    __syncthreads();
+    if (root) w.q[s_base + pre] = (int32_t)c;
+    __syncthreads();
+  }
+}
+
+// Level L -> L+1: every processed cell releases its donors; a donor whose
+// last receiver this was joins the next level.
+__device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L, int wg, int nwg,
+                           int* wsum, int* s_base) {
+  const Work& w = a.w;
+  const GridDev& G = a.grids[0];
+  const int ny = G.ny, nx = G.nx;
+  const int tid = threadIdx.x;
+  for (int64_t base = lo + (int64_t)wg * kChunk; base < hi; base += (int64_t)nwg * kChunk) {
+    uint32_t ready[kItems];
+    int32_t cs[kItems];
+    int cntv = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = base + (int64_t)j * kBlock + tid;
+      ready[j] = 0;
+      cs[j] = 0;
+      if (i < hi) {
+        const int32_t c = w.q[i];
+        cs[j] = c;
+        const int y = c / nx, x = c % nx;
+        const double hc = a.h_in[c];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int yy = y + code_dy(k), xx = x + code_dx(k);
+          if (yy <= 0 || xx <= 0 || yy >= ny - 1 || xx >= nx - 1) continue;  // perimeter or outside
+          const int32_t d = c + (int32_t)neighbour_offset(k, nx);
+          if (a.h_in[d] - hc > 0.0 && atomicSub(&w.par[d], 1) == 1) ready[j] |= 1u << k;
+        }
+        cntv += __popc(ready[j]);
+      }
+    }
+    int tot;
+    const int pre = block_exclusive_scan<kBlock>(cntv, wsum, &tot);
+    if (tid == 0) *s_base = tot ? atomicAdd(&w.lcnt[L + 1], tot) : 0;
+    __syncthreads();
+    int32_t pos = hi + *s_base + pre;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      uint32_t m = ready[j];
+      while (m) {
+        const int k = __ffs(m) - 1;
+        m &= m - 1;
+        const int32_t d = cs[j] + (int32_t)neighbour_offset(k, nx);
+        w.q[pos++] = d;
+        if (a.export_routing) w.dep_g[d] = L + 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Step 5: drainage area of the cells of one level, pulled from their donors
+// in neighbour order.
+__device__ void mfd_area_level(const StepArgs& a, int32_t a0, int32_t a1, int wg, int nwg) {
+  const Work& w = a.w;
+  const GridDev& G = a.grids[0];
+  const int ny = G.ny, nx = G.nx;
+  for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1; i += (int64_t)nwg * kBlock) {
+    const int32_t c = w.q[i];
+    const int y = c / nx, x = c % nx;
+    const double hc = a.h_in[c];
+    double acc = G.dxdy;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int yy = y + code_dy(k), xx = x + code_dx(k);
+      if (yy <= 0 || xx <= 0 || yy >= ny - 1 || xx >= nx - 1) continue;
+      const int32_t d = c + (int32_t)neighbour_offset(k, nx);
+      const double hd = a.h_in[d];
+      if (hd - hc > 0.0) {
+        const double share = slope_pow((hd - hc) / class_dist(G, k), a.mfd_p) / w.hq[d];
+        acc += share * w.area[d];
+      }
+    }
+    w.area[c] = acc;
+  }
+}
+
+// Steps 6-7 for the cells of one level: uplift, then the implicit update
+// with all receivers, h' = (h0 + sum F_k h_k') / (1 + sum F_k).
+__device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int wg, int nwg) {
+  const Work& w = a.w;
+  const GridDev& G = a.grids[0];
+  const int ny = G.ny, nx = G.nx;
+  for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1; i += (int64_t)nwg * kBlock) {
+    const int32_t c = w.q[i];
+    const int y = c / nx, x = c % nx;
+    const double hc = a.h_in[c];
+    if (y == 0 || x == 0 || y == ny - 1 || x == nx - 1) {
+      a.h_out[c] = hc;
+      continue;
+    }
+    const double hup = hc + (a.Uf ? a.Uf[c] * G.dt : G.udt);
+    const double wc = w.hq[c];
+    const double ac = w.area[c];
+    const double kdt = (a.Kf ? a.Kf[c] : G.K) * G.dt;
+    double sumf = 0.0, sumfh = 0.0;
+    int nrec = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int32_t r = c + (int32_t)neighbour_offset(k, nx);
+      const double hr = a.h_in[r];
+      if (hc - hr > 0.0) {
+        const double dk = class_dist(G, k);
+        const double share = slope_pow((hc - hr) / dk, a.mfd_p) / wc;
+        const double f = (kdt * area_power_call(share * ac, G.use_sqrt, G.m)) / dk;
+        sumf += f;
+        sumfh += f * a.h_out[r];
+        ++nrec;
+      }
+    }
+    a.h_out[c] = nrec ? (hup + sumfh) / (1.0 + sumf) : hup;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
+  __shared__ int wsum[kBlock / 64];
+  __shared__ int s_base;
+  const Work w = a.w;
+  Ctrl* ct = w.ctrl;
+  const int wg = blockIdx.x, nwg = gridDim.x;
+  const bool lead = (wg == 0 && threadIdx.x == 0);
+  int32_t lo = 0, hi = load_acquire(&w.lcnt[0]), L = 0;
+  if (lead) w.lev[0] = 0;
+  while (true) {
+    if (lead) {
+      w.lev[L + 1] = hi;
+      w.lcnt[L + 2] = 0;
+    }
+    mfd_expand(a, lo, hi, L, wg, nwg, wsum, &s_base);
+    grid_barrier(ct);
+    const int32_t added = load_acquire(&w.lcnt[L + 1]);
+    if (added == 0) break;
+    lo = hi;
+    hi += added;
+    ++L;
+  }
+  for (int32_t l = L; l >= 0; --l) {
+    mfd_area_level(a, w.lev[l], w.lev[l + 1], wg, nwg);
+    grid_barrier(ct);
+  }
+  for (int32_t l = 0; l <= L; ++l) {
+    mfd_erode_level(a, w.lev[l], w.lev[l + 1], wg, nwg);
+    if (l < L) grid_barrier(ct);
+  }
+  if (lead) {
+    const int32_t nl = L + 1;
+    ct->nlevels = nl;
+    ct->dirty_total = hi;
+    ct->dirty_nlevels = nl;
+    ct->crossing_run += hi;
+    if (nl > ct->max_nlevels) ct->max_nlevels = nl;
+    if (a.step < kHistCap) w.hist[a.step] = nl;
+    ct->steps = a.step + 1;
+    if ((int64_t)hi != (int64_t)a.n) atomicMax(&ct->status, 5);
+    w.lcnt[0] = 0;
+    w.lcnt[1] = 0;
+  }
+}
+
 // Start of a run: tabulate A^m, F and 1 + F per grid (block g does grid g)
 // and reset the control block.
 __global__ void k_begin_run(StepArgs a) {
@@ -1197,15 +1414,13 @@ __global__ __launch_bounds__(256) void k_validate(const double* x, int64_t n, in
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
-void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w);
-
-size_t workspace_bytes(int64_t n, int64_t ngrids, int64_t ntiles) {
+size_t workspace_bytes(int64_t n, int64_t ngrids, int64_t ntiles, bool mfd) {
   Work w;
-  carve(nullptr, n, ngrids, ntiles, &w);
+  carve(nullptr, n, ngrids, ntiles, &w, mfd);
   return (size_t)(uintptr_t)w.scratch + (size_t)align256(4 * kScratchInts);
 }
 
-void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w) {
+void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w, bool mfd) {
   char* p = (char*)base;
   auto take = [&](int64_t bytes) { char* r = p; p += align256(bytes); return (void*)r; };
   w->h2 = (double*)take(8 * n);
@@ -1234,6 +1449,7 @@ void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w) {
   w->gcnt = (int32_t*)take(4 * ngrids);
   w->gnl = (int32_t*)take(4 * ngrids);
   w->gtot = (int32_t*)take(4 * ngrids);
+  w->area = mfd ? (double*)take(8 * n) : nullptr;
   w->ctrl = (Ctrl*)take(sizeof(Ctrl));
   w->scratch = (int32_t*)take(4 * kScratchInts);
 }
@@ -1264,6 +1480,23 @@ hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_grid_levels_finish, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_mfd_step(const StepArgs& a, int grid, hipStream_t s) {
+  const int64_t n = a.n;
+  const unsigned blocks = (unsigned)(n < 256 * 2048 ? (n + 255) / 256 : 2048);
+  hipLaunchKernelGGL(k_mfd_route, dim3(blocks), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  StepArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel((const void*)k_mfd_levels, dim3(grid), dim3(kBlock), args, 0,
+                                    s);
+}
+
+hipError_t mfd_kernel_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_mfd_levels,
+                                                      kBlock, 0);
 }
 
 hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s) {

@@ -23,7 +23,8 @@ EXPORTS = ("lem_workspace_bytes", "lem_create", "lem_run", "lem_run_fixed_routin
            "lem_sync", "lem_routing", "lem_batch_workspace_bytes", "lem_batch_create",
            "lem_batch_run", "lem_batch_run_to_steady", "lem_batch_routing",
            "lem_level_history", "lem_stats", "lem_set_tuning", "lem_get_tuning", "lem_destroy",
-           "lem_status_str", "lem_last_error")
+           "lem_status_str", "lem_last_error", "lem_mfd_workspace_bytes", "lem_mfd_create",
+           "lem_mfd_export")
 
 
 class lem_params(C.Structure):
@@ -108,6 +109,13 @@ def load(path: str = LIB_PATH):
     lib.lem_get_tuning.restype = C.c_int
     lib.lem_destroy.argtypes = [_P]
     lib.lem_destroy.restype = C.c_int
+    lib.lem_mfd_workspace_bytes.argtypes = [C.POINTER(lem_params)]
+    lib.lem_mfd_workspace_bytes.restype = C.c_size_t
+    lib.lem_mfd_create.argtypes = [C.POINTER(lem_params), C.c_double, _P, C.c_size_t, _P,
+                                   C.POINTER(_P)]
+    lib.lem_mfd_create.restype = C.c_int
+    lib.lem_mfd_export.argtypes = [_P, _P, _P, C.POINTER(C.c_int64)]
+    lib.lem_mfd_export.restype = C.c_int
     lib.lem_status_str.argtypes = [C.c_int]
     lib.lem_status_str.restype = C.c_char_p
     lib.lem_last_error.argtypes = [_P]
@@ -453,6 +461,79 @@ class Batch:
 
     def stats(self) -> lem_stats_t:
         return lem_stats(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lem_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lem_mfd_workspace_bytes(p: lem_params) -> int:
+    return int(load().lem_mfd_workspace_bytes(C.byref(p)))
+
+
+class MfdSolver:
+    """Multiple-flow-direction routing (``lem_mfd_create``) for torch tensors:
+    ``run(h, steps, K=None, U=None)`` updates ``h`` in place, ``export()``
+    returns the last step's drainage area, levels and level count."""
+
+    def __init__(self, ny, nx, dx=100.0, dy=100.0, dt=1000.0, m=0.5, U=5e-4, K=1e-5,
+                 exponent=1.0, flags=0, device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self.params = lem_params(ny, nx, dx, dy, dt, m, 1.0, U, K, 1e-12, 100, flags)
+        nbytes = lem_mfd_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise LemError(LEM_E_ARG, "invalid parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        ctx = _P()
+        _check(load().lem_mfd_create(C.byref(self.params), float(exponent),
+                                     _P(self.workspace.data_ptr()), nbytes,
+                                     _P(self.stream.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx.value
+        self.shape = (ny, nx)
+
+    def _check_f(self, name, t):
+        torch = self.torch
+        if t is None:
+            return None
+        if (t.dtype != torch.float64 or tuple(t.shape) != self.shape or not t.is_contiguous()
+                or t.device != self.device):
+            raise LemError(LEM_E_ARG, f"{name} must be a contiguous float64 {self.shape} tensor "
+                                      f"on {self.device}")
+        return t.data_ptr()
+
+    def run(self, h, steps, K=None, U=None):
+        _check(load().lem_run(self.ctx, self._check_f("h", h), self._check_f("K", K),
+                              self._check_f("U", U), int(steps)), self.ctx)
+
+    def sync(self):
+        lem_sync(self.ctx)
+
+    def export(self):
+        torch = self.torch
+        area = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        level = torch.empty(self.shape, dtype=torch.int32, device=self.device)
+        nl = C.c_int64()
+        _check(load().lem_mfd_export(self.ctx, _P(area.data_ptr()), _P(level.data_ptr()),
+                                     C.byref(nl)), self.ctx)
+        return dict(area=area, level=level, nlevels=nl.value)
+
+    def stats(self) -> lem_stats_t:
+        return lem_stats(self.ctx)
+
+    def set_tuning(self, global_workgroups=0, tail_level=0):
+        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level, 0, 0))
+        t = lem_get_tuning(self.ctx)
+        return dict(global_workgroups=t.global_workgroups)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -150,3 +150,22 @@ def test_stored_warm_start_weights_have_the_network_shape():
     from paper_1803_02977_amd import surrogate as sur, warmstart as WS
     p = sur.load_params(WS.WEIGHTS_PATH)
     assert p.shape == (sur.param_count(),) and np.all(np.isfinite(p))
+
+
+def test_mfd_workspace_and_arguments_are_checked_on_the_host():
+    p = _params()
+    d8 = lem.lem_workspace_bytes(p)
+    mfd = lem.lem_mfd_workspace_bytes(p)
+    assert mfd >= d8 + 8 * 256 * 256  # one more FP64 array per cell
+    assert lem.lem_mfd_workspace_bytes(_params(n=2.0)) == 0
+    lib = pkg.load()
+    ctx = C.c_void_p()
+    for exponent in (0.0, -1.0, float("nan"), float("inf")):
+        assert lib.lem_mfd_create(C.byref(p), exponent, C.c_void_p(1 << 20), 1 << 40, None,
+                                  C.byref(ctx)) == lem.LEM_E_ARG
+    q = _params(n=2.0)
+    assert lib.lem_mfd_create(C.byref(q), 1.0, C.c_void_p(1 << 20), 1 << 40, None,
+                              C.byref(ctx)) == lem.LEM_E_ARG
+    assert lib.lem_mfd_create(C.byref(p), 1.0, C.c_void_p(4096), mfd - 1, None,
+                              C.byref(ctx)) == lem.LEM_E_WORKSPACE
+    assert lib.lem_mfd_export(None, None, None, None) == lem.LEM_E_ARG
