@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=W.LARGE_10000.name,
-                    choices=sorted(W.WORKLOADS) + [BATCH_NAME, SWEEP_NAME, WARM_NAME, NET_NAME])
+                    choices=sorted(W.WORKLOADS) + [BATCH_NAME, SWEEP_NAME, WARM_NAME, NET_NAME,
+                                                   MFD_NAME])
     ap.add_argument("--grids", type=int, default=100, help="held-out grids (warm-start workload)")
     ap.add_argument("--plain-sample", type=int, default=10,
                     help="warm-start workload: realizations timed through the plain solver")
@@ -91,6 +92,15 @@ BATCH_NAME = "batch-512-realizations-fp64"
 SWEEP_NAME = "size-sweep-100-16000"
 WARM_NAME = "warmstart-100x256x256-fp64"
 NET_NAME = "warmstart-network-b16-256x256-bf16"
+MFD_NAME = "mfd-10000x10000-fp64"
+# Algorithmic bytes per cell-update of a multiple-flow-direction step:
+# routing (k_mfd_route: read h, write the receiver counter and weight sum:
+# 20 B), then k_mfd_levels: levels (queue read and append, counter update,
+# h: 24 B), areas (queue, h, donors' weight sums and areas, area write:
+# 36 B), erosion (queue, h, weight sum, area, new height written and read as
+# a receiver's: 44 B).
+ALG_BYTES_MFD_ROUTE = 20
+ALG_BYTES_MFD_LEVELS = 104
 # Square edge lengths of the size sweep; the regions (upper edge length)
 # follow the GPU scaling table of the paper (section on GPU performance),
 # whose wall-time exponents x (wall ~ N^x) are quoted beside the fit.
@@ -307,6 +317,75 @@ def _network_throughput(net, dev, side, steps=20):
             "bwd_flop": bwd}
 
 
+def bench_mfd(args):
+    """Multiple-flow-direction routing on the 10000 x 10000 workload (same
+    grid, parameters and initial heights as the default benchmark, flow
+    shared in proportion to the slope)."""
+    import torch
+
+    from paper_1803_02977_amd import LEM_F_PHASE_TIMERS, MfdSolver
+    w = W.LARGE_10000
+    steps = args.steps or 10
+    dev = torch.device("cuda:0")
+    h0 = torch.from_numpy(W.initial_heights(w.ny, w.nx, args.seed)).to(dev)
+    h = h0.clone()
+    s = MfdSolver(w.ny, w.nx, w.dx, w.dy, w.dt, w.m, w.U, w.K, device=dev)
+    if args.warmup > 0:
+        s.run(h, args.warmup)
+        s.sync()
+    h.copy_(h0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.run(h, steps)
+    e1.record(s.stream)
+    s.sync()
+    ms = e0.elapsed_time(e1)
+    nl = s.export()["nlevels"]
+    s.close()
+    # Phase timers synchronise after every step: a run of its own, not the timed one.
+    st = MfdSolver(w.ny, w.nx, w.dx, w.dy, w.dt, w.m, w.U, w.K, flags=LEM_F_PHASE_TIMERS,
+                   device=dev)
+    h.copy_(h0)
+    st.run(h, steps)
+    st.sync()
+    stats = st.stats()
+    route_ms, levels_ms = stats.kernel_ms[0] / steps, stats.kernel_ms[1] / steps
+    phases = {"levels": stats.phase_ms[1] / steps, "areas": stats.phase_ms[2] / steps,
+              "erosion": stats.phase_ms[3] / steps}
+    st.close()
+    cells = w.cells
+    achieved = ALG_BYTES_MFD_LEVELS * cells / (levels_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        side, csteps = 2048, 3
+        hc = W.initial_heights(side, side, args.seed)
+        p = oracle.Params(side, side, w.dx, w.dy, w.dt, w.m, 1.0, w.U, w.K)
+        t0 = time.perf_counter()
+        oracle.mfd_run(hc, p, csteps)
+        dt = time.perf_counter() - t0
+        cpu = {"value": side * side * csteps / dt, "unit": "cell-updates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{csteps} steps of a {side}x{side} grid with the same parameters, "
+                         f"serial C oracle (cells in height order), {dt:.2f} s"}
+    print(json.dumps({
+        "metric": "cell-updates/s", "value": cells * steps / (ms * 1e-3),
+        "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": MFD_NAME, "ny": w.ny, "nx": w.nx, "dx": w.dx, "dt": w.dt,
+                   "m": w.m, "U": w.U, "K": w.K, "exponent": 1.0, "seed": args.seed},
+        "levels": nl,
+        "roofline": {"bound": "hbm", "kernel": "k_mfd_levels", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes": f"{ALG_BYTES_MFD_LEVELS} B per cell",
+                     "avg_launch_ms": levels_ms},
+        "kernel_ms_per_step": {"k_mfd_route": route_ms, "k_mfd_levels": levels_ms},
+        "levels_kernel_phase_ms_per_step": phases,
+        "cpu_baseline": cpu}), flush=True)
+
+
 def bench_network(args):
     """The warm-start network alone: training steps and forward passes at
     batch 16 on 256 x 256 inputs (the convolutions run on MFMA)."""
@@ -436,6 +515,9 @@ def main():
         return
     if args.workload == NET_NAME:
         bench_network(args)
+        return
+    if args.workload == MFD_NAME:
+        bench_mfd(args)
         return
     import torch
 

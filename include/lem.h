@@ -141,6 +141,10 @@ lem_status lem_create(const lem_params* p, void* d_workspace, size_t ws_bytes,
  *   (with optional K and U fields), lem_sync, lem_stats, lem_set_tuning and
  *   lem_destroy work on it; lem_run_fixed_routing and lem_routing return
  *   LEM_E_ARG.  LEM_E_ARG for n != 1 or an exponent that is not finite and > 0.
+ *   In lem_stats of such a context kernel_ms[0] is the routing kernel,
+ *   kernel_ms[1] the level kernel, and phase_ms[1..3] its levels, areas and
+ *   erosion; crossing_last counts every cell (all go through the level
+ *   kernel).
  * lem_mfd_export: drainage area (m^2, FP64, ny*nx) and level per cell of the
  *   last step to device arrays (either may be NULL); *h_nlevels (may be NULL)
  *   receives the number of levels.  Synchronizes the stream.  LEM_E_STATE

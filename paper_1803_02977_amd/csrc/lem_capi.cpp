@@ -203,28 +203,17 @@ int pergrid_threads(const lem_ctx* ctx) {
   return ctx->level_threads ? ctx->level_threads : lem::kBlock;
 }
 
-// One step: the tile pass, then the global level pass for crossing trees.
+// One step: the tile pass, then the global level pass for crossing trees
+// (multiple flow directions: routing, then the level kernel).
 lem_status step(lem_ctx* ctx, lem::StepArgs& a, bool timers) {
-  if (ctx->mfd) {
-    if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
-    hipError_t e = lem::launch_mfd_step(a, ctx->grid, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "multiple-flow-direction launch");
-    if (timers) {
-      (void)hipEventRecord(ctx->ev2, ctx->stream);
-      e = hipEventSynchronize(ctx->ev2);
-      if (e != hipSuccess) return hip_fail(ctx, e, "timer event");
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ctx->ev1, ctx->ev2);
-      ctx->order_ms += ms;
-    }
-    return LEM_OK;
-  }
   if (timers) (void)hipEventRecord(ctx->ev0, ctx->stream);
-  hipError_t e = lem::launch_tile_step(a, ctx->stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "tile launch");
+  hipError_t e = ctx->mfd ? lem::launch_mfd_route(a, ctx->stream)
+                          : lem::launch_tile_step(a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, ctx->mfd ? "routing launch" : "tile launch");
   if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
-  e = ctx->pergrid ? lem::launch_grid_levels(a, pergrid_threads(ctx), ctx->stream)
-                   : lem::launch_global_levels(a, ctx->grid, ctx->stream);
+  e = ctx->mfd      ? lem::launch_mfd_levels(a, ctx->grid, ctx->stream)
+      : ctx->pergrid ? lem::launch_grid_levels(a, pergrid_threads(ctx), ctx->stream)
+                     : lem::launch_global_levels(a, ctx->grid, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "level-pass launch");
   if (timers) {
     (void)hipEventRecord(ctx->ev2, ctx->stream);

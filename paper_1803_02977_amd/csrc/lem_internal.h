@@ -144,9 +144,11 @@ hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user_rcode, hi
 hipError_t launch_tile_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s);
-// Multiple flow directions: routing, then levels, areas and heights in one
-// cooperative launch of `grid` workgroups.
-hipError_t launch_mfd_step(const StepArgs& a, int grid, hipStream_t s);
+// Multiple flow directions: routing (weight sums, receiver counters, roots),
+// then levels, areas and heights in one cooperative launch of `grid`
+// workgroups.
+hipError_t launch_mfd_route(const StepArgs& a, hipStream_t s);
+hipError_t launch_mfd_levels(const StepArgs& a, int grid, hipStream_t s);
 hipError_t mfd_kernel_occupancy(int* blocks_per_cu);
 // Routing export of grid g (its cells [offset, offset + ny*nx)).
 hipError_t launch_export(const StepArgs& a, int g, int64_t offset, int64_t cells, int32_t* rec,

@@ -1077,6 +1077,11 @@ __device__ __forceinline__ double class_dist(const GridDev& G, int k) {
 }
 
 // Receivers, weight sums and counters; roots (no receiver) queued as level 0.
+// Each block takes kRouteItems cells per thread between two appends to the
+// queue counter (a same-address atomic serialises at about 11.5 ns).
+constexpr int kRouteItems = 16;
+constexpr int kRouteChunk = 256 * kRouteItems;
+
 __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
   __shared__ int wsum[256 / 64];
   __shared__ int s_base;
@@ -1084,10 +1089,13 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
   const GridDev& G = a.grids[0];
   const int ny = G.ny, nx = G.nx;
   const int64_t n = (int64_t)ny * nx;
-  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
-    const int64_t c = base + threadIdx.x;
-    int root = 0;
-    if (c < n) {
+  for (int64_t base = (int64_t)blockIdx.x * kRouteChunk; base < n;
+       base += (int64_t)gridDim.x * kRouteChunk) {
+    uint32_t roots = 0;  // bit j: cell base + j * 256 + threadIdx.x is a root
+#pragma unroll 4
+    for (int j = 0; j < kRouteItems; ++j) {
+      const int64_t c = base + (int64_t)j * 256 + threadIdx.x;
+      if (c >= n) break;
       const int y = (int)(c / nx), x = (int)(c % nx);
       double wsum_c = 0.0;
       int nrec = 0;
@@ -1104,14 +1112,21 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
       }
       w.par[c] = nrec;
       w.hq[c] = wsum_c;
-      root = nrec == 0;
-      if (root && a.export_routing) w.dep_g[c] = 0;
+      if (nrec == 0) {
+        roots |= 1u << j;
+        if (a.export_routing) w.dep_g[c] = 0;
+      }
     }
     int tot;
-    const int pre = block_exclusive_scan<256>(root, wsum, &tot);
+    const int pre = block_exclusive_scan<256>(__popc(roots), wsum, &tot);
     if (threadIdx.x == 0) s_base = tot ? atomicAdd(&w.lcnt[0], tot) : 0;
     __syncthreads();
-    if (root) w.q[s_base + pre] = (int32_t)c;
+    int32_t pos = s_base + pre;
+    while (roots) {
+      const int j = __ffs(roots) - 1;
+      roots &= roots - 1;
+      w.q[pos++] = (int32_t)(base + (int64_t)j * 256 + threadIdx.x);
+    }
     __syncthreads();
   }
 }
@@ -1239,6 +1254,8 @@ __global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
   const int wg = blockIdx.x, nwg = gridDim.x;
   const bool lead = (wg == 0 && threadIdx.x == 0);
   int32_t lo = 0, hi = load_acquire(&w.lcnt[0]), L = 0;
+  uint64_t t0 = 0, t1 = 0, t2 = 0;
+  if (lead && a.timers) t0 = wall_clock64();
   if (lead) w.lev[0] = 0;
   while (true) {
     if (lead) {
@@ -1253,13 +1270,22 @@ __global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
     hi += added;
     ++L;
   }
+  if (lead && a.timers) t1 = wall_clock64();
   for (int32_t l = L; l >= 0; --l) {
     mfd_area_level(a, w.lev[l], w.lev[l + 1], wg, nwg);
     grid_barrier(ct);
   }
+  if (lead && a.timers) t2 = wall_clock64();
   for (int32_t l = 0; l <= L; ++l) {
     mfd_erode_level(a, w.lev[l], w.lev[l + 1], wg, nwg);
     if (l < L) grid_barrier(ct);
+  }
+  if (lead && a.timers) {
+    // The last erosion level has no closing barrier: this is workgroup 0's end.
+    const uint64_t t3 = wall_clock64();
+    ct->ticks[1] += t1 - t0;
+    ct->ticks[2] += t2 - t1;
+    ct->ticks[3] += t3 - t2;
   }
   if (lead) {
     const int32_t nl = L + 1;
@@ -1482,12 +1508,15 @@ hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mfd_step(const StepArgs& a, int grid, hipStream_t s) {
+hipError_t launch_mfd_route(const StepArgs& a, hipStream_t s) {
   const int64_t n = a.n;
-  const unsigned blocks = (unsigned)(n < 256 * 2048 ? (n + 255) / 256 : 2048);
+  const int64_t chunks = (n + kRouteChunk - 1) / kRouteChunk;
+  const unsigned blocks = (unsigned)(chunks < 4096 ? chunks : 4096);
   hipLaunchKernelGGL(k_mfd_route, dim3(blocks), dim3(256), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_mfd_levels(const StepArgs& a, int grid, hipStream_t s) {
   StepArgs copy = a;
   void* args[] = {&copy};
   return hipLaunchCooperativeKernel((const void*)k_mfd_levels, dim3(grid), dim3(kBlock), args, 0,

@@ -84,6 +84,28 @@ def test_mfd_exponent_fields_and_rectangular_cells():
     assert_heights_close(h, ref["h"])
 
 
+@pytest.mark.parametrize("kind", ["cone", "ramp-north", "ramp-west", "ramp-south-east"])
+def test_mfd_long_paths_across_many_tiles(kind):
+    """Flow paths of a few hundred cells that cross many tiles, including
+    ramps whose areas must travel against the order in which tiles are
+    visited: every cell still gets the oracle's value."""
+    torch = require_gpu()
+    ny, nx = 203, 261
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    base = {"cone": np.minimum(np.minimum(yy, ny - 1 - yy), np.minimum(xx, nx - 1 - xx)),
+            "ramp-north": yy, "ramp-west": xx, "ramp-south-east": (ny - 1 - yy) + (nx - 1 - xx)}[kind]
+    rng = np.random.default_rng(21)
+    h0 = 0.5 * base + rng.uniform(0.0, 0.01, (ny, nx))
+    h0[0, :] = h0[-1, :] = h0[:, 0] = h0[:, -1] = 0.0
+    print(f"[gpu] mfd {kind} {ny}x{nx}", flush=True)
+    h, area, level, nl = _gpu(torch, h0, 3)
+    ref = _ref(h0, 3)
+    assert ref["nlevels"] > 90
+    assert np.array_equal(level, ref["level"]) and nl == ref["nlevels"]
+    assert np.array_equal(area, ref["area"])
+    assert np.array_equal(h, ref["h"])
+
+
 def test_mfd_large_grid_and_determinism():
     torch = require_gpu()
     h0 = W.initial_heights(1024, 1536, 5)
