@@ -274,6 +274,75 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total
   return off + inc - v;
 }
 
+__device__ __forceinline__ uint64_t wave_inclusive_scan64(uint64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Output positions in item order for kItems items per thread, item j of
+// thread t being queue position base + j * NT + t.  v[g] packs the counts of
+// items 4g..4g+3 (each at most 8) in 16-bit fields; pre[g] receives, field by
+// field, the exclusive prefix over the threads and tot[g] the workgroup
+// totals (at most 8 * NT < 2^16, so fields never carry).  Item j of thread t
+// then starts at sum_{j' < j} total_{j'} + prefix_j(t).  wsum64 holds
+// 4 * NT / 64 + 4 words.
+__device__ __forceinline__ int item_field(uint64_t x, int i) {
+  return (int)((x >> (16 * i)) & 0xFFFFu);
+}
+
+// Donor counts of four items from their masks packed in one word (8 bits
+// each), as block_scan_items wants them (16 bits each).
+__device__ __forceinline__ uint64_t counts_of_masks(uint32_t mk) {
+  uint64_t v = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v |= (uint64_t)__popc((mk >> (8 * i)) & 0xFFu) << (16 * i);
+  return v;
+}
+
+template <int NT>
+__device__ __forceinline__ void block_scan_items(const uint64_t v[4], uint64_t* wsum64,
+                                                 uint64_t pre[4], uint64_t tot[4]) {
+  static_assert(8 * NT < 65536, "16-bit fields");
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    pre[g] = wave_inclusive_scan64(v[g]);
+    if (lane == 63) wsum64[g * NW + w] = pre[g];
+  }
+  __syncthreads();
+  if (w == 0) {  // one wave turns the wave totals into offsets and the workgroup totals
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+      const uint64_t x = lane < NW ? wsum64[g * NW + lane] : 0;
+      const uint64_t y = wave_inclusive_scan64(x);
+      if (lane < NW) wsum64[g * NW + lane] = y - x;
+      if (lane == NW - 1) wsum64[4 * NW + g] = y;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    pre[g] += wsum64[g * NW + w] - v[g];
+    tot[g] = wsum64[4 * NW + g];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int items_total(const uint64_t tot[4]) {
+  int s = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s += item_field(tot[g], i);
+  return s;
+}
+
 __device__ __forceinline__ int32_t load_acquire(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -641,50 +710,61 @@ __device__ __forceinline__ void grid_barrier(Ctrl* ct) {
 }
 
 // Breadth-first expansion of queue positions [lo, hi) (level L) by
-// workgroups wg of nwg: the donors of each position are appended after hi.
+// workgroups wg of nwg: the donors of each position are appended after hi,
+// in the order of the positions (block_scan_items), so cells that are
+// neighbours in one level have their donors next to each other in the next
+// and the gathers of later levels stay local.
 __device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t L, int wg,
-                             int nwg, int* wsum, int* s_base) {
+                             int nwg, uint64_t* wsum64, int* s_base) {
   const Work& w = a.w;
   const int tid = threadIdx.x;
   for (int64_t base = lo + (int64_t)wg * kChunk; base < hi; base += (int64_t)nwg * kChunk) {
-    int32_t cs[kItems];
-    uint32_t ms[kItems];  // donor mask | grid << 8
-    int cntv = 0;
+    uint32_t mk[kItems / 4] = {0, 0, 0, 0};  // donor masks, four to a word
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const int64_t i = base + (int64_t)j * kBlock + tid;
-      cs[j] = 0;
-      ms[j] = 0;
       if (i < hi) {
-        cs[j] = w.q[i];
-        const uint32_t m = w.dmask[cs[j]];
-        ms[j] = m | ((uint32_t)w.gq[i] << 8);
-        cntv += __popc(m);
+        const uint32_t m = w.dmask[w.q[i]];
+        mk[j >> 2] |= m << (8 * (j & 3));
       }
     }
-    int tot;
-    const int pre = block_exclusive_scan<kBlock>(cntv, wsum, &tot);
-    if (tid == 0) *s_base = tot ? atomicAdd(&w.lcnt[L + 1], tot) : 0;
+    uint64_t pre[4], tot[4];
+    const uint64_t v[4] = {counts_of_masks(mk[0]), counts_of_masks(mk[1]), counts_of_masks(mk[2]),
+                           counts_of_masks(mk[3])};
+    block_scan_items<kBlock>(v, wsum64, pre, tot);
+    const int total = items_total(tot);
+    if (tid == 0) *s_base = total ? atomicAdd(&w.lcnt[L + 1], total) : 0;
     __syncthreads();
-    int32_t pos = hi + *s_base + pre;
+    int32_t run = hi + *s_base;
+    // Groups of four items, not unrolled: keeps the kItems re-reads from being
+    // hoisted (register pressure); the selects avoid indexing registers at run time.
+#pragma unroll 1
+    for (int g = 0; g < kItems / 4; ++g) {
+      const uint64_t pg = g == 0 ? pre[0] : g == 1 ? pre[1] : g == 2 ? pre[2] : pre[3];
+      const uint64_t tg = g == 0 ? tot[0] : g == 1 ? tot[1] : g == 2 ? tot[2] : tot[3];
+      const uint32_t mg = g == 0 ? mk[0] : g == 1 ? mk[1] : g == 2 ? mk[2] : mk[3];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int64_t i = base + (int64_t)j * kBlock + tid;
-      if (i < hi) {
-        uint32_t m = ms[j] & 0xFFu;
-        const uint32_t gi = ms[j] >> 8;
-        w.mq[i] = (uint8_t)m;
-        w.fc[i] = pos;
-        if (m) {
-          const int nx = a.grids[gi].nx;
-          while (m) {
-            const int b = __ffs(m) - 1;
-            m &= m - 1;
-            w.q[pos] = (int32_t)(cs[j] + neighbour_offset(b, nx));
-            w.gq[pos] = (uint16_t)gi;
-            w.par[pos] = (int32_t)i;
-            w.kq[pos] = (uint8_t)(7 - b);
-            ++pos;
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = base + (int64_t)(4 * g + e) * kBlock + tid;
+        int32_t pos = run + item_field(pg, e);
+        run += item_field(tg, e);
+        if (i < hi) {
+          uint32_t m = (mg >> (8 * e)) & 0xFFu;
+          w.mq[i] = (uint8_t)m;
+          w.fc[i] = pos;
+          if (m) {
+            const uint32_t gi = w.gq[i];
+            const int nx = a.grids[gi].nx;
+            const int32_t c = w.q[i];  // re-read: cheaper than keeping kItems cells live
+            while (m) {
+              const int b = __ffs(m) - 1;
+              m &= m - 1;
+              w.q[pos] = (int32_t)(c + neighbour_offset(b, nx));
+              w.gq[pos] = (uint16_t)gi;
+              w.par[pos] = (int32_t)i;
+              w.kq[pos] = (uint8_t)(7 - b);
+              ++pos;
+            }
           }
         }
       }
@@ -730,7 +810,7 @@ __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32
 }
 
 __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
-  __shared__ int wsum[kBlock / 64];
+  __shared__ uint64_t wsum64[4 * kBlock / 64 + 4];
   __shared__ int s_base;
   const Work w = a.w;
   Ctrl* ct = w.ctrl;
@@ -752,7 +832,7 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
         w.lev[L + 1] = hi;
         w.lcnt[L + 2] = 0;
       }
-      expand_level(a, lo, hi, L, wg, nwg, wsum, &s_base);
+      expand_level(a, lo, hi, L, wg, nwg, wsum64, &s_base);
       grid_barrier(ct);
       const int32_t added = load_acquire(&w.lcnt[L + 1]);
       if (added == 0) {
@@ -773,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
             w.lev[tL + 1] = thi;
             w.lcnt[tL + 2] = 0;
           }
-          expand_level(a, tlo, thi, tL, 0, 1, wsum, &s_base);
+          expand_level(a, tlo, thi, tL, 0, 1, wsum64, &s_base);
           __syncthreads();
           const int32_t added = load_acquire(&w.lcnt[tL + 1]);
           __syncthreads();
@@ -1134,7 +1214,7 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
 // Level L -> L+1: every processed cell releases its donors; a donor whose
 // last receiver this was joins the next level.
 __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L, int wg, int nwg,
-                           int* wsum, int* s_base) {
+                           uint64_t* wsum64, int* s_base) {
   const Work& w = a.w;
   const GridDev& G = a.grids[0];
   const int ny = G.ny, nx = G.nx;
@@ -1142,7 +1222,7 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
   for (int64_t base = lo + (int64_t)wg * kChunk; base < hi; base += (int64_t)nwg * kChunk) {
     uint32_t ready[kItems];
     int32_t cs[kItems];
-    int cntv = 0;
+    uint64_t v[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const int64_t i = base + (int64_t)j * kBlock + tid;
@@ -1160,16 +1240,19 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
           const int32_t d = c + (int32_t)neighbour_offset(k, nx);
           if (a.h_in[d] - hc > 0.0 && atomicSub(&w.par[d], 1) == 1) ready[j] |= 1u << k;
         }
-        cntv += __popc(ready[j]);
+        v[j >> 2] += (uint64_t)__popc(ready[j]) << (16 * (j & 3));
       }
     }
-    int tot;
-    const int pre = block_exclusive_scan<kBlock>(cntv, wsum, &tot);
-    if (tid == 0) *s_base = tot ? atomicAdd(&w.lcnt[L + 1], tot) : 0;
+    uint64_t pre[4], tot[4];
+    block_scan_items<kBlock>(v, wsum64, pre, tot);
+    const int total = items_total(tot);
+    if (tid == 0) *s_base = total ? atomicAdd(&w.lcnt[L + 1], total) : 0;
     __syncthreads();
-    int32_t pos = hi + *s_base + pre;
+    int32_t run = hi + *s_base;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
+      int32_t pos = run + item_field(pre[j >> 2], j & 3);
+      run += item_field(tot[j >> 2], j & 3);
       uint32_t m = ready[j];
       while (m) {
         const int k = __ffs(m) - 1;
@@ -1247,7 +1330,7 @@ __device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int w
 }
 
 __global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
-  __shared__ int wsum[kBlock / 64];
+  __shared__ uint64_t wsum64[4 * kBlock / 64 + 4];
   __shared__ int s_base;
   const Work w = a.w;
   Ctrl* ct = w.ctrl;
@@ -1262,7 +1345,7 @@ __global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
       w.lev[L + 1] = hi;
       w.lcnt[L + 2] = 0;
     }
-    mfd_expand(a, lo, hi, L, wg, nwg, wsum, &s_base);
+    mfd_expand(a, lo, hi, L, wg, nwg, wsum64, &s_base);
     grid_barrier(ct);
     const int32_t added = load_acquire(&w.lcnt[L + 1]);
     if (added == 0) break;
