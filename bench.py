@@ -555,6 +555,10 @@ def main():
             best = (ms, wall)
     ms, wall = best
     levels = solver.level_history(steps)
+    # Level-size histogram of the last timed step (cells per level of Alg 3,
+    # whole grid: trees inside a tile and crossing trees together).
+    offsets = solver.routing()["offsets"]
+    level_sizes = np.diff(np.asarray(offsets, dtype=np.int64)).tolist()
     solver.close()
 
     # Per-kernel device time, measured live with HIP events on the library's
@@ -607,7 +611,8 @@ def main():
         "hbm_roofline_frac_65B": round(value * alg_step / (HBM_PEAK_GBS * 1e9), 4),
         "wall_s": wall,
         "levels": {"min": int(levels.min()), "max": int(levels.max()),
-                   "mean": float(levels.mean())} if len(levels) else None,
+                   "mean": float(levels.mean()), "per_step": [int(x) for x in levels],
+                   "last_step_level_sizes": level_sizes} if len(levels) else None,
         "kernel_ms_per_step": {"k_tile_step": tile_ms, "k_global_levels": global_ms},
         "global_phase_ms_per_step": {"order": st.phase_ms[1] / steps,
                                      "accumulate": st.phase_ms[2] / steps,

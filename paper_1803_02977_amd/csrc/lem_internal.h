@@ -35,6 +35,10 @@ constexpr int kAmTab = 256;
 constexpr int kBlock = 1024;
 constexpr int kItems = 16;
 constexpr int kChunk = kBlock * kItems;
+// Queue positions per thread in a breadth-first expansion step (4, 8 or 16):
+// levels of the crossing pass hold about 10^6 positions at 10^8 cells, so
+// small chunks keep every workgroup busy.
+constexpr int kExpandItems = 4;
 constexpr int kGlobalMaxWGs = 192;
 constexpr int kTailLevel = 8192;  // default; lem_set_tuning changes it per context
 

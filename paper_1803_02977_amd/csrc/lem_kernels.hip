@@ -284,8 +284,8 @@ __device__ __forceinline__ uint64_t wave_inclusive_scan64(uint64_t v) {
   return v;
 }
 
-// Output positions in item order for kItems items per thread, item j of
-// thread t being queue position base + j * NT + t.  v[g] packs the counts of
+// Output positions in item order for 4W items per thread (W <= 4), item j
+// of thread t being queue position base + j * NT + t.  v[g] packs the counts of
 // items 4g..4g+3 (each at most 8) in 16-bit fields; pre[g] receives, field by
 // field, the exclusive prefix over the threads and tot[g] the workgroup
 // totals (at most 8 * NT < 2^16, so fields never carry).  Item j of thread t
@@ -304,21 +304,21 @@ __device__ __forceinline__ uint64_t counts_of_masks(uint32_t mk) {
   return v;
 }
 
-template <int NT>
-__device__ __forceinline__ void block_scan_items(const uint64_t v[4], uint64_t* wsum64,
-                                                 uint64_t pre[4], uint64_t tot[4]) {
+template <int NT, int W>
+__device__ __forceinline__ void block_scan_items(const uint64_t* v, uint64_t* wsum64,
+                                                 uint64_t* pre, uint64_t* tot) {
   static_assert(8 * NT < 65536, "16-bit fields");
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
+  for (int g = 0; g < W; ++g) {
     pre[g] = wave_inclusive_scan64(v[g]);
     if (lane == 63) wsum64[g * NW + w] = pre[g];
   }
   __syncthreads();
   if (w == 0) {  // one wave turns the wave totals into offsets and the workgroup totals
 #pragma unroll 1
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < W; ++g) {
       const uint64_t x = lane < NW ? wsum64[g * NW + lane] : 0;
       const uint64_t y = wave_inclusive_scan64(x);
       if (lane < NW) wsum64[g * NW + lane] = y - x;
@@ -327,17 +327,18 @@ __device__ __forceinline__ void block_scan_items(const uint64_t v[4], uint64_t* 
   }
   __syncthreads();
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
+  for (int g = 0; g < W; ++g) {
     pre[g] += wsum64[g * NW + w] - v[g];
     tot[g] = wsum64[4 * NW + g];
   }
   __syncthreads();
 }
 
-__device__ __forceinline__ int items_total(const uint64_t tot[4]) {
+template <int W>
+__device__ __forceinline__ int items_total(const uint64_t* tot) {
   int s = 0;
 #pragma unroll
-  for (int g = 0; g < 4; ++g)
+  for (int g = 0; g < W; ++g)
 #pragma unroll
     for (int i = 0; i < 4; ++i) s += item_field(tot[g], i);
   return s;
@@ -714,35 +715,39 @@ __device__ __forceinline__ void grid_barrier(Ctrl* ct) {
 // in the order of the positions (block_scan_items), so cells that are
 // neighbours in one level have their donors next to each other in the next
 // and the gathers of later levels stay local.
+template <int ITEMS>
 __device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t L, int wg,
                              int nwg, uint64_t* wsum64, int* s_base) {
   const Work& w = a.w;
   const int tid = threadIdx.x;
-  for (int64_t base = lo + (int64_t)wg * kChunk; base < hi; base += (int64_t)nwg * kChunk) {
-    uint32_t mk[kItems / 4] = {0, 0, 0, 0};  // donor masks, four to a word
+  constexpr int W = ITEMS / 4, CHUNK = kBlock * ITEMS;
+  for (int64_t base = lo + (int64_t)wg * CHUNK; base < hi; base += (int64_t)nwg * CHUNK) {
+    uint32_t mk[W] = {};  // donor masks, four to a word
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
       const int64_t i = base + (int64_t)j * kBlock + tid;
       if (i < hi) {
         const uint32_t m = w.dmask[w.q[i]];
         mk[j >> 2] |= m << (8 * (j & 3));
       }
     }
-    uint64_t pre[4], tot[4];
-    const uint64_t v[4] = {counts_of_masks(mk[0]), counts_of_masks(mk[1]), counts_of_masks(mk[2]),
-                           counts_of_masks(mk[3])};
-    block_scan_items<kBlock>(v, wsum64, pre, tot);
-    const int total = items_total(tot);
+    uint64_t v[W], pre[W], tot[W];
+#pragma unroll
+    for (int g = 0; g < W; ++g) v[g] = counts_of_masks(mk[g]);
+    block_scan_items<kBlock, W>(v, wsum64, pre, tot);
+    const int total = items_total<W>(tot);
     if (tid == 0) *s_base = total ? atomicAdd(&w.lcnt[L + 1], total) : 0;
     __syncthreads();
     int32_t run = hi + *s_base;
-    // Groups of four items, not unrolled: keeps the kItems re-reads from being
+    // Groups of four items, not unrolled: keeps the re-reads below from being
     // hoisted (register pressure); the selects avoid indexing registers at run time.
 #pragma unroll 1
-    for (int g = 0; g < kItems / 4; ++g) {
-      const uint64_t pg = g == 0 ? pre[0] : g == 1 ? pre[1] : g == 2 ? pre[2] : pre[3];
-      const uint64_t tg = g == 0 ? tot[0] : g == 1 ? tot[1] : g == 2 ? tot[2] : tot[3];
-      const uint32_t mg = g == 0 ? mk[0] : g == 1 ? mk[1] : g == 2 ? mk[2] : mk[3];
+    for (int g = 0; g < W; ++g) {
+      uint64_t pg = pre[0], tg = tot[0];
+      uint32_t mg = mk[0];
+#pragma unroll
+      for (int k = 1; k < W; ++k)
+        if (g == k) pg = pre[k], tg = tot[k], mg = mk[k];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t i = base + (int64_t)(4 * g + e) * kBlock + tid;
@@ -755,7 +760,7 @@ __device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t 
           if (m) {
             const uint32_t gi = w.gq[i];
             const int nx = a.grids[gi].nx;
-            const int32_t c = w.q[i];  // re-read: cheaper than keeping kItems cells live
+            const int32_t c = w.q[i];  // re-read: cheaper than keeping every item's cell live
             while (m) {
               const int b = __ffs(m) - 1;
               m &= m - 1;
@@ -832,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
         w.lev[L + 1] = hi;
         w.lcnt[L + 2] = 0;
       }
-      expand_level(a, lo, hi, L, wg, nwg, wsum64, &s_base);
+      expand_level<kExpandItems>(a, lo, hi, L, wg, nwg, wsum64, &s_base);
       grid_barrier(ct);
       const int32_t added = load_acquire(&w.lcnt[L + 1]);
       if (added == 0) {
@@ -853,7 +858,7 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
             w.lev[tL + 1] = thi;
             w.lcnt[tL + 2] = 0;
           }
-          expand_level(a, tlo, thi, tL, 0, 1, wsum64, &s_base);
+          expand_level<kExpandItems>(a, tlo, thi, tL, 0, 1, wsum64, &s_base);
           __syncthreads();
           const int32_t added = load_acquire(&w.lcnt[tL + 1]);
           __syncthreads();
@@ -1213,18 +1218,20 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
 
 // Level L -> L+1: every processed cell releases its donors; a donor whose
 // last receiver this was joins the next level.
+template <int ITEMS>
 __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L, int wg, int nwg,
                            uint64_t* wsum64, int* s_base) {
   const Work& w = a.w;
   const GridDev& G = a.grids[0];
   const int ny = G.ny, nx = G.nx;
   const int tid = threadIdx.x;
-  for (int64_t base = lo + (int64_t)wg * kChunk; base < hi; base += (int64_t)nwg * kChunk) {
-    uint32_t ready[kItems];
-    int32_t cs[kItems];
-    uint64_t v[4] = {0, 0, 0, 0};
+  constexpr int W = ITEMS / 4, CHUNK = kBlock * ITEMS;
+  for (int64_t base = lo + (int64_t)wg * CHUNK; base < hi; base += (int64_t)nwg * CHUNK) {
+    uint32_t ready[ITEMS];
+    int32_t cs[ITEMS];
+    uint64_t v[W] = {};
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
       const int64_t i = base + (int64_t)j * kBlock + tid;
       ready[j] = 0;
       cs[j] = 0;
@@ -1243,14 +1250,14 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
         v[j >> 2] += (uint64_t)__popc(ready[j]) << (16 * (j & 3));
       }
     }
-    uint64_t pre[4], tot[4];
-    block_scan_items<kBlock>(v, wsum64, pre, tot);
-    const int total = items_total(tot);
+    uint64_t pre[W], tot[W];
+    block_scan_items<kBlock, W>(v, wsum64, pre, tot);
+    const int total = items_total<W>(tot);
     if (tid == 0) *s_base = total ? atomicAdd(&w.lcnt[L + 1], total) : 0;
     __syncthreads();
     int32_t run = hi + *s_base;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
       int32_t pos = run + item_field(pre[j >> 2], j & 3);
       run += item_field(tot[j >> 2], j & 3);
       uint32_t m = ready[j];
@@ -1345,7 +1352,7 @@ __global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
       w.lev[L + 1] = hi;
       w.lcnt[L + 2] = 0;
     }
-    mfd_expand(a, lo, hi, L, wg, nwg, wsum64, &s_base);
+    mfd_expand<kExpandItems>(a, lo, hi, L, wg, nwg, wsum64, &s_base);
     grid_barrier(ct);
     const int32_t added = load_acquire(&w.lcnt[L + 1]);
     if (added == 0) break;
