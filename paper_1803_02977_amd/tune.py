@@ -24,7 +24,7 @@ TUNING_PATH = os.path.join(HERE, "tuning.json")
 BUCKETS = [(0, 1 << 18), (1 << 18, 1 << 22), (1 << 22, 1 << 25), (1 << 25, 1 << 31)]
 # A representative square grid per bucket (side length).
 BUCKET_SIDES = [256, 1024, 4096, 10000]
-CANDIDATES = [(g, t) for g in (16, 64, 128, 192, 256) for t in (2048, 8192, 32768)]
+CANDIDATES = [(g, t) for g in (16, 32, 64, 96, 128, 160, 192, 256) for t in (512, 2048, 8192)]
 
 
 def _bucket(cells: int) -> int:
