@@ -638,9 +638,10 @@ lem_status lem_mfd_export(lem_ctx* ctx, double* d_area, int32_t* d_level, int64_
   if (!ctx->has_routing) return fail(ctx, LEM_E_STATE, "no lem_run step yet");
   hipError_t e = hipSetDevice(ctx->device);
   const size_t n = (size_t)ctx->cells;
-  if (e == hipSuccess && d_area)
-    e = hipMemcpyAsync(d_area, ctx->w.area, sizeof(double) * n, hipMemcpyDeviceToDevice,
-                       ctx->stream);
+  if (e == hipSuccess && d_area) {
+    const lem::StepArgs a = make_args(ctx, nullptr, nullptr);
+    e = lem::launch_mfd_export_area(a, d_area, ctx->stream);
+  }
   if (e == hipSuccess && d_level)
     e = hipMemcpyAsync(d_level, ctx->w.dep_g, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
                        ctx->stream);

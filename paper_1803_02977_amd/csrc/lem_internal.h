@@ -82,6 +82,16 @@ struct GridDev {
   int32_t max_newton;      // iteration limit of that loop
 };
 
+// One cell of a multiple-flow-direction step as the area phase gathers it
+// (grid order): height, weight sum and drainage area in one record.
+struct MfdCell {
+  double h;        // height at the start of the step
+  double wsum;     // sum of the flow weights S^p over the receivers
+  double area;     // drainage area (m^2)
+  double pad;
+};
+static_assert(sizeof(MfdCell) == 32, "four cells per 128-byte line");
+
 // Pointers into the workspace.
 struct Work {
   double* h2;        // [N] second height buffer (steps alternate between h and h2)
@@ -92,7 +102,8 @@ struct Work {
   double* conv;      // [2*ngrids] per grid: largest |change| and largest |h| of a step
   int32_t* q;        // [N] global queue: cell per position, level-major
   uint16_t* gq;      // [N] grid of each queue position
-  int32_t* par;      // [N] queue position of the receiver (-1 at level 0)
+  int32_t* par;      // [N] queue position of the receiver (-1 at level 0); multiple
+                     //     flow directions: receivers of each cell not yet ordered
   int32_t* fc;       // [N] queue position of the first donor
   uint8_t* mq;       // [N] donor mask in queue order
   uint8_t* kq;       // [N] receiver code in queue order
@@ -110,7 +121,7 @@ struct Work {
   int32_t* gcnt;     // [ngrids] per-grid level pass: crossing roots queued per grid
   int32_t* gnl;      // [ngrids] per-grid level pass: levels of the crossing trees
   int32_t* gtot;     // [ngrids] per-grid level pass: cells of the crossing trees
-  double* area;      // [N] multiple flow directions: drainage area (null otherwise)
+  MfdCell* mc;       // [N] multiple flow directions: per-cell records (null otherwise)
   Ctrl* ctrl;
   int32_t* scratch;  // [kScratchInts] reductions (validation)
 };
@@ -153,6 +164,8 @@ hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s);
 // workgroups.
 hipError_t launch_mfd_route(const StepArgs& a, hipStream_t s);
 hipError_t launch_mfd_levels(const StepArgs& a, int grid, hipStream_t s);
+// Copies the last step's drainage areas (m^2, grid order) to d_area.
+hipError_t launch_mfd_export_area(const StepArgs& a, double* d_area, hipStream_t s);
 hipError_t mfd_kernel_occupancy(int* blocks_per_cu);
 // Routing export of grid g (its cells [offset, offset + ny*nx)).
 hipError_t launch_export(const StepArgs& a, int g, int64_t offset, int64_t cells, int32_t* rec,

@@ -1150,9 +1150,12 @@ __global__ __launch_bounds__(1024) void k_grid_levels_finish(StepArgs a) {
 // strictly lower neighbour is a receiver and gets the share
 // S^p / sum_j S_j^p of the flow (S = slope to it); a cell is processed only
 // after all of its receivers, so its level is the longest path to a root.
-// Single grid, global memory, level-synchronous.  Workspace reuse: par holds
-// the receivers still to be processed per cell, hq the sum of the weights
-// per cell (both in grid order), area the drainage area.
+// Single grid, global memory, level-synchronous.  Levels use the dense
+// heights and a dense counter array (par: receivers not yet ordered); areas
+// gather each donor's height, weight sum and area from one 32-byte MfdCell
+// (grid order), about four cache lines per 3x3 neighbourhood instead of
+// three per field; erosion reads the dense old and new heights of its
+// receivers and its own weight sum and area from its record.
 
 __device__ __forceinline__ double slope_pow(double s, double p) { return p == 1.0 ? s : pow(s, p); }
 
@@ -1184,8 +1187,8 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
       const int y = (int)(c / nx), x = (int)(c % nx);
       double wsum_c = 0.0;
       int nrec = 0;
+      const double hc = a.h_in[c];
       if (y > 0 && x > 0 && y < ny - 1 && x < nx - 1) {
-        const double hc = a.h_in[c];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const double hr = a.h_in[c + neighbour_offset(k, nx)];
@@ -1196,7 +1199,9 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
         }
       }
       w.par[c] = nrec;
-      w.hq[c] = wsum_c;
+      MfdCell& mc = w.mc[c];
+      mc.h = hc;
+      mc.wsum = wsum_c;
       if (nrec == 0) {
         roots |= 1u << j;
         if (a.export_routing) w.dep_g[c] = 0;
@@ -1282,20 +1287,20 @@ __device__ void mfd_area_level(const StepArgs& a, int32_t a0, int32_t a1, int wg
   for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1; i += (int64_t)nwg * kBlock) {
     const int32_t c = w.q[i];
     const int y = c / nx, x = c % nx;
-    const double hc = a.h_in[c];
+    const double hc = w.mc[c].h;
     double acc = G.dxdy;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int yy = y + code_dy(k), xx = x + code_dx(k);
       if (yy <= 0 || xx <= 0 || yy >= ny - 1 || xx >= nx - 1) continue;
-      const int32_t d = c + (int32_t)neighbour_offset(k, nx);
-      const double hd = a.h_in[d];
+      const MfdCell& md = w.mc[c + (int32_t)neighbour_offset(k, nx)];
+      const double hd = md.h;
       if (hd - hc > 0.0) {
-        const double share = slope_pow((hd - hc) / class_dist(G, k), a.mfd_p) / w.hq[d];
-        acc += share * w.area[d];
+        const double share = slope_pow((hd - hc) / class_dist(G, k), a.mfd_p) / md.wsum;
+        acc += share * md.area;
       }
     }
-    w.area[c] = acc;
+    w.mc[c].area = acc;
   }
 }
 
@@ -1313,9 +1318,10 @@ __device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int w
       a.h_out[c] = hc;
       continue;
     }
+    const MfdCell& mc = w.mc[c];
     const double hup = hc + (a.Uf ? a.Uf[c] * G.dt : G.udt);
-    const double wc = w.hq[c];
-    const double ac = w.area[c];
+    const double wc = mc.wsum;
+    const double ac = mc.area;
     const double kdt = (a.Kf ? a.Kf[c] : G.K) * G.dt;
     double sumf = 0.0, sumfh = 0.0;
     int nrec = 0;
@@ -1334,6 +1340,13 @@ __device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int w
     }
     a.h_out[c] = nrec ? (hup + sumfh) / (1.0 + sumf) : hup;
   }
+}
+
+// Drainage areas of the last step out of the per-cell records.
+__global__ __launch_bounds__(256) void k_mfd_export_area(StepArgs a, double* d_area) {
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < a.n;
+       c += (int64_t)gridDim.x * 256)
+    d_area[c] = a.w.mc[c].area;
 }
 
 __global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
@@ -1565,7 +1578,7 @@ void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w, bool 
   w->gcnt = (int32_t*)take(4 * ngrids);
   w->gnl = (int32_t*)take(4 * ngrids);
   w->gtot = (int32_t*)take(4 * ngrids);
-  w->area = mfd ? (double*)take(8 * n) : nullptr;
+  w->mc = mfd ? (MfdCell*)take((int64_t)sizeof(MfdCell) * n) : nullptr;
   w->ctrl = (Ctrl*)take(sizeof(Ctrl));
   w->scratch = (int32_t*)take(4 * kScratchInts);
 }
@@ -1611,6 +1624,13 @@ hipError_t launch_mfd_levels(const StepArgs& a, int grid, hipStream_t s) {
   void* args[] = {&copy};
   return hipLaunchCooperativeKernel((const void*)k_mfd_levels, dim3(grid), dim3(kBlock), args, 0,
                                     s);
+}
+
+hipError_t launch_mfd_export_area(const StepArgs& a, double* d_area, hipStream_t s) {
+  const int64_t n = a.n;
+  const unsigned blocks = (unsigned)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_mfd_export_area, dim3(blocks), dim3(256), 0, s, a, d_area);
+  return hipGetLastError();
 }
 
 hipError_t mfd_kernel_occupancy(int* blocks_per_cu) {

@@ -52,9 +52,13 @@ def lookup(cells: int, table=None):
     return None
 
 
-def time_candidates(make_runner, steps: int, candidates=CANDIDATES, repeats: int = 2):
-    """Times each candidate; make_runner() -> (set_tuning, run(steps), sync)."""
-    set_tuning, run, sync = make_runner()
+def time_candidates(make_runner, steps: int, candidates=CANDIDATES, repeats: int = 3):
+    """Times each candidate; make_runner() -> (set_tuning, run(steps), sync,
+    level_ms()), level_ms() giving the level kernel's HIP-event milliseconds
+    summed over the last run.  Settings only change that kernel's schedule,
+    so its own time ranks them (host clocks around whole steps proved too
+    noisy to separate settings a few percent apart)."""
+    set_tuning, run, sync, level_ms = make_runner()
     run(2)
     sync()
     out = []
@@ -62,10 +66,9 @@ def time_candidates(make_runner, steps: int, candidates=CANDIDATES, repeats: int
         set_tuning(g, t)
         best = None
         for _ in range(repeats):
-            t0 = time.perf_counter()
             run(steps)
             sync()
-            dt = (time.perf_counter() - t0) / steps
+            dt = level_ms() / steps / 1e3
             best = dt if best is None else min(best, dt)
         out.append(((g, t), best))
     return out
@@ -75,18 +78,25 @@ def tune(steps: int = 10, path: str = TUNING_PATH, verbose: bool = True):
     import torch
 
     import workloads as W
-    from . import Solver
-    table = {"note": "ms per step of candidate settings, per grid-size bucket; fastest kept",
+    from . import LEM_F_PHASE_TIMERS, Solver
+    table = {"note": "level-kernel ms per step of candidate settings, per grid-size bucket; "
+                     "fastest kept",
              "buckets": []}
     dev = torch.device("cuda:0")
     for (lo, hi), side in zip(BUCKETS, BUCKET_SIDES):
         w = W.LARGE_10000 if side == 10000 else W.SMALL_256.with_(ny=side, nx=side)
         h0 = torch.from_numpy(W.initial_heights(w.ny, w.nx, 0)).to(dev)
         h = h0.clone()
-        s = Solver(w.ny, w.nx, w.dx, w.dy, w.dt, w.m, w.U, w.K, device=dev, tuning=None)
+        s = Solver(w.ny, w.nx, w.dx, w.dy, w.dt, w.m, w.U, w.K, device=dev, tuning=None,
+                   flags=LEM_F_PHASE_TIMERS)
 
         def make():
-            return (lambda g, t: s.set_tuning(g, t), lambda k: s.run(h, k), s.sync)
+            def run(k):  # every timed run starts from the same heights
+                h.copy_(h0)
+                s.run(h, k)
+
+            return (lambda g, t: s.set_tuning(g, t), run, s.sync,
+                    lambda: s.stats().kernel_ms[1])
 
         res = time_candidates(make, steps)
         s.close()
