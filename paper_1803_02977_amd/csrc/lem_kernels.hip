@@ -1484,10 +1484,16 @@ __global__ __launch_bounds__(256) void k_export_cross(StepArgs a) {
 __global__ __launch_bounds__(256) void k_export_cells(StepArgs a, int gi, int64_t off,
                                                       int64_t cells, int32_t* rec,
                                                       int32_t* depth, uint32_t* count) {
+  // Level histogram: per block in LDS for the first kExportBins levels (one
+  // device atomic per non-empty bin and block), deeper levels directly.
+  constexpr int kExportBins = 2048;
+  __shared__ int32_t bins[kExportBins];
   const Work w = a.w;
   const int nx = a.grids[gi].nx;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int32_t nl = w.ctrl->nlevels;
+  for (int b = threadIdx.x; b < kExportBins; b += blockDim.x) bins[b] = 0;
+  __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
     if (rec) {
       const uint8_t k = w.rcode[off + i];
@@ -1496,8 +1502,17 @@ __global__ __launch_bounds__(256) void k_export_cells(StepArgs a, int gi, int64_
     const int32_t d = w.dep_g[off + i];
     if (depth) depth[i] = d;
     if (count) count[i] = w.cnt_g[off + i];
-    if (d >= 0 && d < nl) atomicAdd(&w.dhist[d + 1], 1);
+    if (d >= 0 && d < nl) {
+      if (d < kExportBins)
+        atomicAdd(&bins[d], 1);
+      else
+        atomicAdd(&w.dhist[d + 1], 1);
+    }
   }
+  __syncthreads();
+  const int top = nl < kExportBins ? nl : kExportBins;
+  for (int b = threadIdx.x; b < top; b += blockDim.x)
+    if (bins[b]) atomicAdd(&w.dhist[b + 1], bins[b]);
 }
 
 // Per grid (blockIdx.y): the largest |h_out - h_in| and the largest |h_out|
