@@ -64,6 +64,29 @@ def measured_traffic(kernel):
     return data.get("bytes_per_launch", {}).get(kernel)
 
 
+SQ_PROFILE = os.path.join(ROOT, "profiles", "k_tile_step-sq-counters-plain-10000x10000.md")
+# Issue peak of wave64 VALU instructions: 256 CUs x 4 SIMDs, one instruction
+# per 4 cycles each (16 lanes), 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def measured_valu(kernel):
+    """VALU wave-instructions per launch of `kernel` from the committed
+    instruction-counter summary, or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(SQ_PROFILE).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        data = json.loads(block)
+        digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("source_sha256") != digest:
+        return None
+    return data.get("valu_wave_instructions_per_launch", {}).get(kernel)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -591,6 +614,15 @@ def main():
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=measured_traffic(kname) if w.name == W.LARGE_10000.name else None,
                     alg_bytes=per_unit, avg_launch_ms=round(kms, 4))
+    valu = measured_valu(kname) if w.name == W.LARGE_10000.name else None
+    if valu:
+        # The tile kernel is bound by instruction issue more than by HBM: the
+        # counted VALU instructions over the live launch time, against the peak.
+        rate = valu / (kms / 1e3)
+        roofline["valu_issue"] = {"wave_instructions_per_launch": valu,
+                                  "achieved_per_s": round(rate, -6),
+                                  "peak_per_s": VALU_ISSUE_PEAK,
+                                  "frac": round(rate / VALU_ISSUE_PEAK, 4)}
     out = {
         "metric": "cell-updates/s",
         "value": value,
