@@ -47,21 +47,25 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm-traffic-plain-10000x10000.
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1803_02977_amd", "csrc", "lem_kernels.hip")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source has
-    changed since the counters were taken (the summary records its hash)."""
+def _profile_block(path):
+    """The JSON block of a committed counter summary, or None when the kernel
+    source has changed since the counters were taken (the summary records
+    the source's SHA-256)."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
-        block = text.split("```json", 1)[1].split("```", 1)[0]
-        data = json.loads(block)
+        text = open(path).read()
+        data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
         digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except (OSError, IndexError, ValueError):
         return None
-    if data.get("source_sha256") != digest:
-        return None
-    return data.get("bytes_per_launch", {}).get(kernel)
+    return data if data.get("source_sha256") == digest else None
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None (see _profile_block)."""
+    data = _profile_block(TRAFFIC_PROFILE)
+    return data.get("bytes_per_launch", {}).get(kernel) if data else None
 
 
 SQ_PROFILE = os.path.join(ROOT, "profiles", "k_tile_step-sq-counters-plain-10000x10000.md")
@@ -72,19 +76,9 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 def measured_valu(kernel):
     """VALU wave-instructions per launch of `kernel` from the committed
-    instruction-counter summary, or None when the kernel source has changed
-    since the counters were taken."""
-    import hashlib
-    try:
-        text = open(SQ_PROFILE).read()
-        block = text.split("```json", 1)[1].split("```", 1)[0]
-        data = json.loads(block)
-        digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    except (OSError, IndexError, ValueError):
-        return None
-    if data.get("source_sha256") != digest:
-        return None
-    return data.get("valu_wave_instructions_per_launch", {}).get(kernel)
+    instruction-counter summary, or None (see _profile_block)."""
+    data = _profile_block(SQ_PROFILE)
+    return data.get("valu_wave_instructions_per_launch", {}).get(kernel) if data else None
 
 
 def parse():
