@@ -8,7 +8,7 @@
  * Equation").  This library adds a small convolutional network that predicts
  * that steady state from the erodibility field K, the uplift field U and the
  * initial surface h0; the solver then starts from the prediction (a warm
- * start) and remains the judge of the result: a prediction only changes
+ * start) and alone decides the result: a prediction only changes
  * where the run starts, never the steady-state test.  The network is not
  * part of the paper.
  *

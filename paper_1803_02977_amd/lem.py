@@ -72,8 +72,8 @@ def load(path: str = LIB_PATH):
     if _LIB is not None:
         return _LIB
     if not os.path.exists(path):
-        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
-                          "(hipcc --offload-arch=gfx950)")
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python paper_1803_02977_amd/build_lib.py` (hipcc --offload-arch=gfx950)")
     lib = C.CDLL(path)
     lib.lem_workspace_bytes.argtypes = [C.POINTER(lem_params)]
     lib.lem_workspace_bytes.restype = C.c_size_t

@@ -185,8 +185,8 @@ def test_level_pass_modes_give_identical_results():
     grids = _grids()
     h0 = W.batch_initial_heights(grids)
     out = {}
-    configs = [(LEM_LEVELS_GLOBAL, 0), (LEM_LEVELS_PER_GRID, 1024), (LEM_LEVELS_PER_GRID, 256)]
-    for mode, threads in configs:
+    settings = [(LEM_LEVELS_GLOBAL, 0), (LEM_LEVELS_PER_GRID, 1024), (LEM_LEVELS_PER_GRID, 256)]
+    for mode, threads in settings:
         print(f"[gpu] batch level pass mode {mode} threads {threads}", flush=True)
         b = _batch(torch, grids)
         got = b.set_tuning(level_pass=mode, level_threads=threads)
@@ -197,8 +197,8 @@ def test_level_pass_modes_give_identical_results():
         routes = [b.routing(g) for g in range(len(grids))]
         out[(mode, threads)] = (h.cpu().numpy(), routes, b.stats().max_nlevels)
         b.close()
-    ha, ra, la = out[configs[0]]
-    for cfg in configs[1:]:
+    ha, ra, la = out[settings[0]]
+    for cfg in settings[1:]:
         hb, rb, lb = out[cfg]
         assert np.array_equal(ha, hb), cfg
         assert la == lb, cfg
