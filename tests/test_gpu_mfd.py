@@ -131,3 +131,102 @@ def test_mfd_context_rejects_d8_only_calls():
     with pytest.raises(LemError):
         lem.lem_routing(s.ctx, None, None, None, 0)
     s.close()
+
+
+_DY = (-1, -1, -1, 0, 0, 1, 1, 1)
+_DX = (-1, 0, 1, -1, 1, -1, 0, 1)
+
+
+def test_mfd_full_size_conservation_and_sampled_cells():
+    """The 10000 x 10000 benchmark grid, second step: all drainage area ends
+    at cells without receivers, and 2000 sampled cells have exactly the
+    level, drainage area and new height that the definitions give from their
+    neighbours' exported values (levels and areas bit for bit; heights within
+    1e-12, since m = 0.45 goes through each platform's pow)."""
+    torch = require_gpu()
+    from paper_1803_02977_amd import MfdSolver
+    w = W.LARGE_10000
+    ny, nx = w.ny, w.nx
+    dev = torch.device("cuda:0")
+    print("[gpu] mfd 10000x10000 two steps, conservation and samples", flush=True)
+    h = torch.from_numpy(W.initial_heights(ny, nx, 0)).to(dev)
+    s = MfdSolver(ny, nx, w.dx, w.dy, w.dt, w.m, w.U, w.K, device=dev)
+    s.run(h, 1)
+    s.sync()
+    hs = h.cpu().numpy()  # heights at the start of the checked step
+    s.run(h, 1)
+    s.sync()
+    e = s.export()
+    area = e["area"].cpu().numpy()
+    lev = e["level"].cpu().numpy()
+    hn = h.cpu().numpy()
+    nlevels = e["nlevels"]
+    s.close()
+
+    # Cells with at least one strictly lower neighbour (interior cells only).
+    inner = hs[1:-1, 1:-1]
+    lower = np.zeros(inner.shape, bool)
+    for dy, dx in zip(_DY, _DX):
+        lower |= inner - hs[1 + dy:ny - 1 + dy, 1 + dx:nx - 1 + dx] > 0.0
+    sink = np.ones((ny, nx), bool)
+    sink[1:-1, 1:-1] = ~lower
+    del lower, inner
+    total = float(np.sum(area[sink], dtype=np.float64))
+    assert abs(total - ny * nx * w.dx * w.dy) <= 1e-9 * ny * nx * w.dx * w.dy
+    assert nlevels == int(lev.max()) + 1
+    assert np.all(lev[sink] == 0)
+
+    dd = float(np.sqrt(w.dx * w.dx + w.dy * w.dy))
+    dist = [dd if (_DY[k] and _DX[k]) else (w.dy if _DY[k] else w.dx) for k in range(8)]
+
+    def interior(y, x):
+        return 0 < y < ny - 1 and 0 < x < nx - 1
+
+    def receivers(y, x):
+        if not interior(y, x):
+            return []
+        return [k for k in range(8) if float(hs[y, x]) - float(hs[y + _DY[k], x + _DX[k]]) > 0.0]
+
+    def wsum(y, x):
+        t = 0.0
+        for k in receivers(y, x):
+            t += (float(hs[y, x]) - float(hs[y + _DY[k], x + _DX[k]])) / dist[k]
+        return t
+
+    rng = np.random.default_rng(17)
+    ys = rng.integers(0, ny, 2000)
+    xs = rng.integers(0, nx, 2000)
+    ys[:8] = [0, ny - 1, 0, ny - 1, 0, 5, ny - 1, 7]  # a few perimeter cells
+    xs[:8] = [0, nx - 1, 9, 11, nx - 1, 0, 3, nx - 1]
+    dxdy, udt, kdt = w.dx * w.dy, w.U * w.dt, w.K * w.dt
+    for y, x in zip(ys.tolist(), xs.tolist()):
+        hc = float(hs[y, x])
+        rec = receivers(y, x)
+        want_level = 1 + max(int(lev[y + _DY[k], x + _DX[k]]) for k in rec) if rec else 0
+        assert lev[y, x] == want_level, (y, x)
+        acc = dxdy
+        for k in range(8):
+            yy, xx = y + _DY[k], x + _DX[k]
+            if not interior(yy, xx):
+                continue
+            hd = float(hs[yy, xx])
+            if hd - hc > 0.0:
+                acc += ((hd - hc) / dist[k]) / wsum(yy, xx) * float(area[yy, xx])
+        assert area[y, x] == acc, (y, x, float(area[y, x]), acc)
+        if not interior(y, x):
+            assert hn[y, x] == hs[y, x]
+            continue
+        hup = hc + udt
+        if not rec:
+            want = hup
+        else:
+            wc, ac = wsum(y, x), float(area[y, x])
+            sumf = sumfh = 0.0
+            for k in rec:
+                yy, xx = y + _DY[k], x + _DX[k]
+                share = ((hc - float(hs[yy, xx])) / dist[k]) / wc
+                f = (kdt * (share * ac) ** w.m) / dist[k]
+                sumf += f
+                sumfh += f * float(hn[yy, xx])
+            want = (hup + sumfh) / (1.0 + sumf)
+        assert abs(float(hn[y, x]) - want) <= 1e-12 * max(abs(want), 1.0), (y, x)
