@@ -518,8 +518,9 @@ def cpu_baseline(w, h0, K, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "a multi-GPU sharding design is described but not built", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); sharding over "
+              "several GPUs is designed (row strips, boundary graphs) but not implemented",
+              file=sys.stderr)
         sys.exit(2)
     if args.workload == BATCH_NAME:
         bench_batch(args)
