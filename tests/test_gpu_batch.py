@@ -207,3 +207,26 @@ def test_level_pass_modes_give_identical_results():
                 assert torch.equal(ra[g][k], rb[g][k]), (cfg, g, k)
             assert ra[g]["nlevels"] == rb[g]["nlevels"]
             assert np.array_equal(np.asarray(ra[g]["offsets"]), np.asarray(rb[g]["offsets"]))
+
+
+def test_full_size_batch_sampled_realizations_match_oracle():
+    """The 512-realization benchmark batch (square grids of 128 to 1024 cells
+    a side, 2.16e8 cells, per-grid level pass chosen as the benchmark runs it),
+    3 steps: the smallest, a middle and the largest realization have the
+    oracle's routing exactly and its heights within 1e-12."""
+    torch = require_gpu()
+    from tests.gpu_util import assert_routing_equal
+    grids = W.batch_realizations()
+    print(f"[gpu] full batch: {len(grids)} grids, 3 steps", flush=True)
+    b = _batch(torch, grids)
+    h = torch.from_numpy(W.batch_initial_heights(grids)).to("cuda:0")
+    b.run(h, 3)
+    b.sync()
+    sizes = [r.ny * r.nx for r in grids]
+    for g in (int(np.argmin(sizes)), len(grids) // 2, int(np.argmax(sizes))):
+        r = grids[g]
+        print(f"[gpu] full batch grid {g}: {r.ny}x{r.nx}", flush=True)
+        p = oracle.Params(r.ny, r.nx, r.dx, r.dy, r.dt, r.m, 1.0, r.U, r.K)
+        ref = oracle.run(W.initial_heights(r.ny, r.nx, r.seed), p, 3)
+        assert_routing_equal(b.routing(g), ref)
+        assert_heights_close(b.view(h, g).cpu().numpy(), ref["h"])
