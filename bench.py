@@ -61,10 +61,14 @@ def _profile_block(path):
     return data if data.get("source_sha256") == digest else None
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+MFD_PROFILE = os.path.join(ROOT, "profiles", "k_mfd_levels-mfd-10000x10000.md")
+BATCH_PROFILE = os.path.join(ROOT, "profiles", "k_grid_levels-batch-512-realizations.md")
+
+
+def measured_traffic(kernel, path=TRAFFIC_PROFILE):
+    """HBM bytes per launch of `kernel` from a committed FETCH_SIZE /
     WRITE_SIZE summary, or None (see _profile_block)."""
-    data = _profile_block(TRAFFIC_PROFILE)
+    data = _profile_block(path)
     return data.get("bytes_per_launch", {}).get(kernel) if data else None
 
 
@@ -97,6 +101,8 @@ def parse():
                          "per grid")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="batch workload: skip the grid-by-grid comparison (counter runs)")
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--repeats", type=int, default=1)
     ap.add_argument("--copy-probe", action="store_true",
@@ -188,21 +194,25 @@ def bench_batch(args):
                 "achieved": ALG_BYTES_TILE * cells / (tile_ms * 1e-3) / 1e9,
                 "alg_bytes": f"{ALG_BYTES_TILE} B per cell", "avg_launch_ms": tile_ms}
     roof.update(peak=HBM_PEAK_GBS, unit="GB/s", frac=roof["achieved"] / HBM_PEAK_GBS,
-                traffic=None)
-    # The same grids one at a time through the single-grid path (fewer steps).
-    one_steps = max(1, min(steps, 20))
-    solvers = [Solver(r.ny, r.nx, r.dx, r.dy, r.dt, r.m, r.U, r.K, device=dev) for r in reals]
-    views = [h0[sum(q.ny * q.nx for q in reals[:i]):][: r.ny * r.nx].clone().view(r.ny, r.nx)
-             for i, r in enumerate(reals)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for s_, v in zip(solvers, views):
-        s_.run(v, one_steps)
-    torch.cuda.synchronize()
-    one_wall = time.perf_counter() - t1
-    for s_ in solvers:
-        s_.close()
-    one_value = cells * one_steps / one_wall
+                traffic=measured_traffic(roof["kernel"], BATCH_PROFILE)
+                if args.seed == 0 else None)
+    one_value = None
+    if not args.no_compare:
+        # The same grids one at a time through the single-grid path (fewer steps).
+        one_steps = max(1, min(steps, 20))
+        solvers = [Solver(r.ny, r.nx, r.dx, r.dy, r.dt, r.m, r.U, r.K, device=dev)
+                   for r in reals]
+        views = [h0[sum(q.ny * q.nx for q in reals[:i]):][: r.ny * r.nx].clone().view(r.ny, r.nx)
+                 for i, r in enumerate(reals)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s_, v in zip(solvers, views):
+            s_.run(v, one_steps)
+        torch.cuda.synchronize()
+        one_wall = time.perf_counter() - t1
+        for s_ in solvers:
+            s_.close()
+        one_value = cells * one_steps / one_wall
     out = {
         "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": ms / steps,
@@ -216,8 +226,8 @@ def bench_batch(args):
         "crossing_frac": round(st.crossing_run / steps / cells, 4),
         "grid_by_grid": {"value": one_value, "unit": "cell-updates/s", "steps": one_steps,
                          "note": "same realizations, one single-grid context each, run "
-                                 "one after another on the same GPU"},
-        "batch_speedup_vs_grid_by_grid": round(value / one_value, 2),
+                                 "one after another on the same GPU"} if one_value else None,
+        "batch_speedup_vs_grid_by_grid": round(value / one_value, 2) if one_value else None,
         "level_pass": "one workgroup per grid" if mode == 2 else "one device-wide pass",
         "kernel_ms_per_step": {"k_tile_step": tile_ms,
                                ("k_grid_levels" if mode == 2 else "k_global_levels"): level_ms},
@@ -396,7 +406,9 @@ def bench_mfd(args):
         "levels": nl,
         "roofline": {"bound": "hbm", "kernel": "k_mfd_levels", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes": f"{ALG_BYTES_MFD_LEVELS} B per cell",
+                     "traffic": measured_traffic("k_mfd_levels", MFD_PROFILE)
+                     if args.seed == 0 else None,
+                     "alg_bytes": f"{ALG_BYTES_MFD_LEVELS} B per cell",
                      "avg_launch_ms": levels_ms},
         "kernel_ms_per_step": {"k_mfd_route": route_ms, "k_mfd_levels": levels_ms},
         "levels_kernel_phase_ms_per_step": phases,
