@@ -1204,7 +1204,7 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
       mc.wsum = wsum_c;
       if (nrec == 0) {
         roots |= 1u << j;
-        if (a.export_routing) w.dep_g[c] = 0;
+        w.dep_g[c] = 0;
       }
     }
     int tot;
@@ -1271,7 +1271,7 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
         m &= m - 1;
         const int32_t d = cs[j] + (int32_t)neighbour_offset(k, nx);
         w.q[pos++] = d;
-        if (a.export_routing) w.dep_g[d] = L + 1;
+        w.dep_g[d] = L + 1;
       }
     }
     __syncthreads();
@@ -1342,6 +1342,46 @@ __device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int w
   }
 }
 
+// The cells of each level in grid order: a counting sort by level over
+// contiguous grid-order ranges, one per workgroup (per-range level
+// histograms, their scan per level, then the scatter).  Level-order gathers
+// then touch neighbouring rows close together in time and share cache lines;
+// the order inside a level changes no result.  Counts and starts live in
+// w.fc (level-major, nl * nwg entries).
+constexpr int kMfdSortLevels = 1024;
+
+__device__ void mfd_sort_by_level(const StepArgs& a, int32_t nl, int wg, int nwg, int32_t* hist,
+                                  int* wsum, Ctrl* ct) {
+  const Work& w = a.w;
+  const int64_t n = a.n;
+  const int64_t per = (n + nwg - 1) / nwg;
+  const int64_t c0 = min((int64_t)wg * per, n), c1 = min(c0 + per, n);
+  int32_t* cnt = w.fc;
+  for (int l = threadIdx.x; l < nl; l += kBlock) hist[l] = 0;
+  __syncthreads();
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += kBlock) {
+    const int32_t l = w.dep_g[c];
+    if ((uint32_t)l < (uint32_t)nl) atomicAdd(&hist[l], 1);
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < nl; l += kBlock) cnt[(int64_t)l * nwg + wg] = hist[l];
+  grid_barrier(ct);
+  for (int l = wg; l < nl; l += nwg) {  // nwg <= kBlock: one range per thread
+    const int v = threadIdx.x < nwg ? cnt[(int64_t)l * nwg + threadIdx.x] : 0;
+    int tot;
+    const int pre = block_exclusive_scan<kBlock>(v, wsum, &tot);
+    if (threadIdx.x < nwg) cnt[(int64_t)l * nwg + threadIdx.x] = w.lev[l] + pre;
+  }
+  grid_barrier(ct);
+  for (int l = threadIdx.x; l < nl; l += kBlock) hist[l] = cnt[(int64_t)l * nwg + wg];
+  __syncthreads();
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += kBlock) {
+    const int32_t l = w.dep_g[c];
+    if ((uint32_t)l < (uint32_t)nl) w.q[atomicAdd(&hist[l], 1)] = (int32_t)c;
+  }
+  grid_barrier(ct);
+}
+
 // Drainage areas of the last step out of the per-cell records.
 __global__ __launch_bounds__(256) void k_mfd_export_area(StepArgs a, double* d_area) {
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < a.n;
@@ -1351,6 +1391,8 @@ __global__ __launch_bounds__(256) void k_mfd_export_area(StepArgs a, double* d_a
 
 __global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
   __shared__ uint64_t wsum64[4 * kBlock / 64 + 4];
+  __shared__ int wsum[kBlock / 64];
+  __shared__ int32_t hist[kMfdSortLevels];
   __shared__ int s_base;
   const Work w = a.w;
   Ctrl* ct = w.ctrl;
@@ -1373,6 +1415,11 @@ __global__ __launch_bounds__(kBlock) void k_mfd_levels(StepArgs a) {
     hi += added;
     ++L;
   }
+  // Every cell reached (else the step reports an error below) and a level
+  // table that fits: put each level's cells in grid order.
+  if (hi == a.n && L + 1 <= kMfdSortLevels && (int64_t)(L + 1) * nwg <= (int64_t)a.n &&
+      nwg <= kBlock)
+    mfd_sort_by_level(a, L + 1, wg, nwg, hist, wsum, ct);
   if (lead && a.timers) t1 = wall_clock64();
   for (int32_t l = L; l >= 0; --l) {
     mfd_area_level(a, w.lev[l], w.lev[l + 1], wg, nwg);
