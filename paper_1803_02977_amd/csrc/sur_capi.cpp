@@ -17,7 +17,8 @@ namespace {
 constexpr int kChannels[4] = {32, 64, 128, 256};
 constexpr int kNumConv = 14;
 constexpr int64_t kPartCap = int64_t(32) << 20;  // floats of split partials
-constexpr int kColsumSplits = 256;
+constexpr int kBiasBlocks = 1024;   // pixel ranges of the bias gradient's partials
+constexpr int kWgradBlocks = 1024;  // workgroups a weight-gradient launch aims for
 constexpr int kLossBlocks = 1024;
 constexpr int kHeadBlocks = 512;
 
@@ -207,9 +208,12 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x) {
   const int64_t n = (int64_t)L.cout * 9 * L.cin;
   const int per = sur::wgrad_blocks_per_split(L.cin, L.cout);
   const int patches = sur::wgrad_patches(B, H, W);
-  int splits = std::max(1, (2048 + per - 1) / per);
-  splits = std::min<int64_t>(splits, patches);
-  splits = (int)std::min<int64_t>(splits, kPartCap / n);
+  int splits = std::max(1, (kWgradBlocks + per - 1) / per);
+  splits = std::min(splits, patches);
+  // Partials and their group sums must fit the partial buffer.
+  while (splits > 1 &&
+         n * (splits + sur::reduce_scratch_groups(splits)) > kPartCap)
+    --splits;
   sur::WgradArgs a{};
   a.x = x;
   a.dz = c->dz;
@@ -221,35 +225,37 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x) {
   a.Cout = L.cout;
   a.splits = splits;
   SUR_CHECK(sur::launch_wgrad(a, c->s));
-  SUR_CHECK(sur::launch_reduce_splits(c->part, splits, n, c->g + L.off, c->s));
+  SUR_CHECK(sur::launch_reduce_splits(c->part, splits, n, c->part + (int64_t)splits * n,
+                                      c->g + L.off, c->s));
   return LEM_OK;
 }
 
-lem_status bias_grad(lem_sur_ctx* c, int li, const float* g, int64_t P) {
+// ReLU backward of layer li's output y given its gradient g: dz (bfloat16)
+// for the weight and input gradients, and the bias gradient into c->g.
+lem_status relu_bias_bwd(lem_sur_ctx* c, int li, const float* g, const uint16_t* y, int64_t P) {
   const Layer& L = table().conv[li];
-  SUR_CHECK(sur::launch_colsum(g, P, L.cout, c->part, kColsumSplits, c->s));
-  SUR_CHECK(sur::launch_reduce_splits(c->part, kColsumSplits, L.cout,
+  SUR_CHECK(sur::launch_relu_bwd_bias(g, y, c->dz, P, L.cout, c->part, kBiasBlocks, c->s));
+  SUR_CHECK(sur::launch_reduce_splits(c->part, kBiasBlocks, L.cout,
+                                      c->part + (int64_t)kBiasBlocks * L.cout,
                                       c->g + L.off + (int64_t)L.cout * 9 * L.cin, c->s));
   return LEM_OK;
 }
 
 // Backward through conv(lb)(relu(conv(la)(x))) + ReLU given the gradient ge of
-// its output e (overwritten); gx (float32, cin(la) channels) may be null.
+// its output e; gx (float32, cin(la) channels) may be null.
 lem_status block_bwd(lem_sur_ctx* c, int B, int level, const uint16_t* x, const uint16_t* a,
-                     const uint16_t* e, float* ge, int la, int lb, float* gx) {
+                     const uint16_t* e, const float* ge, int la, int lb, float* gx) {
   lem_status st;
   const Layer& A = table().conv[la];
   const Layer& Bl = table().conv[lb];
   const int64_t P = (int64_t)B * (c->H >> level) * (c->W >> level);
   float* ga = c->gw[2];
-  SUR_CHECK(sur::launch_relu_bwd(ge, e, c->dz, P * Bl.cout, c->s));
-  if ((st = bias_grad(c, lb, ge, P)) != LEM_OK) return st;
+  if ((st = relu_bias_bwd(c, lb, ge, e, P)) != LEM_OK) return st;
   if ((st = wgrad(c, B, level, lb, a)) != LEM_OK) return st;
   if ((st = conv(c, B, level, c->dz, Bl.cout, c->wd + Bl.off, nullptr, Bl.cin, false, nullptr,
                  ga)) != LEM_OK)
     return st;
-  SUR_CHECK(sur::launch_relu_bwd(ga, a, c->dz, P * A.cout, c->s));
-  if ((st = bias_grad(c, la, ga, P)) != LEM_OK) return st;
+  if ((st = relu_bias_bwd(c, la, ga, a, P)) != LEM_OK) return st;
   if ((st = wgrad(c, B, level, la, x)) != LEM_OK) return st;
   if (gx && (st = conv(c, B, level, c->dz, A.cout, c->wd + A.off, nullptr, A.cin, false, nullptr,
                        gx)) != LEM_OK)
@@ -273,6 +279,7 @@ lem_status backward(lem_sur_ctx* c, int B, const double* U, const double* target
   SUR_CHECK(sur::launch_head_bwd(c->dy, c->d[0], c->pb + t.head_off, c->gw[0], c->part,
                                  kHeadBlocks, P0, c->s));
   SUR_CHECK(sur::launch_reduce_splits(c->part, kHeadBlocks, sur::kHeadChannels + 1,
+                                      c->part + (int64_t)kHeadBlocks * (sur::kHeadChannels + 1),
                                       c->g + t.head_off, c->s));
   // Decoder, level 0 up to 2: the concatenation's gradient lands in gcat[l];
   // its upsampled part becomes the gradient of the level below's output.

@@ -44,7 +44,11 @@ hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s);
 int wgrad_blocks_per_split(int Cin, int Cout);
 int wgrad_patches(int B, int H, int W);
 
-hipError_t launch_reduce_splits(const float* part, int splits, int64_t n, float* out,
+// Split partials are summed in groups of kReduceGroup consecutive splits,
+// then over the groups; tmp holds reduce_scratch_groups(splits) * n floats.
+constexpr int kReduceGroup = 32;
+int reduce_scratch_groups(int splits);
+hipError_t launch_reduce_splits(const float* part, int splits, int64_t n, float* tmp, float* out,
                                 hipStream_t s);
 hipError_t launch_to_bf16(const float* p, uint16_t* pb, int64_t n, hipStream_t s);
 hipError_t launch_dgrad_weights(const uint16_t* w, uint16_t* wd, int Cin, int Cout,
@@ -59,9 +63,8 @@ hipError_t launch_up_bwd(const float* gcat, float* glow, int B, int H, int W, in
                          hipStream_t s);
 hipError_t launch_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
                                float* out, int B, int H, int W, int C, hipStream_t s);
-hipError_t launch_relu_bwd(float* g, const uint16_t* y, uint16_t* dz, int64_t n, hipStream_t s);
-hipError_t launch_colsum(const float* g, int64_t P, int C, float* part, int splits,
-                         hipStream_t s);
+hipError_t launch_relu_bwd_bias(const float* g, const uint16_t* y, uint16_t* dz, int64_t P,
+                                int C, float* part, int nblk, hipStream_t s);
 hipError_t launch_head(const uint16_t* d0, const uint16_t* wb, const float* bias, float* y,
                        int64_t P, hipStream_t s);
 hipError_t launch_loss(const float* y, const double* target, const double* U, int B, int H,

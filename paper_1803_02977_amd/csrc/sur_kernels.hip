@@ -145,103 +145,181 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient of a 3x3 convolution for one tap per workgroup:
+// Weight gradient of a 3x3 convolution:
 // dW[co, tap, ci] = sum_p dz[p, co] * x[p + tap offset, ci], a GEMM with
-// M = output channels, N = input channels and K = pixels.  A workgroup owns
-// (tap, COB output channels, 32 input channels, split s) and loops over the
-// 16x16-pixel patches s, s + splits, ...; per patch it stages dz and the
-// tap-shifted x transposed (channel-major, pixels contiguous) in LDS and
-// runs eight K = 32 steps.  Results go to per-split partials, summed later
-// in split order.
-constexpr int kPP = 264;  // LDS pitch of one channel's 256 pixels
+// M = output channels, N = input channels and K = pixels for each tap.  A
+// workgroup owns (COB output channels, 32 input channels, split s), computes
+// all nine taps, and loops over the 16x16-pixel patches s, s + splits, ....
+// Per patch it stages, channel-major (pixels contiguous), the patch's dz and
+// the 18x18 input halo around it; the halo rows are 16-byte aligned, so the
+// three column shifts of one tap row come from one aligned 16-byte read and
+// one 4-byte read (shifts by one pixel via alignbit).  The next patch's
+// global loads are issued before the current patch's MFMAs.  Results go to
+// per-split partials, summed later in split order.
+constexpr int kPP = 264;  // LDS pitch of one output channel's 256 patch pixels
+constexpr int kHR = 24;   // LDS pitch of one 18-pixel halo row (16-byte aligned)
+constexpr int kHP = 456;  // LDS pitch of one input channel's 18 halo rows
+constexpr int kHaloPairs = kHalo * kHalo / 2 * 4;  // (pixel pair, 8-channel part) items
 
 int wgrad_blocks_per_split(int Cin, int Cout) {
   const int cob = (Cout % 64 == 0) ? 64 : 32;
-  return 9 * (Cout / cob) * (Cin / 32);
+  return (Cout / cob) * (Cin / 32);
 }
 
 int wgrad_patches(int B, int H, int W) {
   return B * ((H + kT - 1) / kT) * ((W + kT - 1) / kT);
 }
 
+__device__ __forceinline__ uint32_t lo_pair(uint32_t a, uint32_t b) {
+  return (a & 0xFFFFu) | (b << 16);
+}
+__device__ __forceinline__ uint32_t hi_pair(uint32_t a, uint32_t b) {
+  return (a >> 16) | (b & 0xFFFF0000u);
+}
+__device__ __forceinline__ uint32_t word(const uint4& v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
 template <int COB>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t dzt[COB * kPP];
-  __shared__ __attribute__((aligned(16))) uint16_t xt[32 * kPP];
-  constexpr int NT = COB == 64 ? 2 : 1;  // tiles per wave
+  __shared__ __attribute__((aligned(16))) uint16_t xt[32 * kHP];
+  constexpr int NCB = COB == 64 ? 2 : 1;    // 16-channel input blocks per wave
+  constexpr int PARTS = COB / 8;            // 8-channel parts of one dz pixel
+  constexpr int DZ_ITEMS = 64 * PARTS / 256;  // (4-pixel quad, part) items per thread
+  constexpr int X_ITEMS = (kHaloPairs + 255) / 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = (lane >> 4) * 8;
+  const int lr = lane & 15, grp = lane >> 4;
   int bid = blockIdx.x;
   const int s = bid % a.splits;
   bid /= a.splits;
   const int ncit = a.Cin / 32;
   const int cit = bid % ncit;
-  bid /= ncit;
-  const int ncot = a.Cout / COB;
-  const int cot = bid % ncot;
-  const int tap = bid / ncot;
-  const int ky = tap / 3 - 1, kx = tap % 3 - 1;
+  const int cot = bid / ncit;
   const int ci0 = cit * 32, co0 = cot * COB;
   const int tiles_x = (a.W + kT - 1) / kT, tiles_y = (a.H + kT - 1) / kT;
   const int npatch = a.B * tiles_x * tiles_y;
   const int mb = COB == 64 ? wave : (wave >> 1);
-  const int nb0 = COB == 64 ? 0 : (wave & 1);
+  const int cb0 = COB == 64 ? 0 : (wave & 1);
 
-  f32x4 acc[NT];
+  f32x4 acc[9][NCB];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int i = 0; i < NCB; ++i) acc[t][i] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int pt = s; pt < npatch; pt += a.splits) {
+  uint4 dzr[DZ_ITEMS][4], xr[X_ITEMS][2];
+  auto load = [&](int pt) {
     const int tx = pt % tiles_x, ty = (pt / tiles_x) % tiles_y, b = pt / (tiles_x * tiles_y);
     const int y0 = ty * kT, x0 = tx * kT;
-    __syncthreads();
-    for (int i = tid; i < 256 * (COB / 8); i += 256) {
-      const int px = i / (COB / 8), part = i % (COB / 8);
-      const int gy = y0 + px / kT, gx = x0 + px % kT;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (gy < a.H && gx < a.W)
-        v = *reinterpret_cast<const uint4*>(
-            a.dz + (((int64_t)b * a.H + gy) * a.W + gx) * a.Cout + co0 + part * 8);
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        dzt[(part * 8 + j) * kPP + px] = (uint16_t)(w4[j >> 1] >> ((j & 1) * 16));
+    for (int k = 0; k < DZ_ITEMS; ++k) {
+      const int i = tid + k * 256;
+      const int quad = i / PARTS, part = i % PARTS;
+      const int gy = y0 + quad / 4, gx = x0 + (quad % 4) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy < a.H && gx + j < a.W)
+          v = *reinterpret_cast<const uint4*>(
+              a.dz + (((int64_t)b * a.H + gy) * a.W + gx + j) * a.Cout + co0 + part * 8);
+        dzr[k][j] = v;
+      }
     }
-    for (int i = tid; i < 256 * 4; i += 256) {
-      const int px = i >> 2, part = i & 3;
-      const int oy = y0 + px / kT, ox = x0 + px % kT;
-      const int gy = oy + ky, gx = ox + kx;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (oy < a.H && ox < a.W && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-        v = *reinterpret_cast<const uint4*>(
-            a.x + (((int64_t)b * a.H + gy) * a.W + gx) * a.Cin + ci0 + part * 8);
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        xt[(part * 8 + j) * kPP + px] = (uint16_t)(w4[j >> 1] >> ((j & 1) * 16));
+    for (int k = 0; k < X_ITEMS; ++k) {
+      const int i = tid + k * 256;
+      const int pair = i >> 2, part = i & 3;
+      const int gy = y0 + pair / (kHalo / 2) - 1, gx = x0 + (pair % (kHalo / 2)) * 2 - 1;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (i < kHaloPairs && gy >= 0 && gy < a.H && gx + j >= 0 && gx + j < a.W)
+          v = *reinterpret_cast<const uint4*>(
+              a.x + (((int64_t)b * a.H + gy) * a.W + gx + j) * a.Cin + ci0 + part * 8);
+        xr[k][j] = v;
+      }
     }
-    __syncthreads();
-#pragma unroll 2
-    for (int k0 = 0; k0 < 256; k0 += 32) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(dzt + (mb * 16 + lr) * kPP + k0 + lk);
+  };
+  auto store = [&]() {
 #pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        const bf16x8 bv =
-            *reinterpret_cast<const bf16x8*>(xt + ((nb0 + i) * 16 + lr) * kPP + k0 + lk);
-        acc[i] = mfma(av, bv, acc[i]);
+    for (int k = 0; k < DZ_ITEMS; ++k) {
+      const int i = tid + k * 256;
+      const int quad = i / PARTS, part = i % PARTS;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int w = c >> 1;
+        uint2 pk;
+        if (c & 1) {
+          pk.x = hi_pair(word(dzr[k][0], w), word(dzr[k][1], w));
+          pk.y = hi_pair(word(dzr[k][2], w), word(dzr[k][3], w));
+        } else {
+          pk.x = lo_pair(word(dzr[k][0], w), word(dzr[k][1], w));
+          pk.y = lo_pair(word(dzr[k][2], w), word(dzr[k][3], w));
+        }
+        *reinterpret_cast<uint2*>(dzt + (part * 8 + c) * kPP + quad * 4) = pk;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < X_ITEMS; ++k) {
+      const int i = tid + k * 256;
+      if (i >= kHaloPairs) continue;
+      const int pair = i >> 2, part = i & 3;
+      const int hy = pair / (kHalo / 2), hx = (pair % (kHalo / 2)) * 2;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int w = c >> 1;
+        const uint32_t v = (c & 1) ? hi_pair(word(xr[k][0], w), word(xr[k][1], w))
+                                   : lo_pair(word(xr[k][0], w), word(xr[k][1], w));
+        *reinterpret_cast<uint32_t*>(xt + (part * 8 + c) * kHP + hy * kHR + hx) = v;
+      }
+    }
+  };
+
+  if (s < npatch) load(s);
+  for (int pt = s; pt < npatch; pt += a.splits) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (pt + a.splits < npatch) load(pt + a.splits);
+#pragma unroll 1
+    for (int ks = 0; ks < 8; ++ks) {
+      // K step ks: patch pixels 32 ks .. 32 ks + 31; lane group grp holds
+      // pixels 32 ks + 8 grp .. + 7 = row 2 ks + grp / 2, columns 8 (grp % 2) ...
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(dzt + (mb * 16 + lr) * kPP + ks * 32 +
+                                                         grp * 8);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const uint16_t* col = xt + ((cb0 + cb) * 16 + lr) * kHP + (2 * ks + (grp >> 1)) * kHR +
+                              (grp & 1) * 8;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+          const uint4 v = *reinterpret_cast<const uint4*>(col + ky * kHR);
+          const uint32_t e = *reinterpret_cast<const uint32_t*>(col + ky * kHR + 8);
+          const uint4 v1 = make_uint4(__builtin_amdgcn_alignbit(v.y, v.x, 16),
+                                      __builtin_amdgcn_alignbit(v.z, v.y, 16),
+                                      __builtin_amdgcn_alignbit(v.w, v.z, 16),
+                                      __builtin_amdgcn_alignbit(e, v.w, 16));
+          const uint4 v2 = make_uint4(v.y, v.z, v.w, e);
+          acc[ky * 3 + 0][cb] = mfma(av, __builtin_bit_cast(bf16x8, v), acc[ky * 3 + 0][cb]);
+          acc[ky * 3 + 1][cb] = mfma(av, __builtin_bit_cast(bf16x8, v1), acc[ky * 3 + 1][cb]);
+          acc[ky * 3 + 2][cb] = mfma(av, __builtin_bit_cast(bf16x8, v2), acc[ky * 3 + 2][cb]);
+        }
       }
     }
   }
 
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const int ci = ci0 + (nb0 + i) * 16 + lr;
+  for (int t = 0; t < 9; ++t)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int co = co0 + mb * 16 + (lane >> 4) * 4 + j;
-      a.part[(((int64_t)s * a.Cout + co) * 9 + tap) * a.Cin + ci] = acc[i][j];
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int ci = ci0 + (cb0 + cb) * 16 + lr;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int co = co0 + mb * 16 + grp * 4 + j;
+        a.part[(((int64_t)s * a.Cout + co) * 9 + t) * a.Cin + ci] = acc[t][cb][j];
+      }
     }
-  }
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
@@ -257,19 +335,39 @@ hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Reductions and elementwise kernels.
 
-// out[i] = sum over s = 0..splits-1, in that order, of part[s * n + i].
-__global__ void k_reduce_splits(const float* part, int splits, int64_t n, float* out) {
+// out[g * n + i] = sum over s = g S .. min((g + 1) S, splits) - 1, in that
+// order, of part[s * n + i]; one thread per (i, g).
+__global__ void k_reduce_groups(const float* part, int splits, int64_t n, int S, float* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int s0 = (int)blockIdx.y * S, s1 = min(splits, s0 + S);
   float acc = 0.f;
-  for (int s = 0; s < splits; ++s) acc += part[(int64_t)s * n + i];
-  out[i] = acc;
+#pragma unroll 8
+  for (int s = s0; s < s1; ++s) acc += part[(int64_t)s * n + i];
+  out[(int64_t)blockIdx.y * n + i] = acc;
 }
 
-hipError_t launch_reduce_splits(const float* part, int splits, int64_t n, float* out,
+int reduce_scratch_groups(int splits) {
+  return splits <= kReduceGroup ? 0 : (splits + kReduceGroup - 1) / kReduceGroup;
+}
+
+// out[i] = sum of part[s * n + i] over the splits: in order within groups of
+// kReduceGroup consecutive splits, then over the groups in order (tmp holds
+// the group sums, reduce_scratch_groups(splits) * n floats).
+hipError_t launch_reduce_splits(const float* part, int splits, int64_t n, float* tmp, float* out,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
-                     splits, n, out);
+  if (splits < 1 || n < 1) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  const int G = reduce_scratch_groups(splits);
+  if (G == 0) {
+    hipLaunchKernelGGL(k_reduce_groups, dim3(nb, 1), dim3(256), 0, s, part, splits, n, splits,
+                       out);
+  } else {
+    if (!tmp) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce_groups, dim3(nb, G), dim3(256), 0, s, part, splits, n,
+                       kReduceGroup, tmp);
+    hipLaunchKernelGGL(k_reduce_groups, dim3(nb, 1), dim3(256), 0, s, tmp, G, n, G, out);
+  }
   return hipGetLastError();
 }
 
@@ -420,47 +518,56 @@ hipError_t launch_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float*
   return hipGetLastError();
 }
 
-// ReLU backward: g <- g where the stored output y > 0, else 0; dz = bf16(g).
-__global__ void k_relu_bwd(float* g, const uint16_t* y, uint16_t* dz, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float v = bf2f(y[i]) > 0.f ? g[i] : 0.f;
-    g[i] = v;
-    dz[i] = f2bf(v);
+// ReLU backward with the bias gradient's partial sums: v = g where the
+// stored output y > 0, else 0; dz = bf16(v); part[blk][c] = sum of v[p, c]
+// over pixels p of block blk's range [blk P / nblk, (blk + 1) P / nblk).  A
+// thread handles 4 consecutive channels of one pixel (C / 4 threads per
+// pixel, 1024 / C pixels per pass, each thread summing its pixels in order);
+// the per-thread sums are then added in LDS in pixel order.
+__global__ __launch_bounds__(256) void k_relu_bwd_bias(const float* g, const uint16_t* y,
+                                                       uint16_t* dz, int64_t P, int C,
+                                                       float* part, int nblk) {
+  __shared__ float4 red[256];
+  const int Q = C / 4, R = 256 / Q;
+  const int r = threadIdx.x / Q, q = threadIdx.x % Q;
+  const int64_t p0 = P * blockIdx.x / nblk, p1 = P * (blockIdx.x + 1) / nblk;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int64_t p = p0 + r; p < p1; p += R) {
+    const int64_t e = p * C + q * 4;
+    const float4 gv = *reinterpret_cast<const float4*>(g + e);
+    const uint2 yv = *reinterpret_cast<const uint2*>(y + e);
+    const float v0 = bf2f((uint16_t)(yv.x & 0xFFFFu)) > 0.f ? gv.x : 0.f;
+    const float v1 = bf2f((uint16_t)(yv.x >> 16)) > 0.f ? gv.y : 0.f;
+    const float v2 = bf2f((uint16_t)(yv.y & 0xFFFFu)) > 0.f ? gv.z : 0.f;
+    const float v3 = bf2f((uint16_t)(yv.y >> 16)) > 0.f ? gv.w : 0.f;
+    acc.x += v0;
+    acc.y += v1;
+    acc.z += v2;
+    acc.w += v3;
+    uint2 pk;
+    pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+    pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
+    *reinterpret_cast<uint2*>(dz + e) = pk;
   }
-}
-
-hipError_t launch_relu_bwd(float* g, const uint16_t* y, uint16_t* dz, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_relu_bwd, dim3(4096), dim3(256), 0, s, g, y, dz, n);
-  return hipGetLastError();
-}
-
-// Per-channel sums over pixels: split s sums pixels [s P/splits, (s+1) P/splits).
-// C divides 256: the 256 threads form 256/C rows of C channels, so each
-// iteration reads 256 consecutive floats; the rows are then summed in LDS in
-// a fixed order.
-__global__ __launch_bounds__(256) void k_colsum(const float* g, int64_t P, int C, float* part,
-                                                int splits) {
-  __shared__ float red[256];
-  const int s = blockIdx.x;
-  const int R = 256 / C;
-  const int r = threadIdx.x / C, c = threadIdx.x % C;
-  const int64_t p0 = P * s / splits, p1 = P * (s + 1) / splits;
-  float acc = 0.f;
-  for (int64_t p = p0 + r; p < p1; p += R) acc += g[p * C + c];
   red[threadIdx.x] = acc;
   __syncthreads();
-  if (r == 0) {
-    float t = 0.f;
-    for (int k = 0; k < R; ++k) t += red[k * C + c];
-    part[(int64_t)s * C + c] = t;
+  if ((int)threadIdx.x < Q) {
+    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = 0; k < R; ++k) {
+      const float4 u = red[k * Q + q];
+      t.x += u.x;
+      t.y += u.y;
+      t.z += u.z;
+      t.w += u.w;
+    }
+    *reinterpret_cast<float4*>(part + (int64_t)blockIdx.x * C + q * 4) = t;
   }
 }
 
-hipError_t launch_colsum(const float* g, int64_t P, int C, float* part, int splits,
-                         hipStream_t s) {
-  if (C < 1 || C > 256 || 256 % C != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_colsum, dim3(splits), dim3(256), 0, s, g, P, C, part, splits);
+hipError_t launch_relu_bwd_bias(const float* g, const uint16_t* y, uint16_t* dz, int64_t P,
+                                int C, float* part, int nblk, hipStream_t s) {
+  if (C < 4 || C > 1024 || 1024 % C != 0 || nblk < 1 || P < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_relu_bwd_bias, dim3(nblk), dim3(256), 0, s, g, y, dz, P, C, part, nblk);
   return hipGetLastError();
 }
 
