@@ -20,7 +20,7 @@ constexpr int64_t kPartCap = int64_t(32) << 20;  // floats of split partials
 constexpr int kBiasBlocks = 1024;   // pixel ranges of the bias gradient's partials
 constexpr int kWgradBlocks = 1024;  // workgroups a weight-gradient launch aims for
 constexpr int kLossBlocks = 1024;
-constexpr int kHeadBlocks = 512;
+constexpr int kHeadBlocks = 2048;
 
 struct Layer {
   int cin, cout;

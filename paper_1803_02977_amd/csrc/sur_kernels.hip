@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sur_internal.h"
 
 namespace sur {
@@ -34,7 +36,7 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 convolution.  A workgroup (4 waves) computes a 16x16-pixel tile for
+// 3x3 convolution.  A workgroup (4 waves) computes 16x16-pixel tiles for
 // COB output channels.  Per chunk of 32 input channels it stages the tile's
 // 18x18 input halo and the COB x 9 x 32 weights in LDS; for each of the nine
 // taps every wave multiplies weights (A: 16 output channels x 32 input
@@ -42,26 +44,33 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 // tile row).  Wave w owns tile rows 4w..4w+3.  The accumulator of a tile
 // holds 4 consecutive output channels of one pixel per lane, stored as one
 // 8-byte (bfloat16) or 16-byte (float32) write.
+//
+// The grid is persistent: workgroup (g, cob) of G x (Cout / COB) takes output
+// channel block cob and tiles g, g + G, ...; its steps are (tile, input
+// chunk) pairs, and each step's global loads are issued into registers
+// before the previous step's MFMAs, so memory latency hides behind them.
+// With a single input chunk (ONE) the weights are staged once.
 constexpr int kT = 16;
 constexpr int kHalo = kT + 2;
 constexpr int kKC = 32;
 constexpr int kXP = 40;   // LDS pitch of one pixel's 32 channels (bank spread)
 constexpr int kWP = 40;   // LDS pitch of one (output channel, tap) row
 
-template <int COB>
+template <int COB, bool ONE>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t xs[kHalo * kHalo * kXP];
   __shared__ __attribute__((aligned(16))) uint16_t ws[COB * 9 * kWP];
   constexpr int MB = COB / 16;
+  constexpr int XN = kHalo * kHalo * 4, WN = COB * 9 * 4;  // 16-byte items
+  constexpr int XI = (XN + 255) / 256, WI = (WN + 255) / 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles_x = (a.W + kT - 1) / kT, tiles_y = (a.H + kT - 1) / kT;
-  int t = blockIdx.x;
-  const int tx = t % tiles_x;
-  t /= tiles_x;
-  const int ty = t % tiles_y;
-  const int b = t / tiles_y;
-  const int co0 = blockIdx.y * COB;
-  const int y0 = ty * kT, x0 = tx * kT;
+  const int ntiles = a.B * tiles_x * tiles_y;
+  const int nco = a.Cout / COB;
+  const int cob = blockIdx.x % nco, g = blockIdx.x / nco, G = gridDim.x / nco;
+  const int co0 = cob * COB;
+  const int nchunk = ONE ? 1 : a.Cin / kKC;
+  const int nsteps = (g < ntiles ? (ntiles - g + G - 1) / G : 0) * nchunk;
   const int lr = lane & 15, lk = (lane >> 4) * 8;
 
   f32x4 acc[MB][4];
@@ -70,24 +79,67 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int ci0 = 0; ci0 < a.Cin; ci0 += kKC) {
-    __syncthreads();
-    for (int i = tid; i < kHalo * kHalo * 4; i += 256) {
+  uint4 xr[XI], wr[ONE ? 1 : WI];
+  auto load_w = [&](int ci0, int j) {
+    const int i = tid + j * 256;
+    const int row = i >> 2, part = i & 3;  // row = co * 9 + tap
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (i < WN)
+      v = *reinterpret_cast<const uint4*>(a.w + ((int64_t)co0 * 9 + row) * a.Cin + ci0 + part * 8);
+    return v;
+  };
+  auto load = [&](int k) {
+    int t = g + (k / nchunk) * G;
+    const int ci0 = (k % nchunk) * kKC;
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int ty = t % tiles_y, b = t / tiles_y;
+    const int y0 = ty * kT, x0 = tx * kT;
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      const int i = tid + j * 256;
       const int pix = i >> 2, part = i & 3;
       const int gy = y0 + pix / kHalo - 1, gx = x0 + pix % kHalo - 1;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+      if (i < XN && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
         v = *reinterpret_cast<const uint4*>(
             a.x + (((int64_t)b * a.H + gy) * a.W + gx) * a.Cin + ci0 + part * 8);
-      *reinterpret_cast<uint4*>(xs + pix * kXP + part * 8) = v;
+      xr[j] = v;
     }
-    for (int i = tid; i < COB * 9 * 4; i += 256) {
-      const int row = i >> 2, part = i & 3;  // row = co * 9 + tap
-      const uint4 v = *reinterpret_cast<const uint4*>(
-          a.w + ((int64_t)co0 * 9 + row) * a.Cin + ci0 + part * 8);
-      *reinterpret_cast<uint4*>(ws + row * kWP + part * 8) = v;
+    if (!ONE) {
+#pragma unroll
+      for (int j = 0; j < WI; ++j) wr[j] = load_w(ci0, j);
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      const int i = tid + j * 256;
+      if (i < XN) *reinterpret_cast<uint4*>(xs + (i >> 2) * kXP + (i & 3) * 8) = xr[j];
+    }
+    if (!ONE) {
+#pragma unroll
+      for (int j = 0; j < WI; ++j) {
+        const int i = tid + j * 256;
+        if (i < WN) *reinterpret_cast<uint4*>(ws + (i >> 2) * kWP + (i & 3) * 8) = wr[j];
+      }
+    }
+  };
+
+  if (ONE) {
+#pragma unroll
+    for (int j = 0; j < WI; ++j) {
+      const int i = tid + j * 256;
+      const uint4 v = load_w(0, j);
+      if (i < WN) *reinterpret_cast<uint4*>(ws + (i >> 2) * kWP + (i & 3) * 8) = v;
+    }
+  }
+  if (nsteps > 0) load(0);
+  for (int k = 0; k < nsteps; ++k) {
     __syncthreads();
+    store();
+    __syncthreads();
+    if (k + 1 < nsteps) load(k + 1);
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
       const int ky = tap / 3, kx = tap % 3;
@@ -105,43 +157,72 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mfma(av[mb], bv[nb], acc[mb][nb]);
     }
-  }
+    if (k % nchunk != nchunk - 1) continue;
 
+    int t = g + (k / nchunk) * G;
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int ty = t % tiles_y, b = t / tiles_y;
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int py = y0 + wave * 4 + nb, px = x0 + lr;
-    if (py >= a.H || px >= a.W) continue;
-    const int64_t p = ((int64_t)b * a.H + py) * a.W + px;
+    for (int nb = 0; nb < 4; ++nb) {
+      const int py = ty * kT + wave * 4 + nb, px = tx * kT + lr;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const int co = co0 + mb * 16 + (lane >> 4) * 4;
-      float v[4];
+      for (int mb = 0; mb < MB; ++mb) {
+        const f32x4 r = acc[mb][nb];
+        acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (py >= a.H || px >= a.W) continue;
+        const int64_t p = ((int64_t)b * a.H + py) * a.W + px;
+        const int co = co0 + mb * 16 + (lane >> 4) * 4;
+        float v[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        v[j] = acc[mb][nb][j] + (a.bias ? a.bias[co + j] : 0.f);
-        if (a.relu) v[j] = fmaxf(v[j], 0.f);
-      }
-      if (a.out_f32) {
-        *reinterpret_cast<float4*>(a.outf + p * a.Cout + co) = make_float4(v[0], v[1], v[2], v[3]);
-      } else {
-        uint2 pk;
-        pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-        pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-        *reinterpret_cast<uint2*>(a.outb + p * a.Cout + co) = pk;
+        for (int j = 0; j < 4; ++j) {
+          v[j] = r[j] + (a.bias ? a.bias[co + j] : 0.f);
+          if (a.relu) v[j] = fmaxf(v[j], 0.f);
+        }
+        if (a.out_f32) {
+          *reinterpret_cast<float4*>(a.outf + p * a.Cout + co) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          uint2 pk;
+          pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+          pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+          *reinterpret_cast<uint2*>(a.outb + p * a.Cout + co) = pk;
+        }
       }
     }
   }
 }
 
+// Workgroups a persistent launch can keep resident at once.
+template <int COB, bool ONE>
+int resident_groups() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_conv3x3<COB, ONE>, 256, 0) != hipSuccess ||
+        cus < 1 || per < 1)
+      return 256;
+    n = cus * per;
+  }
+  return n;
+}
+
+template <int COB, bool ONE>
+hipError_t launch_conv_cob(const ConvArgs& a, hipStream_t s) {
+  const int tiles = a.B * ((a.H + kT - 1) / kT) * ((a.W + kT - 1) / kT);
+  const int nco = a.Cout / COB;
+  const int G = std::max(1, std::min(tiles, resident_groups<COB, ONE>() / nco));
+  hipLaunchKernelGGL((k_conv3x3<COB, ONE>), dim3(G * nco), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   if (a.Cin % 32 != 0 || a.Cout % 32 != 0 || a.B < 1 || a.H < 1 || a.W < 1)
     return hipErrorInvalidValue;
-  const int tiles = a.B * ((a.H + kT - 1) / kT) * ((a.W + kT - 1) / kT);
   if (a.Cout % 64 == 0)
-    hipLaunchKernelGGL(k_conv3x3<64>, dim3(tiles, a.Cout / 64), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_conv3x3<32>, dim3(tiles, a.Cout / 32), dim3(256), 0, s, a);
-  return hipGetLastError();
+    return a.Cin == kKC ? launch_conv_cob<64, true>(a, s) : launch_conv_cob<64, false>(a, s);
+  return a.Cin == kKC ? launch_conv_cob<32, true>(a, s) : launch_conv_cob<32, false>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -622,16 +703,25 @@ hipError_t launch_loss(const float* y, const double* target, const double* U, in
   return hipGetLastError();
 }
 
-__global__ void k_reduce_f64(const double* part, int n, double scale, double* out) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// out = scale * (sum of part[0..n)): thread t sums part[t], part[t + 256], ...
+// in order, then the 256 sums are added pairwise in a fixed tree.
+__global__ __launch_bounds__(256) void k_reduce_f64(const double* part, int n, double scale,
+                                                    double* out) {
+  __shared__ double red[256];
   double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += part[i];
-  out[0] = acc * scale;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] * scale;
 }
 
 hipError_t launch_reduce_f64(const double* part, int n, double scale, double* out,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(64), 0, s, part, n, scale, out);
+  hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, s, part, n, scale, out);
   return hipGetLastError();
 }
 
