@@ -505,25 +505,57 @@ hipError_t launch_features(const double* K, const double* U, const double* h0, u
   return hipGetLastError();
 }
 
-// 2x2 average pool of bfloat16 maps (C channels; Ho x Wo output).
-__global__ void k_pool(const uint16_t* x, uint16_t* out, int B, int Ho, int Wo, int C) {
-  const int64_t n = (int64_t)B * Ho * Wo * C;
+// Channel groups per pixel must be a power of two (the channel counts of the
+// network are); lg is its log2, so a flat index splits by shifts.
+static bool pow2_groups(int C, int per, int* lg) {
+  if (C < per || C % per != 0) return false;
+  const int g = C / per;
+  if (g & (g - 1)) return false;
+  int l = 0;
+  while ((1 << l) < g) ++l;
+  *lg = l;
+  return true;
+}
+
+// 2x2 average pool of bfloat16 maps (C channels; Ho x Wo output), 8 channels
+// (16 bytes) per thread and iteration.
+__global__ void k_pool(const uint16_t* x, uint16_t* out, int B, int Ho, int Wo, int C, int lg) {
+  const int64_t n = ((int64_t)B * Ho * Wo) << lg;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const int64_t q = i / C;
-    const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), b = (int)(q / ((int64_t)Wo * Ho));
+    const int c = (int)(i & ((1 << lg) - 1)) * 8;
+    const int q = (int)(i >> lg);
+    const int xo = q % Wo, yo = (q / Wo) % Ho, b = q / (Wo * Ho);
     const int W = 2 * Wo;
     const int64_t r0 = ((int64_t)b * 2 * Ho + 2 * yo) * W + 2 * xo, r1 = r0 + W;
-    const float s = ((bf2f(x[r0 * C + c]) + bf2f(x[(r0 + 1) * C + c])) + bf2f(x[r1 * C + c])) +
-                    bf2f(x[(r1 + 1) * C + c]);
-    out[i] = f2bf(s * 0.25f);
+    const uint4 v00 = *reinterpret_cast<const uint4*>(x + r0 * C + c);
+    const uint4 v01 = *reinterpret_cast<const uint4*>(x + (r0 + 1) * C + c);
+    const uint4 v10 = *reinterpret_cast<const uint4*>(x + r1 * C + c);
+    const uint4 v11 = *reinterpret_cast<const uint4*>(x + (r1 + 1) * C + c);
+    uint32_t o[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t a0 = word(v00, w), a1 = word(v01, w), a2 = word(v10, w), a3 = word(v11, w);
+      uint32_t r = 0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int sh = 16 * h;
+        const float t = ((bf2f((uint16_t)(a0 >> sh)) + bf2f((uint16_t)(a1 >> sh))) +
+                         bf2f((uint16_t)(a2 >> sh))) +
+                        bf2f((uint16_t)(a3 >> sh));
+        r |= (uint32_t)f2bf(t * 0.25f) << sh;
+      }
+      o[w] = r;
+    }
+    *reinterpret_cast<uint4*>(out + (int64_t)q * C + c) = make_uint4(o[0], o[1], o[2], o[3]);
   }
 }
 
 hipError_t launch_pool(const uint16_t* x, uint16_t* out, int B, int Ho, int Wo, int C,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_pool, dim3(2048), dim3(256), 0, s, x, out, B, Ho, Wo, C);
+  int lg;
+  if (!pow2_groups(C, 8, &lg)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pool, dim3(2048), dim3(256), 0, s, x, out, B, Ho, Wo, C, lg);
   return hipGetLastError();
 }
 
@@ -556,46 +588,61 @@ hipError_t launch_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out
 }
 
 // Gradient of the upsampled part of a concatenation: glow (H/2 x W/2, Cu
-// channels) = sum of the 2x2 block of gcat[..., 0:Cu] (H x W, Ccat channels).
-__global__ void k_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat) {
+// channels) = sum of the 2x2 block of gcat[..., 0:Cu] (H x W, Ccat channels);
+// 4 channels (16 bytes) per thread and iteration.
+__global__ void k_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat,
+                         int lg) {
   const int Ho = H / 2, Wo = W / 2;
-  const int64_t n = (int64_t)B * Ho * Wo * Cu;
+  const int64_t n = ((int64_t)B * Ho * Wo) << lg;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % Cu);
-    const int64_t q = i / Cu;
-    const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), b = (int)(q / ((int64_t)Wo * Ho));
+    const int c = (int)(i & ((1 << lg) - 1)) * 4;
+    const int q = (int)(i >> lg);
+    const int xo = q % Wo, yo = (q / Wo) % Ho, b = q / (Wo * Ho);
     const int64_t r0 = ((int64_t)b * H + 2 * yo) * W + 2 * xo, r1 = r0 + W;
-    glow[i] = ((gcat[r0 * Ccat + c] + gcat[(r0 + 1) * Ccat + c]) + gcat[r1 * Ccat + c]) +
-              gcat[(r1 + 1) * Ccat + c];
+    const float4 a = *reinterpret_cast<const float4*>(gcat + r0 * Ccat + c);
+    const float4 e = *reinterpret_cast<const float4*>(gcat + (r0 + 1) * Ccat + c);
+    const float4 f = *reinterpret_cast<const float4*>(gcat + r1 * Ccat + c);
+    const float4 g = *reinterpret_cast<const float4*>(gcat + (r1 + 1) * Ccat + c);
+    *reinterpret_cast<float4*>(glow + (int64_t)q * Cu + c) =
+        make_float4(((a.x + e.x) + f.x) + g.x, ((a.y + e.y) + f.y) + g.y,
+                    ((a.z + e.z) + f.z) + g.z, ((a.w + e.w) + f.w) + g.w);
   }
 }
 
 hipError_t launch_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_up_bwd, dim3(2048), dim3(256), 0, s, gcat, glow, B, H, W, Cu, Ccat);
+  int lg;
+  if (!pow2_groups(Cu, 4, &lg) || Ccat % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_up_bwd, dim3(2048), dim3(256), 0, s, gcat, glow, B, H, W, Cu, Ccat, lg);
   return hipGetLastError();
 }
 
 // Gradient of an encoder output: its skip part gcat[..., Cu:Cu+C] plus the
-// pooled path's gradient spread over each 2x2 block (a quarter each).
+// pooled path's gradient spread over each 2x2 block (a quarter each); 4
+// channels (16 bytes) per thread and iteration.
 __global__ void k_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
-                               float* out, int B, int H, int W, int C) {
-  const int64_t n = (int64_t)B * H * W * C;
+                               float* out, int B, int H, int W, int C, int lg) {
+  const int64_t n = ((int64_t)B * H * W) << lg;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const int64_t p = i / C;
-    const int x = (int)(p % W), y = (int)((p / W) % H), b = (int)(p / ((int64_t)W * H));
+    const int c = (int)(i & ((1 << lg) - 1)) * 4;
+    const int p = (int)(i >> lg);
+    const int x = p % W, y = (p / W) % H, b = p / (W * H);
     const int64_t q = ((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2;
-    out[i] = gcat[p * Ccat + Cu + c] + 0.25f * gsmall[q * C + c];
+    const float4 a = *reinterpret_cast<const float4*>(gcat + (int64_t)p * Ccat + Cu + c);
+    const float4 g = *reinterpret_cast<const float4*>(gsmall + q * C + c);
+    *reinterpret_cast<float4*>(out + (int64_t)p * C + c) =
+        make_float4(a.x + 0.25f * g.x, a.y + 0.25f * g.y, a.z + 0.25f * g.z, a.w + 0.25f * g.w);
   }
 }
 
 hipError_t launch_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
                                float* out, int B, int H, int W, int C, hipStream_t s) {
+  int lg;
+  if (!pow2_groups(C, 4, &lg) || Cu % 4 != 0 || Ccat % 4 != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pool_bwd_add, dim3(2048), dim3(256), 0, s, gcat, Cu, Ccat, gsmall, out, B,
-                     H, W, C);
+                     H, W, C, lg);
   return hipGetLastError();
 }
 
