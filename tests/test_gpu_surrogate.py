@@ -81,6 +81,68 @@ def test_forward_matches_reference(shape):
     net.close()
 
 
+def test_full_batch_forward_equals_single_images_and_reference():
+    """Batch 16 of 256 x 256, the benchmark's size: the level-0 convolutions
+    have more tiles than resident workgroups, so each workgroup walks several
+    tiles (a single image: one tile per workgroup).  The forward pass works
+    image by image, so every image's output equals the same image run alone,
+    bit for bit, and two of them match the reference."""
+    torch = require_gpu()
+    B, H, W = 16, 256, 256
+    print(f"[gpu] surrogate forward, batch {B} of {H}x{W}", flush=True)
+    p, K, U, h0, _ = _problem(5, B, H, W)
+    net = _net(torch, B, H, W)
+    net.set_params(p)
+    dK, dU, dh = (_dev(torch, a) for a in (K, U, h0))
+    _, y = net.predict(dK, dU, dh, want_y=True)
+    y = y.cpu().numpy()
+    for b in (0, 7, 15):
+        sl = slice(b, b + 1)
+        _, y1 = net.predict(dK[sl].contiguous(), dU[sl].contiguous(), dh[sl].contiguous(),
+                            want_y=True)
+        assert np.array_equal(y1.cpu().numpy()[0], y[b]), b
+    for b in (0, 15):
+        sl = slice(b, b + 1)
+        ref = S.forward(p.astype(np.float64), K[sl], U[sl], h0[sl], bf16=True)["y"]
+        assert _rel(y[sl].astype(np.float64), ref) < REL_Y, (b, _rel(y[sl], ref))
+    net.close()
+
+
+def test_batch_gradient_is_the_mean_of_single_image_gradients():
+    """Batch 4 of 256 x 256: the weight gradient's splits then take several
+    patches each (a single image: one patch per split).  The loss is a mean
+    over all interior cells, so the batch's loss and gradient are the means of
+    the four single-image ones; the output gradient of the batch is a single
+    image's times exactly 1/4, so only the float32 summation order of the
+    weight and bias gradients differs."""
+    torch = require_gpu()
+    B, H, W = 4, 256, 256
+    print(f"[gpu] surrogate gradient, batch {B} of {H}x{W} against single images", flush=True)
+    p, K, U, h0, ht = _problem(6, B, H, W)
+    net = _net(torch, B, H, W)
+    net.set_params(p)
+    args = [_dev(torch, a) for a in (K, U, h0, ht)]
+    loss, g = net.loss_grad(*args)
+    g = g.cpu().numpy().astype(np.float64)
+    losses, gsum = [], np.zeros_like(g)
+    for b in range(B):
+        lb, gb = net.loss_grad(*[a[b:b + 1].contiguous() for a in args])
+        losses.append(lb)
+        gsum += gb.cpu().numpy().astype(np.float64)
+    gmean = gsum / B
+    assert abs(loss - sum(losses) / B) <= 1e-12 * loss, (loss, losses)
+    layout, _ = S.param_layout()
+    for name, cin, cout in S.layer_table():
+        off = layout[name][0]
+        nw = cout * 9 * cin
+        for part, (a, b) in (("w", (off, off + nw)), ("b", (off + nw, off + nw + cout))):
+            r = _rel(g[a:b], gmean[a:b])
+            assert r < 1e-4, (name, part, r)
+    ho = layout["head"][0]
+    assert _rel(g[ho:], gmean[ho:]) < 1e-4
+    net.close()
+
+
 @pytest.mark.parametrize("shape", SHAPES[:2], ids=lambda s: "x".join(map(str, s)))
 def test_gradients_match_reference(shape):
     torch = require_gpu()
