@@ -41,9 +41,13 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 // 18x18 input halo and the COB x 9 x 32 weights in LDS; for each of the nine
 // taps every wave multiplies weights (A: 16 output channels x 32 input
 // channels) by shifted input pixels (B: 32 input channels x 16 pixels of one
-// tile row).  Wave w owns tile rows 4w..4w+3.  The accumulator of a tile
-// holds 4 consecutive output channels of one pixel per lane, stored as one
-// 8-byte (bfloat16) or 16-byte (float32) write.
+// tile row).  A wave owns two 16-channel output blocks and NR tile rows (NR =
+// 8 for COB = 64, 4 for COB = 32) and takes the taps by column shift kx: the
+// three row-shift weights of one kx stay in registers while the halo rows
+// stream past, each loaded once and used for every (row, ky) pair it
+// serves.  The accumulator of a tile holds 4 consecutive output channels of
+// one pixel per lane, stored as one 8-byte (bfloat16) or 16-byte (float32)
+// write.
 //
 // The grid is persistent: workgroup (g, cob) of G x (Cout / COB) takes output
 // channel block cob and tiles g, g + G, ...; its steps are (tile, input
@@ -57,10 +61,12 @@ constexpr int kXP = 40;   // LDS pitch of one pixel's 32 channels (bank spread)
 constexpr int kWP = 40;   // LDS pitch of one (output channel, tap) row
 
 template <int COB, bool ONE>
-__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+__global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t xs[kHalo * kHalo * kXP];
   __shared__ __attribute__((aligned(16))) uint16_t ws[COB * 9 * kWP];
-  constexpr int MB = COB / 16;
+  constexpr int MB = COB / 16;     // 16-channel output blocks of the workgroup
+  constexpr int MBW = 2;           // of them per wave
+  constexpr int NR = MB * kT / (4 * MBW);  // tile rows per wave
   constexpr int XN = kHalo * kHalo * 4, WN = COB * 9 * 4;  // 16-byte items
   constexpr int XI = (XN + 255) / 256, WI = (WN + 255) / 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -72,12 +78,13 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
   const int nchunk = ONE ? 1 : a.Cin / kKC;
   const int nsteps = (g < ntiles ? (ntiles - g + G - 1) / G : 0) * nchunk;
   const int lr = lane & 15, lk = (lane >> 4) * 8;
+  const int cb0 = (wave % (MB / MBW)) * MBW, row0 = (wave / (MB / MBW)) * NR;
 
-  f32x4 acc[MB][4];
+  f32x4 acc[MBW][NR];
 #pragma unroll
-  for (int i = 0; i < MB; ++i)
+  for (int i = 0; i < MBW; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NR; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   uint4 xr[XI], wr[ONE ? 1 : WI];
   auto load_w = [&](int ci0, int j) {
@@ -141,21 +148,27 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
     __syncthreads();
     if (k + 1 < nsteps) load(k + 1);
 #pragma unroll 1
-    for (int tap = 0; tap < 9; ++tap) {
-      const int ky = tap / 3, kx = tap % 3;
-      bf16x8 av[MB], bv[4];
+    for (int kx = 0; kx < 3; ++kx) {
+      bf16x8 av[3][MBW];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-        av[mb] = *reinterpret_cast<const bf16x8*>(ws + ((mb * 16 + lr) * 9 + tap) * kWP + lk);
+      for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int py = wave * 4 + nb;
-        bv[nb] = *reinterpret_cast<const bf16x8*>(xs + ((py + ky) * kHalo + lr + kx) * kXP + lk);
+        for (int mb = 0; mb < MBW; ++mb)
+          av[ky][mb] = *reinterpret_cast<const bf16x8*>(
+              ws + (((cb0 + mb) * 16 + lr) * 9 + ky * 3 + kx) * kWP + lk);
+      // Halo row row0 + r serves output row nb = r - ky of tap (ky, kx).
+#pragma unroll
+      for (int r = 0; r < NR + 2; ++r) {
+        const bf16x8 bv =
+            *reinterpret_cast<const bf16x8*>(xs + ((row0 + r) * kHalo + lr + kx) * kXP + lk);
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+          const int nb = r - ky;
+          if (nb < 0 || nb >= NR) continue;
+#pragma unroll
+          for (int mb = 0; mb < MBW; ++mb) acc[mb][nb] = mfma(av[ky][mb], bv, acc[mb][nb]);
+        }
       }
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mfma(av[mb], bv[nb], acc[mb][nb]);
     }
     if (k % nchunk != nchunk - 1) continue;
 
@@ -164,15 +177,15 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
     t /= tiles_x;
     const int ty = t % tiles_y, b = t / tiles_y;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const int py = ty * kT + wave * 4 + nb, px = tx * kT + lr;
+    for (int nb = 0; nb < NR; ++nb) {
+      const int py = ty * kT + row0 + nb, px = tx * kT + lr;
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
+      for (int mb = 0; mb < MBW; ++mb) {
         const f32x4 r = acc[mb][nb];
         acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
         if (py >= a.H || px >= a.W) continue;
         const int64_t p = ((int64_t)b * a.H + py) * a.W + px;
-        const int co = co0 + mb * 16 + (lane >> 4) * 4;
+        const int co = co0 + (cb0 + mb) * 16 + (lane >> 4) * 4;
         float v[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
