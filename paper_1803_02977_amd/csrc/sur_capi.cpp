@@ -18,7 +18,6 @@ constexpr int kChannels[4] = {32, 64, 128, 256};
 constexpr int kNumConv = 14;
 constexpr int64_t kPartCap = int64_t(32) << 20;  // floats of split partials
 constexpr int kBiasBlocks = 1024;   // pixel ranges of the bias gradient's partials
-constexpr int kWgradBlocks = 1024;  // workgroups a weight-gradient launch aims for
 constexpr int kLossBlocks = 1024;
 constexpr int kHeadBlocks = 2048;
 
@@ -208,7 +207,9 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x) {
   const int64_t n = (int64_t)L.cout * 9 * L.cin;
   const int per = sur::wgrad_blocks_per_split(L.cin, L.cout);
   const int patches = sur::wgrad_patches(B, H, W);
-  int splits = std::max(1, (kWgradBlocks + per - 1) / per);
+  // One round of resident workgroups: a second, partly filled round would
+  // cost as long as the first.
+  int splits = std::max(1, sur::wgrad_resident(L.cout) / per);
   splits = std::min(splits, patches);
   // Partials and their group sums must fit the partial buffer.
   while (splits > 1 &&

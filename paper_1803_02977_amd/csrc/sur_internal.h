@@ -42,6 +42,7 @@ struct WgradArgs {
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s);
 int wgrad_blocks_per_split(int Cin, int Cout);
+int wgrad_resident(int Cout);  // workgroups the weight-gradient kernel keeps resident
 int wgrad_patches(int B, int H, int W);
 
 // Split partials are summed in groups of kReduceGroup consecutive splits,

@@ -205,27 +205,28 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
   }
 }
 
-// Workgroups a persistent launch can keep resident at once.
-template <int COB, bool ONE>
-int resident_groups() {
-  static int n = 0;
-  if (n == 0) {
+// Workgroups of 256 threads of kernel fn that the device keeps resident at
+// once (computed on first use; *cache holds it).
+template <typename F>
+int resident_groups(F fn, int* cache) {
+  if (*cache == 0) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_conv3x3<COB, ONE>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess ||
         cus < 1 || per < 1)
       return 256;
-    n = cus * per;
+    *cache = cus * per;
   }
-  return n;
+  return *cache;
 }
 
 template <int COB, bool ONE>
 hipError_t launch_conv_cob(const ConvArgs& a, hipStream_t s) {
   const int tiles = a.B * ((a.H + kT - 1) / kT) * ((a.W + kT - 1) / kT);
   const int nco = a.Cout / COB;
-  const int G = std::max(1, std::min(tiles, resident_groups<COB, ONE>() / nco));
+  static int resident = 0;
+  const int G = std::max(1, std::min(tiles, resident_groups(k_conv3x3<COB, ONE>, &resident) / nco));
   hipLaunchKernelGGL((k_conv3x3<COB, ONE>), dim3(G * nco), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -414,6 +415,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         a.part[(((int64_t)s * a.Cout + co) * 9 + t) * a.Cin + ci] = acc[t][cb][j];
       }
     }
+}
+
+int wgrad_resident(int Cout) {
+  static int r64 = 0, r32 = 0;
+  return (Cout % 64 == 0) ? resident_groups(k_wgrad<64>, &r64) : resident_groups(k_wgrad<32>, &r32);
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
