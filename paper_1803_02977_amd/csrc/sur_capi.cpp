@@ -74,7 +74,7 @@ struct lem_sur_ctx {
   float *p, *m, *v, *g;
   uint16_t *pb, *wd;
   uint16_t* x0;
-  uint16_t *a_enc[4], *e[4], *pool[3], *cat[3], *a_dec[3], *d[3];
+  uint16_t *a_enc[4], *e[4], *pool[3], *a_dec[3], *d[3];
   float *y, *dy;
   float *gw[3], *gcat[3];
   uint16_t* dz;
@@ -116,7 +116,6 @@ size_t carve(lem_sur_ctx* c, char* base) {
   for (int l = 0; l < 3; ++l) {
     c->pool[l] = (uint16_t*)take(2 * px(c, l + 1) * kChannels[l]);
     const int ccat = kChannels[l + 1] + kChannels[l];
-    c->cat[l] = (uint16_t*)take(2 * px(c, l) * ccat);
     c->a_dec[l] = (uint16_t*)take(2 * px(c, l) * kChannels[l]);
     c->d[l] = (uint16_t*)take(2 * px(c, l) * kChannels[l]);
     c->gcat[l] = (float*)take(4 * px(c, l) * ccat);
@@ -148,10 +147,14 @@ lem_status fail(lem_sur_ctx* c, lem_status st, const std::string& m) {
                                              hipGetErrorString(e_));             \
   } while (0)
 
+// x may be the concatenation [upsampled xu (cu channels), x] (xu null: x alone).
 lem_status conv(lem_sur_ctx* c, int B, int level, const uint16_t* x, int cin, const uint16_t* w,
-                const float* bias, int cout, bool relu, uint16_t* outb, float* outf) {
+                const float* bias, int cout, bool relu, uint16_t* outb, float* outf,
+                const uint16_t* xu = nullptr, int cu = 0) {
   sur::ConvArgs a{};
   a.x = x;
+  a.xu = xu;
+  a.Cu = cu;
   a.w = w;
   a.bias = bias;
   a.outb = outb;
@@ -167,11 +170,16 @@ lem_status conv(lem_sur_ctx* c, int B, int level, const uint16_t* x, int cin, co
   return LEM_OK;
 }
 
-lem_status conv_layer(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x, uint16_t* out) {
+lem_status conv_layer(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x, uint16_t* out,
+                      const uint16_t* xu = nullptr, int cu = 0) {
   const Layer& L = table().conv[li];
   return conv(c, B, level, x, L.cin, c->pb + L.off,
-              c->p + L.off + (int64_t)L.cout * 9 * L.cin, L.cout, true, out, nullptr);
+              c->p + L.off + (int64_t)L.cout * 9 * L.cin, L.cout, true, out, nullptr, xu, cu);
 }
+
+// The lower-resolution input of decoder level l: the encoder's bottom output
+// for l = 2, else the decoder output of level l + 1.
+const uint16_t* decoder_low(const lem_sur_ctx* c, int l) { return l == 2 ? c->e[3] : c->d[l + 1]; }
 
 lem_status forward(lem_sur_ctx* c, int B, const double* K, const double* U, const double* h0) {
   lem_status st;
@@ -187,13 +195,13 @@ lem_status forward(lem_sur_ctx* c, int B, const double* K, const double* U, cons
       x = c->pool[l];
     }
   }
-  const uint16_t* low = c->e[3];
+  // Decoder: the first convolution of level l reads the concatenation
+  // [upsampled lower level, skip] straight from the two maps.
   for (int l = 2; l >= 0; --l) {
-    SUR_CHECK(sur::launch_upcat(low, c->e[l], c->cat[l], B, c->H >> l, c->W >> l,
-                                kChannels[l + 1], kChannels[l], c->s));
-    if ((st = conv_layer(c, B, l, kDecA[l], c->cat[l], c->a_dec[l])) != LEM_OK) return st;
+    if ((st = conv_layer(c, B, l, kDecA[l], c->e[l], c->a_dec[l], decoder_low(c, l),
+                         kChannels[l + 1])) != LEM_OK)
+      return st;
     if ((st = conv_layer(c, B, l, kDecB[l], c->a_dec[l], c->d[l])) != LEM_OK) return st;
-    low = c->d[l];
   }
   const int64_t ho = table().head_off;
   SUR_CHECK(sur::launch_head(c->d[0], c->pb + ho, c->p + ho + sur::kHeadChannels, c->y, P0, c->s));
@@ -201,7 +209,8 @@ lem_status forward(lem_sur_ctx* c, int B, const double* K, const double* U, cons
 }
 
 // Weight gradient of layer li into c->g (split partials, then their sum).
-lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x) {
+lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x,
+                 const uint16_t* xu = nullptr, int cu = 0) {
   const Layer& L = table().conv[li];
   const int H = c->H >> level, W = c->W >> level;
   const int64_t n = (int64_t)L.cout * 9 * L.cin;
@@ -217,6 +226,8 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x) {
     --splits;
   sur::WgradArgs a{};
   a.x = x;
+  a.xu = xu;
+  a.Cu = cu;
   a.dz = c->dz;
   a.part = c->part;
   a.B = B;
@@ -243,9 +254,11 @@ lem_status relu_bias_bwd(lem_sur_ctx* c, int li, const float* g, const uint16_t*
 }
 
 // Backward through conv(lb)(relu(conv(la)(x))) + ReLU given the gradient ge of
-// its output e; gx (float32, cin(la) channels) may be null.
+// its output e; gx (float32, cin(la) channels) may be null.  x may be the
+// concatenation [upsampled xu (cu channels), x].
 lem_status block_bwd(lem_sur_ctx* c, int B, int level, const uint16_t* x, const uint16_t* a,
-                     const uint16_t* e, const float* ge, int la, int lb, float* gx) {
+                     const uint16_t* e, const float* ge, int la, int lb, float* gx,
+                     const uint16_t* xu = nullptr, int cu = 0) {
   lem_status st;
   const Layer& A = table().conv[la];
   const Layer& Bl = table().conv[lb];
@@ -257,7 +270,7 @@ lem_status block_bwd(lem_sur_ctx* c, int B, int level, const uint16_t* x, const 
                  ga)) != LEM_OK)
     return st;
   if ((st = relu_bias_bwd(c, la, ga, a, P)) != LEM_OK) return st;
-  if ((st = wgrad(c, B, level, la, x)) != LEM_OK) return st;
+  if ((st = wgrad(c, B, level, la, x, xu, cu)) != LEM_OK) return st;
   if (gx && (st = conv(c, B, level, c->dz, A.cout, c->wd + A.off, nullptr, A.cin, false, nullptr,
                        gx)) != LEM_OK)
     return st;
@@ -286,8 +299,8 @@ lem_status backward(lem_sur_ctx* c, int B, const double* U, const double* target
   // its upsampled part becomes the gradient of the level below's output.
   float* g = c->gw[0];
   for (int l = 0; l < 3; ++l) {
-    if ((st = block_bwd(c, B, l, c->cat[l], c->a_dec[l], c->d[l], g, kDecA[l], kDecB[l],
-                        c->gcat[l])) != LEM_OK)
+    if ((st = block_bwd(c, B, l, c->e[l], c->a_dec[l], c->d[l], g, kDecA[l], kDecB[l],
+                        c->gcat[l], decoder_low(c, l), kChannels[l + 1])) != LEM_OK)
       return st;
     float* glow = (g == c->gw[0]) ? c->gw[1] : c->gw[0];
     SUR_CHECK(sur::launch_up_bwd(c->gcat[l], glow, B, c->H >> l, c->W >> l, kChannels[l + 1],
@@ -462,7 +475,7 @@ lem_status lem_sur_activation(lem_sur_ctx* c, int32_t index, int32_t batch, uint
   } else if (index >= 12 && index <= 20) {
     level = 2 - (index - 12) / 3;
     const int k = (index - 12) % 3;
-    src = k == 0 ? c->cat[level] : (k == 1 ? c->a_dec[level] : c->d[level]);
+    src = k == 0 ? nullptr : (k == 1 ? c->a_dec[level] : c->d[level]);
     ch = k == 0 ? kChannels[level + 1] + kChannels[level] : kChannels[level];
   } else {
     return fail(c, LEM_E_ARG, "unknown activation index");
@@ -471,9 +484,15 @@ lem_status lem_sur_activation(lem_sur_ctx* c, int32_t index, int32_t batch, uint
   if (channels) *channels = ch;
   if (height) *height = h;
   if (width) *width = w;
-  if (d_dst)
+  if (d_dst && src) {
     SUR_CHECK(hipMemcpyAsync(d_dst, src, 2 * (size_t)batch * h * w * ch, hipMemcpyDeviceToDevice,
                              c->s));
+  } else if (d_dst) {
+    // The decoder's concatenated input is never stored: it is assembled here
+    // from the two maps its convolution reads.
+    SUR_CHECK(sur::launch_upcat(decoder_low(c, level), c->e[level], d_dst, batch, h, w,
+                                kChannels[level + 1], kChannels[level], c->s));
+  }
   return LEM_OK;
 }
 

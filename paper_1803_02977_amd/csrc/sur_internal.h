@@ -19,9 +19,13 @@ constexpr int kHeadChannels = 32;
 // out[p, co] = bias[co] + sum_{tap, ci} x[p + tap offset, ci] * w[co, tap, ci],
 // optionally followed by ReLU.  x is bfloat16 NHWC with Cin channels
 // (a multiple of 32), w bfloat16 [Cout][9][Cin], out bfloat16 or float32
-// NHWC with Cout channels (a multiple of 32).
+// NHWC with Cout channels (a multiple of 32).  With xu set, the input is the
+// concatenation [nearest 2x upsample of xu (H/2 x W/2, Cu channels), x (Cin -
+// Cu channels)], read from the two maps directly (Cu a multiple of 32).
 struct ConvArgs {
   const uint16_t* x;
+  const uint16_t* xu;  // may be null (then Cu = 0)
+  int Cu;
   const uint16_t* w;
   const float* bias;   // may be null
   uint16_t* outb;      // bfloat16 output (out_f32 == 0)
@@ -33,7 +37,9 @@ struct ConvArgs {
 // Weight gradient partials: part[s][co][tap][ci] = sum over the pixels of
 // split s of dz[p, co] * x[p + tap offset, ci].
 struct WgradArgs {
-  const uint16_t* x;   // bfloat16 NHWC, Cin channels
+  const uint16_t* x;   // bfloat16 NHWC, Cin channels (Cin - Cu with xu set)
+  const uint16_t* xu;  // may be null; else channels [0, Cu) upsampled from it, as in ConvArgs
+  int Cu;
   const uint16_t* dz;  // bfloat16 NHWC, Cout channels
   float* part;
   int B, H, W, Cin, Cout, splits;

@@ -35,6 +35,17 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Channels c..c+7 of pixel (b, y, x) of a convolution input that may be the
+// concatenation [nearest 2x upsample of xu (Cu channels), x (Cin - Cu
+// channels)] (Cu = 0: all of x).
+__device__ __forceinline__ const uint16_t* conv_input(const uint16_t* x, const uint16_t* xu,
+                                                      int Cu, int Cin, int H, int W, int b,
+                                                      int y, int xx, int c) {
+  if (c < Cu)
+    return xu + (((int64_t)b * (H >> 1) + (y >> 1)) * (W >> 1) + (xx >> 1)) * Cu + c;
+  return x + (((int64_t)b * H + y) * W + xx) * (Cin - Cu) + (c - Cu);
+}
+
 // ---------------------------------------------------------------------------
 // 3x3 convolution.  A workgroup (4 waves) computes 16x16-pixel tiles for
 // COB output channels.  Per chunk of 32 input channels it stages the tile's
@@ -110,7 +121,7 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (i < XN && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
         v = *reinterpret_cast<const uint4*>(
-            a.x + (((int64_t)b * a.H + gy) * a.W + gx) * a.Cin + ci0 + part * 8);
+            conv_input(a.x, a.xu, a.Cu, a.Cin, a.H, a.W, b, gy, gx, ci0 + part * 8));
       xr[j] = v;
     }
     if (!ONE) {
@@ -231,8 +242,16 @@ hipError_t launch_conv_cob(const ConvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// A concatenated input needs whole 32-channel chunks from each part and an
+// even-sized map.
+static bool valid_split(const uint16_t* xu, int Cu, int Cin, int H, int W) {
+  if (!xu) return Cu == 0;
+  return Cu > 0 && Cu < Cin && Cu % 32 == 0 && H % 2 == 0 && W % 2 == 0;
+}
+
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
-  if (a.Cin % 32 != 0 || a.Cout % 32 != 0 || a.B < 1 || a.H < 1 || a.W < 1)
+  if (a.Cin % 32 != 0 || a.Cout % 32 != 0 || a.B < 1 || a.H < 1 || a.W < 1 ||
+      !valid_split(a.xu, a.Cu, a.Cin, a.H, a.W))
     return hipErrorInvalidValue;
   if (a.Cout % 64 == 0)
     return a.Cin == kKC ? launch_conv_cob<64, true>(a, s) : launch_conv_cob<64, false>(a, s);
@@ -331,7 +350,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (i < kHaloPairs && gy >= 0 && gy < a.H && gx + j >= 0 && gx + j < a.W)
           v = *reinterpret_cast<const uint4*>(
-              a.x + (((int64_t)b * a.H + gy) * a.W + gx + j) * a.Cin + ci0 + part * 8);
+              conv_input(a.x, a.xu, a.Cu, a.Cin, a.H, a.W, b, gy, gx + j, ci0 + part * 8));
         xr[k][j] = v;
       }
     }
@@ -423,7 +442,9 @@ int wgrad_resident(int Cout) {
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
-  if (a.Cin % 32 != 0 || a.Cout % 32 != 0 || a.splits < 1) return hipErrorInvalidValue;
+  if (a.Cin % 32 != 0 || a.Cout % 32 != 0 || a.splits < 1 ||
+      !valid_split(a.xu, a.Cu, a.Cin, a.H, a.W))
+    return hipErrorInvalidValue;
   const int blocks = wgrad_blocks_per_split(a.Cin, a.Cout) * a.splits;
   if (a.Cout % 64 == 0)
     hipLaunchKernelGGL(k_wgrad<64>, dim3(blocks), dim3(256), 0, s, a);
