@@ -115,10 +115,9 @@ size_t carve(lem_sur_ctx* c, char* base) {
   }
   for (int l = 0; l < 3; ++l) {
     c->pool[l] = (uint16_t*)take(2 * px(c, l + 1) * kChannels[l]);
-    const int ccat = kChannels[l + 1] + kChannels[l];
     c->a_dec[l] = (uint16_t*)take(2 * px(c, l) * kChannels[l]);
     c->d[l] = (uint16_t*)take(2 * px(c, l) * kChannels[l]);
-    c->gcat[l] = (float*)take(4 * px(c, l) * ccat);
+    c->gcat[l] = (float*)take(4 * px(c, l) * kChannels[l]);  // skip part of the gradient
   }
   c->y = (float*)take(4 * P0);
   c->dy = (float*)take(4 * P0);
@@ -150,11 +149,14 @@ lem_status fail(lem_sur_ctx* c, lem_status st, const std::string& m) {
 // x may be the concatenation [upsampled xu (cu channels), x] (xu null: x alone).
 lem_status conv(lem_sur_ctx* c, int B, int level, const uint16_t* x, int cin, const uint16_t* w,
                 const float* bias, int cout, bool relu, uint16_t* outb, float* outf,
-                const uint16_t* xu = nullptr, int cu = 0) {
+                const uint16_t* xu = nullptr, int cu = 0, float* outu = nullptr,
+                int cu_out = 0) {
   sur::ConvArgs a{};
   a.x = x;
   a.xu = xu;
   a.Cu = cu;
+  a.outu = outu;
+  a.Cu_out = cu_out;
   a.w = w;
   a.bias = bias;
   a.outb = outb;
@@ -255,10 +257,12 @@ lem_status relu_bias_bwd(lem_sur_ctx* c, int li, const float* g, const uint16_t*
 
 // Backward through conv(lb)(relu(conv(la)(x))) + ReLU given the gradient ge of
 // its output e; gx (float32, cin(la) channels) may be null.  x may be the
-// concatenation [upsampled xu (cu channels), x].
+// concatenation [upsampled xu (cu channels), x]; then, with gxu set, the
+// gradient of its upsampled part goes to gxu (the lower level's map: sums of
+// 2x2 blocks) instead of gx.
 lem_status block_bwd(lem_sur_ctx* c, int B, int level, const uint16_t* x, const uint16_t* a,
                      const uint16_t* e, const float* ge, int la, int lb, float* gx,
-                     const uint16_t* xu = nullptr, int cu = 0) {
+                     const uint16_t* xu = nullptr, int cu = 0, float* gxu = nullptr) {
   lem_status st;
   const Layer& A = table().conv[la];
   const Layer& Bl = table().conv[lb];
@@ -272,7 +276,7 @@ lem_status block_bwd(lem_sur_ctx* c, int B, int level, const uint16_t* x, const 
   if ((st = relu_bias_bwd(c, la, ga, a, P)) != LEM_OK) return st;
   if ((st = wgrad(c, B, level, la, x, xu, cu)) != LEM_OK) return st;
   if (gx && (st = conv(c, B, level, c->dz, A.cout, c->wd + A.off, nullptr, A.cin, false, nullptr,
-                       gx)) != LEM_OK)
+                       gx, nullptr, 0, gxu, gxu ? cu : 0)) != LEM_OK)
     return st;
   return LEM_OK;
 }
@@ -295,16 +299,16 @@ lem_status backward(lem_sur_ctx* c, int B, const double* U, const double* target
   SUR_CHECK(sur::launch_reduce_splits(c->part, kHeadBlocks, sur::kHeadChannels + 1,
                                       c->part + (int64_t)kHeadBlocks * (sur::kHeadChannels + 1),
                                       c->g + t.head_off, c->s));
-  // Decoder, level 0 up to 2: the concatenation's gradient lands in gcat[l];
+  // Decoder, level 0 up to 2: the concatenation's skip part lands in gcat[l];
   // its upsampled part becomes the gradient of the level below's output.
   float* g = c->gw[0];
   for (int l = 0; l < 3; ++l) {
-    if ((st = block_bwd(c, B, l, c->e[l], c->a_dec[l], c->d[l], g, kDecA[l], kDecB[l],
-                        c->gcat[l], decoder_low(c, l), kChannels[l + 1])) != LEM_OK)
-      return st;
+    // The upsampled part's gradient goes straight to the lower level as 2x2
+    // block sums; gcat[l] keeps the skip part.
     float* glow = (g == c->gw[0]) ? c->gw[1] : c->gw[0];
-    SUR_CHECK(sur::launch_up_bwd(c->gcat[l], glow, B, c->H >> l, c->W >> l, kChannels[l + 1],
-                                 kChannels[l + 1] + kChannels[l], c->s));
+    if ((st = block_bwd(c, B, l, c->e[l], c->a_dec[l], c->d[l], g, kDecA[l], kDecB[l],
+                        c->gcat[l], decoder_low(c, l), kChannels[l + 1], glow)) != LEM_OK)
+      return st;
     g = glow;
   }
   // Encoder, level 3 down to 0: an encoder output's gradient is its skip
@@ -316,7 +320,7 @@ lem_status backward(lem_sur_ctx* c, int B, const double* U, const double* target
       return st;
     if (l > 0) {
       float* gn = (gx == c->gw[0]) ? c->gw[1] : c->gw[0];
-      SUR_CHECK(sur::launch_pool_bwd_add(c->gcat[l - 1], kChannels[l], kChannels[l] + kChannels[l - 1],
+      SUR_CHECK(sur::launch_pool_bwd_add(c->gcat[l - 1], 0, kChannels[l - 1],
                                          gx, gn, B, c->H >> (l - 1), c->W >> (l - 1),
                                          kChannels[l - 1], c->s));
       g = gn;

@@ -30,6 +30,12 @@ struct ConvArgs {
   const float* bias;   // may be null
   uint16_t* outb;      // bfloat16 output (out_f32 == 0)
   float* outf;         // float32 output (out_f32 == 1)
+  // With outu set (float32 output, no bias or ReLU): output channels below
+  // Cu_out are not written; outu (H/2 x W/2, Cu_out channels) gets the sums
+  // of their 2x2 pixel blocks instead, and outf holds channels Cu_out..Cout-1
+  // (Cout - Cu_out per pixel).
+  float* outu;
+  int Cu_out;
   int B, H, W, Cin, Cout;
   int relu, out_f32;
 };
@@ -66,8 +72,6 @@ hipError_t launch_pool(const uint16_t* x, uint16_t* out, int B, int Ho, int Wo, 
                        hipStream_t s);
 hipError_t launch_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out, int B, int H,
                         int W, int Cu, int Cs, hipStream_t s);
-hipError_t launch_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat,
-                         hipStream_t s);
 hipError_t launch_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
                                float* out, int B, int H, int W, int C, hipStream_t s);
 hipError_t launch_relu_bwd_bias(const float* g, const uint16_t* y, uint16_t* dz, int64_t P,

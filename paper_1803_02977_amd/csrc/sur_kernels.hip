@@ -187,6 +187,33 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
     const int tx = t % tiles_x;
     t /= tiles_x;
     const int ty = t % tiles_y, b = t / tiles_y;
+    if (a.outu && co0 < a.Cu_out) {
+      // Output channels below Cu_out: only their 2x2 block sums are stored,
+      // at half resolution.  Rows nb, nb + 1 of a block are this lane's
+      // accumulators, columns lr, lr ^ 1 neighbouring lanes; the sum is
+      // ((top left + top right) + bottom left) + bottom right.
+#pragma unroll
+      for (int nb = 0; nb < NR; nb += 2) {
+        const int py = ty * kT + row0 + nb, px = tx * kT + lr;
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb) {
+          const f32x4 top = acc[mb][nb], bot = acc[mb][nb + 1];
+          acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+          acc[mb][nb + 1] = f32x4{0.f, 0.f, 0.f, 0.f};
+          float o[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float tr = __shfl_xor(top[j], 1, 64), br = __shfl_xor(bot[j], 1, 64);
+            o[j] = ((top[j] + tr) + bot[j]) + br;
+          }
+          if ((lr & 1) || py >= a.H || px >= a.W) continue;
+          const int co = co0 + (cb0 + mb) * 16 + (lane >> 4) * 4;
+          const int64_t q = ((int64_t)b * (a.H >> 1) + (py >> 1)) * (a.W >> 1) + (px >> 1);
+          *reinterpret_cast<float4*>(a.outu + q * a.Cu_out + co) = make_float4(o[0], o[1], o[2], o[3]);
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int nb = 0; nb < NR; ++nb) {
       const int py = ty * kT + row0 + nb, px = tx * kT + lr;
@@ -204,7 +231,9 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
           if (a.relu) v[j] = fmaxf(v[j], 0.f);
         }
         if (a.out_f32) {
-          *reinterpret_cast<float4*>(a.outf + p * a.Cout + co) = make_float4(v[0], v[1], v[2], v[3]);
+          // Channels below Cu_out (block sums, if any) are not part of outf.
+          *reinterpret_cast<float4*>(a.outf + p * (a.Cout - a.Cu_out) + (co - a.Cu_out)) =
+              make_float4(v[0], v[1], v[2], v[3]);
         } else {
           uint2 pk;
           pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
@@ -252,6 +281,12 @@ static bool valid_split(const uint16_t* xu, int Cu, int Cin, int H, int W) {
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   if (a.Cin % 32 != 0 || a.Cout % 32 != 0 || a.B < 1 || a.H < 1 || a.W < 1 ||
       !valid_split(a.xu, a.Cu, a.Cin, a.H, a.W))
+    return hipErrorInvalidValue;
+  // Block sums: float32 output without bias or ReLU, whole channel blocks,
+  // an even-sized map.
+  const int cob = a.Cout % 64 == 0 ? 64 : 32;
+  if (a.outu && (!a.out_f32 || a.bias || a.relu || a.Cu_out <= 0 || a.Cu_out > a.Cout ||
+                 a.Cu_out % cob != 0 || a.H % 2 != 0 || a.W % 2 != 0))
     return hipErrorInvalidValue;
   if (a.Cout % 64 == 0)
     return a.Cin == kKC ? launch_conv_cob<64, true>(a, s) : launch_conv_cob<64, false>(a, s);
@@ -624,37 +659,6 @@ __global__ void k_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out
 hipError_t launch_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out, int B, int H,
                         int W, int Cu, int Cs, hipStream_t s) {
   hipLaunchKernelGGL(k_upcat, dim3(2048), dim3(256), 0, s, low, skip, out, B, H, W, Cu, Cs);
-  return hipGetLastError();
-}
-
-// Gradient of the upsampled part of a concatenation: glow (H/2 x W/2, Cu
-// channels) = sum of the 2x2 block of gcat[..., 0:Cu] (H x W, Ccat channels);
-// 4 channels (16 bytes) per thread and iteration.
-__global__ void k_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat,
-                         int lg) {
-  const int Ho = H / 2, Wo = W / 2;
-  const int64_t n = ((int64_t)B * Ho * Wo) << lg;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i & ((1 << lg) - 1)) * 4;
-    const int q = (int)(i >> lg);
-    const int xo = q % Wo, yo = (q / Wo) % Ho, b = q / (Wo * Ho);
-    const int64_t r0 = ((int64_t)b * H + 2 * yo) * W + 2 * xo, r1 = r0 + W;
-    const float4 a = *reinterpret_cast<const float4*>(gcat + r0 * Ccat + c);
-    const float4 e = *reinterpret_cast<const float4*>(gcat + (r0 + 1) * Ccat + c);
-    const float4 f = *reinterpret_cast<const float4*>(gcat + r1 * Ccat + c);
-    const float4 g = *reinterpret_cast<const float4*>(gcat + (r1 + 1) * Ccat + c);
-    *reinterpret_cast<float4*>(glow + (int64_t)q * Cu + c) =
-        make_float4(((a.x + e.x) + f.x) + g.x, ((a.y + e.y) + f.y) + g.y,
-                    ((a.z + e.z) + f.z) + g.z, ((a.w + e.w) + f.w) + g.w);
-  }
-}
-
-hipError_t launch_up_bwd(const float* gcat, float* glow, int B, int H, int W, int Cu, int Ccat,
-                         hipStream_t s) {
-  int lg;
-  if (!pow2_groups(Cu, 4, &lg) || Ccat % 4 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_up_bwd, dim3(2048), dim3(256), 0, s, gcat, glow, B, H, W, Cu, Ccat, lg);
   return hipGetLastError();
 }
 
