@@ -244,11 +244,14 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x,
   return LEM_OK;
 }
 
-// ReLU backward of layer li's output y given its gradient g: dz (bfloat16)
-// for the weight and input gradients, and the bias gradient into c->g.
-lem_status relu_bias_bwd(lem_sur_ctx* c, int li, const float* g, const uint16_t* y, int64_t P) {
+// ReLU backward of layer li's output y (level `level`) given its gradient g
+// (plus 0.25 g2 spread over 2x2 blocks when g2 is set): dz (bfloat16) for the
+// weight and input gradients, and the bias gradient into c->g.
+lem_status relu_bias_bwd(lem_sur_ctx* c, int level, int li, const float* g, const uint16_t* y,
+                         int64_t P, const float* g2 = nullptr) {
   const Layer& L = table().conv[li];
-  SUR_CHECK(sur::launch_relu_bwd_bias(g, y, c->dz, P, L.cout, c->part, kBiasBlocks, c->s));
+  SUR_CHECK(sur::launch_relu_bwd_bias(g, g2, c->H >> level, c->W >> level, y, c->dz, P, L.cout,
+                                      c->part, kBiasBlocks, c->s));
   SUR_CHECK(sur::launch_reduce_splits(c->part, kBiasBlocks, L.cout,
                                       c->part + (int64_t)kBiasBlocks * L.cout,
                                       c->g + L.off + (int64_t)L.cout * 9 * L.cin, c->s));
@@ -256,24 +259,26 @@ lem_status relu_bias_bwd(lem_sur_ctx* c, int li, const float* g, const uint16_t*
 }
 
 // Backward through conv(lb)(relu(conv(la)(x))) + ReLU given the gradient ge of
-// its output e; gx (float32, cin(la) channels) may be null.  x may be the
+// its output e (plus 0.25 ge2 over 2x2 blocks when ge2, half resolution, is
+// set); gx (float32, cin(la) channels) may be null.  x may be the
 // concatenation [upsampled xu (cu channels), x]; then, with gxu set, the
 // gradient of its upsampled part goes to gxu (the lower level's map: sums of
 // 2x2 blocks) instead of gx.
 lem_status block_bwd(lem_sur_ctx* c, int B, int level, const uint16_t* x, const uint16_t* a,
                      const uint16_t* e, const float* ge, int la, int lb, float* gx,
-                     const uint16_t* xu = nullptr, int cu = 0, float* gxu = nullptr) {
+                     const uint16_t* xu = nullptr, int cu = 0, float* gxu = nullptr,
+                     const float* ge2 = nullptr) {
   lem_status st;
   const Layer& A = table().conv[la];
   const Layer& Bl = table().conv[lb];
   const int64_t P = (int64_t)B * (c->H >> level) * (c->W >> level);
   float* ga = c->gw[2];
-  if ((st = relu_bias_bwd(c, lb, ge, e, P)) != LEM_OK) return st;
+  if ((st = relu_bias_bwd(c, level, lb, ge, e, P, ge2)) != LEM_OK) return st;
   if ((st = wgrad(c, B, level, lb, a)) != LEM_OK) return st;
   if ((st = conv(c, B, level, c->dz, Bl.cout, c->wd + Bl.off, nullptr, Bl.cin, false, nullptr,
                  ga)) != LEM_OK)
     return st;
-  if ((st = relu_bias_bwd(c, la, ga, a, P)) != LEM_OK) return st;
+  if ((st = relu_bias_bwd(c, level, la, ga, a, P)) != LEM_OK) return st;
   if ((st = wgrad(c, B, level, la, x, xu, cu)) != LEM_OK) return st;
   if (gx && (st = conv(c, B, level, c->dz, A.cout, c->wd + A.off, nullptr, A.cin, false, nullptr,
                        gx, nullptr, 0, gxu, gxu ? cu : 0)) != LEM_OK)
@@ -312,18 +317,19 @@ lem_status backward(lem_sur_ctx* c, int B, const double* U, const double* target
     g = glow;
   }
   // Encoder, level 3 down to 0: an encoder output's gradient is its skip
-  // part plus the pooled path's.
+  // part plus the pooled path's (a quarter of the level above's input
+  // gradient on each pixel of its 2x2 block), added in the ReLU backward.
+  const float* g2 = nullptr;
   for (int l = 3; l >= 0; --l) {
-    float* gx = (l > 0) ? ((g == c->gw[0]) ? c->gw[1] : c->gw[0]) : nullptr;
+    const float* busy = g2 ? g2 : g;
+    float* gx = (l > 0) ? ((busy == c->gw[0]) ? c->gw[1] : c->gw[0]) : nullptr;
     const uint16_t* x = (l > 0) ? c->pool[l - 1] : c->x0;
-    if ((st = block_bwd(c, B, l, x, c->a_enc[l], c->e[l], g, kEncA[l], kEncB[l], gx)) != LEM_OK)
+    if ((st = block_bwd(c, B, l, x, c->a_enc[l], c->e[l], g, kEncA[l], kEncB[l], gx, nullptr, 0,
+                        nullptr, g2)) != LEM_OK)
       return st;
     if (l > 0) {
-      float* gn = (gx == c->gw[0]) ? c->gw[1] : c->gw[0];
-      SUR_CHECK(sur::launch_pool_bwd_add(c->gcat[l - 1], 0, kChannels[l - 1],
-                                         gx, gn, B, c->H >> (l - 1), c->W >> (l - 1),
-                                         kChannels[l - 1], c->s));
-      g = gn;
+      g = c->gcat[l - 1];
+      g2 = gx;
     }
   }
   return LEM_OK;

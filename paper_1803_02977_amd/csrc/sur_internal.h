@@ -72,10 +72,9 @@ hipError_t launch_pool(const uint16_t* x, uint16_t* out, int B, int Ho, int Wo, 
                        hipStream_t s);
 hipError_t launch_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out, int B, int H,
                         int W, int Cu, int Cs, hipStream_t s);
-hipError_t launch_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
-                               float* out, int B, int H, int W, int C, hipStream_t s);
-hipError_t launch_relu_bwd_bias(const float* g, const uint16_t* y, uint16_t* dz, int64_t P,
-                                int C, float* part, int nblk, hipStream_t s);
+hipError_t launch_relu_bwd_bias(const float* g, const float* g2, int H, int W, const uint16_t* y,
+                                uint16_t* dz, int64_t P, int C, float* part, int nblk,
+                                hipStream_t s);
 hipError_t launch_head(const uint16_t* d0, const uint16_t* wb, const float* bias, float* y,
                        int64_t P, hipStream_t s);
 hipError_t launch_loss(const float* y, const double* target, const double* U, int B, int H,

@@ -662,43 +662,17 @@ hipError_t launch_upcat(const uint16_t* low, const uint16_t* skip, uint16_t* out
   return hipGetLastError();
 }
 
-// Gradient of an encoder output: its skip part gcat[..., Cu:Cu+C] plus the
-// pooled path's gradient spread over each 2x2 block (a quarter each); 4
-// channels (16 bytes) per thread and iteration.
-__global__ void k_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
-                               float* out, int B, int H, int W, int C, int lg) {
-  const int64_t n = ((int64_t)B * H * W) << lg;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i & ((1 << lg) - 1)) * 4;
-    const int p = (int)(i >> lg);
-    const int x = p % W, y = (p / W) % H, b = p / (W * H);
-    const int64_t q = ((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2;
-    const float4 a = *reinterpret_cast<const float4*>(gcat + (int64_t)p * Ccat + Cu + c);
-    const float4 g = *reinterpret_cast<const float4*>(gsmall + q * C + c);
-    *reinterpret_cast<float4*>(out + (int64_t)p * C + c) =
-        make_float4(a.x + 0.25f * g.x, a.y + 0.25f * g.y, a.z + 0.25f * g.z, a.w + 0.25f * g.w);
-  }
-}
-
-hipError_t launch_pool_bwd_add(const float* gcat, int Cu, int Ccat, const float* gsmall,
-                               float* out, int B, int H, int W, int C, hipStream_t s) {
-  int lg;
-  if (!pow2_groups(C, 4, &lg) || Cu % 4 != 0 || Ccat % 4 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pool_bwd_add, dim3(2048), dim3(256), 0, s, gcat, Cu, Ccat, gsmall, out, B,
-                     H, W, C, lg);
-  return hipGetLastError();
-}
-
 // ReLU backward with the bias gradient's partial sums: v = g where the
 // stored output y > 0, else 0; dz = bf16(v); part[blk][c] = sum of v[p, c]
-// over pixels p of block blk's range [blk P / nblk, (blk + 1) P / nblk).  A
-// thread handles 4 consecutive channels of one pixel (C / 4 threads per
+// over pixels p of block blk's range [blk P / nblk, (blk + 1) P / nblk).
+// With g2 set, the gradient is g + 0.25 g2 at the pixel's 2x2 block (g2 is
+// H/2 x W/2, C channels: the pooled path's gradient spread over the block).
+// A thread handles 4 consecutive channels of one pixel (C / 4 threads per
 // pixel, 1024 / C pixels per pass, each thread summing its pixels in order);
 // the per-thread sums are then added in LDS in pixel order.
-__global__ __launch_bounds__(256) void k_relu_bwd_bias(const float* g, const uint16_t* y,
-                                                       uint16_t* dz, int64_t P, int C,
-                                                       float* part, int nblk) {
+__global__ __launch_bounds__(256) void k_relu_bwd_bias(const float* g, const float* g2, int H,
+                                                       int W, const uint16_t* y, uint16_t* dz,
+                                                       int64_t P, int C, float* part, int nblk) {
   __shared__ float4 red[256];
   const int Q = C / 4, R = 256 / Q;
   const int r = threadIdx.x / Q, q = threadIdx.x % Q;
@@ -706,7 +680,15 @@ __global__ __launch_bounds__(256) void k_relu_bwd_bias(const float* g, const uin
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int64_t p = p0 + r; p < p1; p += R) {
     const int64_t e = p * C + q * 4;
-    const float4 gv = *reinterpret_cast<const float4*>(g + e);
+    float4 gv = *reinterpret_cast<const float4*>(g + e);
+    if (g2) {
+      const int pp = (int)p;
+      const int xx = pp % W, yy = (pp / W) % H, bb = pp / (W * H);
+      const int64_t qq = ((int64_t)bb * (H / 2) + yy / 2) * (W / 2) + xx / 2;
+      const float4 u = *reinterpret_cast<const float4*>(g2 + qq * C + q * 4);
+      gv = make_float4(gv.x + 0.25f * u.x, gv.y + 0.25f * u.y, gv.z + 0.25f * u.z,
+                       gv.w + 0.25f * u.w);
+    }
     const uint2 yv = *reinterpret_cast<const uint2*>(y + e);
     const float v0 = bf2f((uint16_t)(yv.x & 0xFFFFu)) > 0.f ? gv.x : 0.f;
     const float v1 = bf2f((uint16_t)(yv.x >> 16)) > 0.f ? gv.y : 0.f;
@@ -736,10 +718,15 @@ __global__ __launch_bounds__(256) void k_relu_bwd_bias(const float* g, const uin
   }
 }
 
-hipError_t launch_relu_bwd_bias(const float* g, const uint16_t* y, uint16_t* dz, int64_t P,
-                                int C, float* part, int nblk, hipStream_t s) {
+hipError_t launch_relu_bwd_bias(const float* g, const float* g2, int H, int W, const uint16_t* y,
+                                uint16_t* dz, int64_t P, int C, float* part, int nblk,
+                                hipStream_t s) {
   if (C < 4 || C > 1024 || 1024 % C != 0 || nblk < 1 || P < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_relu_bwd_bias, dim3(nblk), dim3(256), 0, s, g, y, dz, P, C, part, nblk);
+  if (g2 && (H < 2 || W < 2 || H % 2 != 0 || W % 2 != 0 || P % ((int64_t)H * W) != 0 ||
+             P > INT32_MAX))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_relu_bwd_bias, dim3(nblk), dim3(256), 0, s, g, g2, H, W, y, dz, P, C, part,
+                     nblk);
   return hipGetLastError();
 }
 
