@@ -76,8 +76,8 @@ struct lem_sur_ctx {
   uint16_t* x0;
   uint16_t *a_enc[4], *e[4], *pool[3], *a_dec[3], *d[3];
   float *y, *dy;
-  float *gw[3], *gcat[3];
-  uint16_t* dz;
+  float *gw[2], *gcat[3];  // gradients of level outputs (ping-pong), skip parts
+  uint16_t *dz, *dz2;  // output gradients in bfloat16 (two layers of a block)
   float* part;
   double* lpart;
   double* loss;
@@ -121,8 +121,9 @@ size_t carve(lem_sur_ctx* c, char* base) {
   }
   c->y = (float*)take(4 * P0);
   c->dy = (float*)take(4 * P0);
-  for (int k = 0; k < 3; ++k) c->gw[k] = (float*)take(4 * P0 * kChannels[0]);
+  for (int k = 0; k < 2; ++k) c->gw[k] = (float*)take(4 * P0 * kChannels[0]);
   c->dz = (uint16_t*)take(2 * P0 * kChannels[0]);
+  c->dz2 = (uint16_t*)take(2 * P0 * kChannels[0]);
   c->part = (float*)take(4 * kPartCap);
   c->lpart = (double*)take(8 * kLossBlocks);
   c->loss = (double*)take(8);
@@ -211,7 +212,7 @@ lem_status forward(lem_sur_ctx* c, int B, const double* K, const double* U, cons
 }
 
 // Weight gradient of layer li into c->g (split partials, then their sum).
-lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x,
+lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x, const uint16_t* dz,
                  const uint16_t* xu = nullptr, int cu = 0) {
   const Layer& L = table().conv[li];
   const int H = c->H >> level, W = c->W >> level;
@@ -230,7 +231,7 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x,
   a.x = x;
   a.xu = xu;
   a.Cu = cu;
-  a.dz = c->dz;
+  a.dz = dz;
   a.part = c->part;
   a.B = B;
   a.H = H;
@@ -258,6 +259,32 @@ lem_status relu_bias_bwd(lem_sur_ctx* c, int level, int li, const float* g, cons
   return LEM_OK;
 }
 
+// Input gradient of layer lb (from c->dz) fused with the ReLU backward of
+// layer la, whose stored output is a: c->dz2 = bf16 of the gradient where a
+// is positive, and la's bias gradient from the convolution's per-workgroup
+// sums.
+lem_status dgrad_relu_bwd(lem_sur_ctx* c, int B, int level, int lb, int la, const uint16_t* a) {
+  const Layer& Lb = table().conv[lb];
+  const Layer& La = table().conv[la];
+  sur::ConvArgs g{};
+  g.x = c->dz;
+  g.w = c->wd + Lb.off;
+  g.outb = c->dz2;
+  g.mask_y = a;
+  g.bias_part = c->part;
+  g.B = B;
+  g.H = c->H >> level;
+  g.W = c->W >> level;
+  g.Cin = Lb.cout;
+  g.Cout = Lb.cin;
+  const int groups = sur::conv_groups(g);
+  SUR_CHECK(sur::launch_conv(g, c->s));
+  SUR_CHECK(sur::launch_reduce_splits(c->part, groups, La.cout,
+                                      c->part + (int64_t)groups * La.cout,
+                                      c->g + La.off + (int64_t)La.cout * 9 * La.cin, c->s));
+  return LEM_OK;
+}
+
 // Backward through conv(lb)(relu(conv(la)(x))) + ReLU given the gradient ge of
 // its output e (plus 0.25 ge2 over 2x2 blocks when ge2, half resolution, is
 // set); gx (float32, cin(la) channels) may be null.  x may be the
@@ -270,17 +297,12 @@ lem_status block_bwd(lem_sur_ctx* c, int B, int level, const uint16_t* x, const 
                      const float* ge2 = nullptr) {
   lem_status st;
   const Layer& A = table().conv[la];
-  const Layer& Bl = table().conv[lb];
   const int64_t P = (int64_t)B * (c->H >> level) * (c->W >> level);
-  float* ga = c->gw[2];
   if ((st = relu_bias_bwd(c, level, lb, ge, e, P, ge2)) != LEM_OK) return st;
-  if ((st = wgrad(c, B, level, lb, a)) != LEM_OK) return st;
-  if ((st = conv(c, B, level, c->dz, Bl.cout, c->wd + Bl.off, nullptr, Bl.cin, false, nullptr,
-                 ga)) != LEM_OK)
-    return st;
-  if ((st = relu_bias_bwd(c, level, la, ga, a, P)) != LEM_OK) return st;
-  if ((st = wgrad(c, B, level, la, x, xu, cu)) != LEM_OK) return st;
-  if (gx && (st = conv(c, B, level, c->dz, A.cout, c->wd + A.off, nullptr, A.cin, false, nullptr,
+  if ((st = wgrad(c, B, level, lb, a, c->dz)) != LEM_OK) return st;
+  if ((st = dgrad_relu_bwd(c, B, level, lb, la, a)) != LEM_OK) return st;
+  if ((st = wgrad(c, B, level, la, x, c->dz2, xu, cu)) != LEM_OK) return st;
+  if (gx && (st = conv(c, B, level, c->dz2, A.cout, c->wd + A.off, nullptr, A.cin, false, nullptr,
                        gx, nullptr, 0, gxu, gxu ? cu : 0)) != LEM_OK)
     return st;
   return LEM_OK;

@@ -36,6 +36,12 @@ struct ConvArgs {
   // (Cout - Cu_out per pixel).
   float* outu;
   int Cu_out;
+  // With mask_y set (bfloat16 output, no bias or ReLU): the ReLU backward of
+  // the layer whose stored output mask_y (NHWC, Cout channels) is: outb gets
+  // bf16(r) where mask_y > 0, else 0, and bias_part[g][co] (conv_groups(a) x
+  // Cout floats) the per-workgroup sums of those masked values (float32).
+  const uint16_t* mask_y;
+  float* bias_part;
   int B, H, W, Cin, Cout;
   int relu, out_f32;
 };
@@ -52,6 +58,7 @@ struct WgradArgs {
 };
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
+int conv_groups(const ConvArgs& a);  // tile groups of launch_conv's persistent grid
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s);
 int wgrad_blocks_per_split(int Cin, int Cout);
 int wgrad_resident(int Cout);  // workgroups the weight-gradient kernel keeps resident

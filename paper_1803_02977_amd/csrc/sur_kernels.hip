@@ -75,6 +75,7 @@ template <int COB, bool ONE>
 __global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t xs[kHalo * kHalo * kXP];
   __shared__ __attribute__((aligned(16))) uint16_t ws[COB * 9 * kWP];
+  __shared__ float red[4][COB];    // per-wave channel sums (ReLU-backward mode)
   constexpr int MB = COB / 16;     // 16-channel output blocks of the workgroup
   constexpr int MBW = 2;           // of them per wave
   constexpr int NR = MB * kT / (4 * MBW);  // tile rows per wave
@@ -96,6 +97,11 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
   for (int i = 0; i < MBW; ++i)
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum[MBW][4];  // ReLU-backward mode: this lane's sums of its masked outputs
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bsum[i][j] = 0.f;
 
   uint4 xr[XI], wr[ONE ? 1 : WI];
   auto load_w = [&](int ci0, int j) {
@@ -224,6 +230,24 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
         if (py >= a.H || px >= a.W) continue;
         const int64_t p = ((int64_t)b * a.H + py) * a.W + px;
         const int co = co0 + (cb0 + mb) * 16 + (lane >> 4) * 4;
+        if (a.mask_y) {
+          // ReLU backward of the layer whose stored output is mask_y: keep
+          // the gradient where that output is positive, store it in
+          // bfloat16, and sum it per channel for the bias gradient.
+          const uint2 yv = *reinterpret_cast<const uint2*>(a.mask_y + p * a.Cout + co);
+          float m[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t yw = (j < 2) ? yv.x : yv.y;
+            m[j] = bf2f((uint16_t)(yw >> (16 * (j & 1)))) > 0.f ? r[j] : 0.f;
+            bsum[mb][j] += m[j];
+          }
+          uint2 pk;
+          pk.x = (uint32_t)f2bf(m[0]) | ((uint32_t)f2bf(m[1]) << 16);
+          pk.y = (uint32_t)f2bf(m[2]) | ((uint32_t)f2bf(m[3]) << 16);
+          *reinterpret_cast<uint2*>(a.outb + p * a.Cout + co) = pk;
+          continue;
+        }
         float v[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -241,6 +265,30 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3(ConvArgs a) {
           *reinterpret_cast<uint2*>(a.outb + p * a.Cout + co) = pk;
         }
       }
+    }
+  }
+
+  if (a.mask_y) {
+    // Channel sums: over the 16 lanes of a channel group (a fixed xor tree),
+    // then over the waves holding the same channels, in wave order.
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v = bsum[mb][j];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        if (lr == 0) red[wave][(cb0 + mb) * 16 + (lane >> 4) * 4 + j] = v;
+      }
+    __syncthreads();
+    if (tid < COB) {
+      const int blk = tid / 16;
+      float t = 0.f;
+      for (int w = 0; w < 4; ++w)
+        if ((w % (MB / MBW)) * MBW <= blk && blk < (w % (MB / MBW)) * MBW + MBW) t += red[w][tid];
+      a.bias_part[(int64_t)g * a.Cout + co0 + tid] = t;
     }
   }
 }
@@ -261,14 +309,26 @@ int resident_groups(F fn, int* cache) {
   return *cache;
 }
 
+// Tile groups G of a persistent launch (grid G x Cout / COB).
 template <int COB, bool ONE>
-hipError_t launch_conv_cob(const ConvArgs& a, hipStream_t s) {
+int conv_groups_cob(const ConvArgs& a) {
   const int tiles = a.B * ((a.H + kT - 1) / kT) * ((a.W + kT - 1) / kT);
   const int nco = a.Cout / COB;
   static int resident = 0;
-  const int G = std::max(1, std::min(tiles, resident_groups(k_conv3x3<COB, ONE>, &resident) / nco));
-  hipLaunchKernelGGL((k_conv3x3<COB, ONE>), dim3(G * nco), dim3(256), 0, s, a);
+  return std::max(1, std::min(tiles, resident_groups(k_conv3x3<COB, ONE>, &resident) / nco));
+}
+
+template <int COB, bool ONE>
+hipError_t launch_conv_cob(const ConvArgs& a, hipStream_t s) {
+  const int G = conv_groups_cob<COB, ONE>(a);
+  hipLaunchKernelGGL((k_conv3x3<COB, ONE>), dim3(G * (a.Cout / COB)), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+int conv_groups(const ConvArgs& a) {
+  if (a.Cout % 64 == 0)
+    return a.Cin == kKC ? conv_groups_cob<64, true>(a) : conv_groups_cob<64, false>(a);
+  return a.Cin == kKC ? conv_groups_cob<32, true>(a) : conv_groups_cob<32, false>(a);
 }
 
 // A concatenated input needs whole 32-channel chunks from each part and an
@@ -287,6 +347,9 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const int cob = a.Cout % 64 == 0 ? 64 : 32;
   if (a.outu && (!a.out_f32 || a.bias || a.relu || a.Cu_out <= 0 || a.Cu_out > a.Cout ||
                  a.Cu_out % cob != 0 || a.H % 2 != 0 || a.W % 2 != 0))
+    return hipErrorInvalidValue;
+  // ReLU-backward mode: bfloat16 output, no bias, ReLU or block sums.
+  if (a.mask_y && (a.out_f32 || !a.outb || a.bias || a.relu || a.outu || !a.bias_part))
     return hipErrorInvalidValue;
   if (a.Cout % 64 == 0)
     return a.Cin == kKC ? launch_conv_cob<64, true>(a, s) : launch_conv_cob<64, false>(a, s);
