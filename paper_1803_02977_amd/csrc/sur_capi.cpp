@@ -16,7 +16,7 @@ namespace {
 
 constexpr int kChannels[4] = {32, 64, 128, 256};
 constexpr int kNumConv = 14;
-constexpr int64_t kPartCap = int64_t(32) << 20;  // floats of split partials
+constexpr int64_t kPartCap = int64_t(64) << 20;  // floats of split partials
 constexpr int kBiasBlocks = 1024;   // pixel ranges of the bias gradient's partials
 constexpr int kLossBlocks = 1024;
 constexpr int kHeadBlocks = 2048;
@@ -79,6 +79,11 @@ struct lem_sur_ctx {
   float *gw[2], *gcat[3];  // gradients of level outputs (ping-pong), skip parts
   uint16_t *dz, *dz2;  // output gradients in bfloat16 (two layers of a block)
   float* part;
+  // Split sums queued during a backward pass; their partials occupy
+  // part[0, part_used).
+  sur::ReduceJob jobs[sur::kMaxReduceJobs];
+  int njobs;
+  int64_t part_used;
   double* lpart;
   double* loss;
 };
@@ -146,6 +151,32 @@ lem_status fail(lem_sur_ctx* c, lem_status st, const std::string& m) {
     if (e_ != hipSuccess) return fail(c, LEM_E_HIP, std::string(#call) + ": " +  \
                                              hipGetErrorString(e_));             \
   } while (0)
+
+// Sums the queued split partials into their outputs; the partial buffer is
+// then free again.
+lem_status flush_reduce(lem_sur_ctx* c) {
+  if (c->njobs) SUR_CHECK(sur::launch_reduce_batch(c->jobs, c->njobs, c->s));
+  c->njobs = 0;
+  c->part_used = 0;
+  return LEM_OK;
+}
+
+// Reserves room for `splits` partials of n values (and their group sums) and
+// queues their sum into out; *part receives the partials' address.  Queued
+// sums run in stream order before the space is reused.
+lem_status queue_reduce(lem_sur_ctx* c, int splits, int64_t n, float* out, float** part) {
+  lem_status st;
+  const int64_t groups = sur::reduce_scratch_groups(splits);
+  const int64_t need = ((n * (splits + groups)) + 63) & ~int64_t(63);
+  if (need > kPartCap) return fail(c, LEM_E_SIZE, "split partials exceed the partial buffer");
+  if (c->njobs == sur::kMaxReduceJobs || c->part_used + need > kPartCap)
+    if ((st = flush_reduce(c)) != LEM_OK) return st;
+  float* p = c->part + c->part_used;
+  c->jobs[c->njobs++] = sur::ReduceJob{p, groups ? p + (int64_t)splits * n : nullptr, out, n, splits};
+  c->part_used += need;
+  *part = p;
+  return LEM_OK;
+}
 
 // x may be the concatenation [upsampled xu (cu channels), x] (xu null: x alone).
 lem_status conv(lem_sur_ctx* c, int B, int level, const uint16_t* x, int cin, const uint16_t* w,
@@ -227,12 +258,15 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x, co
   while (splits > 1 &&
          n * (splits + sur::reduce_scratch_groups(splits)) > kPartCap)
     --splits;
+  float* part;
+  lem_status st;
+  if ((st = queue_reduce(c, splits, n, c->g + L.off, &part)) != LEM_OK) return st;
   sur::WgradArgs a{};
   a.x = x;
   a.xu = xu;
   a.Cu = cu;
   a.dz = dz;
-  a.part = c->part;
+  a.part = part;
   a.B = B;
   a.H = H;
   a.W = W;
@@ -240,8 +274,6 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x, co
   a.Cout = L.cout;
   a.splits = splits;
   SUR_CHECK(sur::launch_wgrad(a, c->s));
-  SUR_CHECK(sur::launch_reduce_splits(c->part, splits, n, c->part + (int64_t)splits * n,
-                                      c->g + L.off, c->s));
   return LEM_OK;
 }
 
@@ -251,11 +283,13 @@ lem_status wgrad(lem_sur_ctx* c, int B, int level, int li, const uint16_t* x, co
 lem_status relu_bias_bwd(lem_sur_ctx* c, int level, int li, const float* g, const uint16_t* y,
                          int64_t P, const float* g2 = nullptr) {
   const Layer& L = table().conv[li];
+  float* part;
+  lem_status st;
+  if ((st = queue_reduce(c, kBiasBlocks, L.cout, c->g + L.off + (int64_t)L.cout * 9 * L.cin,
+                         &part)) != LEM_OK)
+    return st;
   SUR_CHECK(sur::launch_relu_bwd_bias(g, g2, c->H >> level, c->W >> level, y, c->dz, P, L.cout,
-                                      c->part, kBiasBlocks, c->s));
-  SUR_CHECK(sur::launch_reduce_splits(c->part, kBiasBlocks, L.cout,
-                                      c->part + (int64_t)kBiasBlocks * L.cout,
-                                      c->g + L.off + (int64_t)L.cout * 9 * L.cin, c->s));
+                                      part, kBiasBlocks, c->s));
   return LEM_OK;
 }
 
@@ -271,17 +305,17 @@ lem_status dgrad_relu_bwd(lem_sur_ctx* c, int B, int level, int lb, int la, cons
   g.w = c->wd + Lb.off;
   g.outb = c->dz2;
   g.mask_y = a;
-  g.bias_part = c->part;
   g.B = B;
   g.H = c->H >> level;
   g.W = c->W >> level;
   g.Cin = Lb.cout;
   g.Cout = Lb.cin;
   const int groups = sur::conv_groups(g);
+  lem_status st;
+  if ((st = queue_reduce(c, groups, La.cout, c->g + La.off + (int64_t)La.cout * 9 * La.cin,
+                         &g.bias_part)) != LEM_OK)
+    return st;
   SUR_CHECK(sur::launch_conv(g, c->s));
-  SUR_CHECK(sur::launch_reduce_splits(c->part, groups, La.cout,
-                                      c->part + (int64_t)groups * La.cout,
-                                      c->g + La.off + (int64_t)La.cout * 9 * La.cin, c->s));
   return LEM_OK;
 }
 
@@ -321,11 +355,16 @@ lem_status backward(lem_sur_ctx* c, int B, const double* U, const double* target
   const double n = (double)B * (c->H - 2) * (c->W - 2);
   SUR_CHECK(sur::launch_loss(c->y, target, U, B, c->H, c->W, c->dy, c->lpart, kLossBlocks, c->s));
   SUR_CHECK(sur::launch_reduce_f64(c->lpart, kLossBlocks, 1.0 / n, c->loss, c->s));
-  SUR_CHECK(sur::launch_head_bwd(c->dy, c->d[0], c->pb + t.head_off, c->gw[0], c->part,
+  // Every split sum of the pass is queued and run at its end (or earlier when
+  // the partial buffer fills); nothing reads c->g before.
+  c->njobs = 0;
+  c->part_used = 0;
+  float* hpart;
+  if ((st = queue_reduce(c, kHeadBlocks, sur::kHeadChannels + 1, c->g + t.head_off, &hpart)) !=
+      LEM_OK)
+    return st;
+  SUR_CHECK(sur::launch_head_bwd(c->dy, c->d[0], c->pb + t.head_off, c->gw[0], hpart,
                                  kHeadBlocks, P0, c->s));
-  SUR_CHECK(sur::launch_reduce_splits(c->part, kHeadBlocks, sur::kHeadChannels + 1,
-                                      c->part + (int64_t)kHeadBlocks * (sur::kHeadChannels + 1),
-                                      c->g + t.head_off, c->s));
   // Decoder, level 0 up to 2: the concatenation's skip part lands in gcat[l];
   // its upsampled part becomes the gradient of the level below's output.
   float* g = c->gw[0];
@@ -354,7 +393,7 @@ lem_status backward(lem_sur_ctx* c, int B, const double* U, const double* target
       g2 = gx;
     }
   }
-  return LEM_OK;
+  return flush_reduce(c);
 }
 
 lem_status check_call(lem_sur_ctx* c, int32_t batch, const void* K, const void* U,

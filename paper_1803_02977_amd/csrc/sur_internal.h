@@ -65,11 +65,24 @@ int wgrad_resident(int Cout);  // workgroups the weight-gradient kernel keeps re
 int wgrad_patches(int B, int H, int W);
 
 // Split partials are summed in groups of kReduceGroup consecutive splits,
-// then over the groups; tmp holds reduce_scratch_groups(splits) * n floats.
+// then over the groups (in order both times); a job with more than
+// kReduceGroup splits needs reduce_scratch_groups(splits) * n floats of group
+// sums (tmp).
 constexpr int kReduceGroup = 32;
 int reduce_scratch_groups(int splits);
-hipError_t launch_reduce_splits(const float* part, int splits, int64_t n, float* tmp, float* out,
-                                hipStream_t s);
+
+// One split sum: out[i] = sum of part[s * n + i] over s < splits (tmp: its
+// group sums, or null if splits <= kReduceGroup).
+struct ReduceJob {
+  const float* part;
+  float* tmp;
+  float* out;
+  int64_t n;
+  int splits;
+};
+constexpr int kMaxReduceJobs = 32;
+// Runs up to kMaxReduceJobs independent split sums in two launches.
+hipError_t launch_reduce_batch(const ReduceJob* jobs, int njobs, hipStream_t s);
 hipError_t launch_to_bf16(const float* p, uint16_t* pb, int64_t n, hipStream_t s);
 hipError_t launch_dgrad_weights(const uint16_t* w, uint16_t* wd, int Cin, int Cout,
                                 hipStream_t s);

@@ -554,40 +554,78 @@ hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Reductions and elementwise kernels.
 
-// out[g * n + i] = sum over s = g S .. min((g + 1) S, splits) - 1, in that
-// order, of part[s * n + i]; one thread per (i, g).
-__global__ void k_reduce_groups(const float* part, int splits, int64_t n, int S, float* out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int s0 = (int)blockIdx.y * S, s1 = min(splits, s0 + S);
-  float acc = 0.f;
-#pragma unroll 8
-  for (int s = s0; s < s1; ++s) acc += part[(int64_t)s * n + i];
-  out[(int64_t)blockIdx.y * n + i] = acc;
+__device__ __forceinline__ int reduce_scratch_groups_dev(int splits) {
+  return splits <= kReduceGroup ? 0 : (splits + kReduceGroup - 1) / kReduceGroup;
 }
 
 int reduce_scratch_groups(int splits) {
   return splits <= kReduceGroup ? 0 : (splits + kReduceGroup - 1) / kReduceGroup;
 }
 
-// out[i] = sum of part[s * n + i] over the splits: in order within groups of
-// kReduceGroup consecutive splits, then over the groups in order (tmp holds
-// the group sums, reduce_scratch_groups(splits) * n floats).
-hipError_t launch_reduce_splits(const float* part, int splits, int64_t n, float* tmp, float* out,
-                                hipStream_t s) {
-  if (splits < 1 || n < 1) return hipErrorInvalidValue;
-  const unsigned nb = (unsigned)((n + 255) / 256);
-  const int G = reduce_scratch_groups(splits);
-  if (G == 0) {
-    hipLaunchKernelGGL(k_reduce_groups, dim3(nb, 1), dim3(256), 0, s, part, splits, n, splits,
-                       out);
+// Up to kMaxReduceJobs split sums, out[i] = sum of part[s * n + i] over the
+// splits, in one launch per stage; one thread per (value, group).  Stage 1:
+// jobs of at most kReduceGroup splits are summed whole, in split order, into
+// out; the others in groups of kReduceGroup consecutive splits, each in split
+// order, into tmp.  Stage 2 adds a job's group sums in group order into out.
+// first[j] is the first block of job j (first[njobs] = all blocks).
+struct ReduceBatchArgs {
+  ReduceJob job[kMaxReduceJobs];
+  int first[kMaxReduceJobs + 1];
+  int njobs, stage;
+};
+
+__global__ void k_reduce_batch(ReduceBatchArgs a) {
+  int j = 0;
+  while (j + 1 < a.njobs && (int)blockIdx.x >= a.first[j + 1]) ++j;
+  const ReduceJob& J = a.job[j];
+  const int local = (int)blockIdx.x - a.first[j];
+  const int chunks = (int)((J.n + 255) / 256);
+  const int G = reduce_scratch_groups_dev(J.splits);
+  if (a.stage == 1) {
+    const int g = local / chunks;
+    const int64_t i = (int64_t)(local % chunks) * 256 + threadIdx.x;
+    if (i >= J.n) return;
+    const int s0 = G ? g * kReduceGroup : 0, s1 = G ? min(J.splits, s0 + kReduceGroup) : J.splits;
+    float acc = 0.f;
+#pragma unroll 8
+    for (int s = s0; s < s1; ++s) acc += J.part[(int64_t)s * J.n + i];
+    if (G) J.tmp[(int64_t)g * J.n + i] = acc;
+    else J.out[i] = acc;
   } else {
-    if (!tmp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_reduce_groups, dim3(nb, G), dim3(256), 0, s, part, splits, n,
-                       kReduceGroup, tmp);
-    hipLaunchKernelGGL(k_reduce_groups, dim3(nb, 1), dim3(256), 0, s, tmp, G, n, G, out);
+    const int64_t i = (int64_t)local * 256 + threadIdx.x;
+    if (i >= J.n) return;
+    float acc = 0.f;
+    for (int g = 0; g < G; ++g) acc += J.tmp[(int64_t)g * J.n + i];
+    J.out[i] = acc;
   }
-  return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const ReduceJob* jobs, int njobs, hipStream_t s) {
+  if (njobs < 0 || njobs > kMaxReduceJobs) return hipErrorInvalidValue;
+  for (int stage = 1; stage <= 2; ++stage) {
+    ReduceBatchArgs a{};
+    a.stage = stage;
+    int64_t blocks = 0;
+    for (int k = 0; k < njobs; ++k) {
+      const ReduceJob& J = jobs[k];
+      if (J.splits < 1 || J.n < 1 || !J.part || !J.out) return hipErrorInvalidValue;
+      const int G = reduce_scratch_groups(J.splits);
+      if (G && !J.tmp) return hipErrorInvalidValue;
+      if (stage == 2 && G == 0) continue;
+      const int64_t chunks = (J.n + 255) / 256;
+      a.job[a.njobs] = J;
+      a.first[a.njobs] = (int)blocks;
+      ++a.njobs;
+      blocks += (stage == 1 && G) ? chunks * G : chunks;
+    }
+    if (a.njobs == 0) continue;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    a.first[a.njobs] = (int)blocks;
+    hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 __global__ void k_to_bf16(const float* p, uint16_t* pb, int64_t n) {
