@@ -494,6 +494,16 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     store();
     __syncthreads();
     if (pt + a.splits < npatch) load(pt + a.splits);
+    // Halo row 2 ks + grp / 2 + 2 (tap row ky = 2 of K step ks) is row ky = 0
+    // of step ks + 1: it is carried in registers instead of read again.
+    uint4 cv[NCB];
+    uint32_t ce[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const uint16_t* col = xt + ((cb0 + cb) * 16 + lr) * kHP + (grp >> 1) * kHR + (grp & 1) * 8;
+      cv[cb] = *reinterpret_cast<const uint4*>(col);
+      ce[cb] = *reinterpret_cast<const uint32_t*>(col + 8);
+    }
 #pragma unroll 1
     for (int ks = 0; ks < 8; ++ks) {
       // K step ks: patch pixels 32 ks .. 32 ks + 31; lane group grp holds
@@ -506,8 +516,19 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
                               (grp & 1) * 8;
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
-          const uint4 v = *reinterpret_cast<const uint4*>(col + ky * kHR);
-          const uint32_t e = *reinterpret_cast<const uint32_t*>(col + ky * kHR + 8);
+          uint4 v;
+          uint32_t e;
+          if (ky == 0) {
+            v = cv[cb];
+            e = ce[cb];
+          } else {
+            v = *reinterpret_cast<const uint4*>(col + ky * kHR);
+            e = *reinterpret_cast<const uint32_t*>(col + ky * kHR + 8);
+          }
+          if (ky == 2) {
+            cv[cb] = v;
+            ce[cb] = e;
+          }
           const uint4 v1 = make_uint4(__builtin_amdgcn_alignbit(v.y, v.x, 16),
                                       __builtin_amdgcn_alignbit(v.z, v.y, 16),
                                       __builtin_amdgcn_alignbit(v.w, v.z, 16),
