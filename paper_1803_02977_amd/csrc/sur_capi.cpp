@@ -346,9 +346,16 @@ lem_status backward(lem_sur_ctx* c, int B, const double* U, const double* target
   lem_status st;
   const Table& t = table();
   if (!c->wd_fresh) {
-    for (int k = 1; k < kNumConv; ++k)
-      SUR_CHECK(sur::launch_dgrad_weights(c->pb + t.conv[k].off, c->wd + t.conv[k].off,
-                                          t.conv[k].cin, t.conv[k].cout, c->s));
+    // Every layer but the first (whose input gradient is never needed).
+    sur::DgradLayers L{};
+    for (int k = 1; k < kNumConv; ++k) {
+      const int m = L.nlayers++;
+      L.off[m] = t.conv[k].off;
+      L.cin[m] = t.conv[k].cin;
+      L.cout[m] = t.conv[k].cout;
+      L.first[m + 1] = L.first[m] + (int64_t)t.conv[k].cout * 9 * t.conv[k].cin;
+    }
+    SUR_CHECK(sur::launch_dgrad_weights(c->pb, c->wd, L, c->s));
     c->wd_fresh = true;
   }
   const int64_t P0 = (int64_t)B * c->H * c->W;

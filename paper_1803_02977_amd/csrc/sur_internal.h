@@ -84,7 +84,17 @@ constexpr int kMaxReduceJobs = 32;
 // Runs up to kMaxReduceJobs independent split sums in two launches.
 hipError_t launch_reduce_batch(const ReduceJob* jobs, int njobs, hipStream_t s);
 hipError_t launch_to_bf16(const float* p, uint16_t* pb, int64_t n, hipStream_t s);
-hipError_t launch_dgrad_weights(const uint16_t* w, uint16_t* wd, int Cin, int Cout,
+// Layers whose flipped, channel-transposed weights launch_dgrad_weights
+// builds: weights of layer k at off[k] (cin[k] x 9 x cout[k] values); first
+// holds the running element counts (first[0] = 0).
+constexpr int kMaxDgradLayers = 16;
+struct DgradLayers {
+  int64_t off[kMaxDgradLayers];
+  int64_t first[kMaxDgradLayers + 1];
+  int cin[kMaxDgradLayers], cout[kMaxDgradLayers];
+  int nlayers;
+};
+hipError_t launch_dgrad_weights(const uint16_t* w, uint16_t* wd, const DgradLayers& L,
                                 hipStream_t s);
 hipError_t launch_features(const double* K, const double* U, const double* h0, uint16_t* x0,
                            int64_t P, hipStream_t s);

@@ -660,23 +660,30 @@ hipError_t launch_to_bf16(const float* p, uint16_t* pb, int64_t n, hipStream_t s
   return hipGetLastError();
 }
 
-// wd[ci][t][co] = w[co][8 - t][ci]: the input gradient of a 3x3 convolution
-// is the convolution of the output gradient with the spatially flipped,
-// channel-transposed kernel.
-__global__ void k_dgrad_weights(const uint16_t* w, uint16_t* wd, int Cin, int Cout) {
-  const int64_t n = (int64_t)Cin * 9 * Cout;
+// wd[ci][t][co] = w[co][8 - t][ci] for every listed layer (its weights at
+// off[k] in both arrays): the input gradient of a 3x3 convolution is the
+// convolution of the output gradient with the spatially flipped,
+// channel-transposed kernel.  One launch covers all layers; element i of the
+// concatenated layers belongs to layer k when first[k] <= i < first[k + 1].
+__global__ void k_dgrad_weights(const uint16_t* w, uint16_t* wd, DgradLayers L) {
+  const int64_t n = L.first[L.nlayers];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int co = (int)(i % Cout);
-    const int t = (int)((i / Cout) % 9);
-    const int ci = (int)(i / ((int64_t)Cout * 9));
-    wd[i] = w[((int64_t)co * 9 + (8 - t)) * Cin + ci];
+    int k = 0;
+    while (k + 1 < L.nlayers && i >= L.first[k + 1]) ++k;
+    const int64_t j = i - L.first[k];
+    const int Cin = L.cin[k], Cout = L.cout[k];
+    const int co = (int)(j % Cout);
+    const int t = (int)((j / Cout) % 9);
+    const int ci = (int)(j / ((int64_t)Cout * 9));
+    wd[L.off[k] + j] = w[L.off[k] + ((int64_t)co * 9 + (8 - t)) * Cin + ci];
   }
 }
 
-hipError_t launch_dgrad_weights(const uint16_t* w, uint16_t* wd, int Cin, int Cout,
+hipError_t launch_dgrad_weights(const uint16_t* w, uint16_t* wd, const DgradLayers& L,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_dgrad_weights, dim3(512), dim3(256), 0, s, w, wd, Cin, Cout);
+  if (L.nlayers < 1 || L.nlayers > kMaxDgradLayers) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dgrad_weights, dim3(1024), dim3(256), 0, s, w, wd, L);
   return hipGetLastError();
 }
 
