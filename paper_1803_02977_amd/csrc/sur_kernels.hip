@@ -372,6 +372,10 @@ constexpr int kPP = 264;  // LDS pitch of one output channel's 256 patch pixels
 constexpr int kHR = 24;   // LDS pitch of one 18-pixel halo row (16-byte aligned)
 constexpr int kHP = 456;  // LDS pitch of one input channel's 18 halo rows
 constexpr int kHaloPairs = kHalo * kHalo / 2 * 4;  // (pixel pair, 8-channel part) items
+// Tails of the halo rows (columns 8-9 and 16-17, read for the one-pixel
+// shifts), also kept apart: 2 per row, pitch kTP per channel, so that the 64
+// lanes' 4-byte reads of one row fall on 64 different banks.
+constexpr int kTP = 36;
 
 int wgrad_blocks_per_split(int Cin, int Cout) {
   const int cob = (Cout % 64 == 0) ? 64 : 32;
@@ -396,6 +400,7 @@ template <int COB>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t dzt[COB * kPP];
   __shared__ __attribute__((aligned(16))) uint16_t xt[32 * kHP];
+  __shared__ uint32_t xtail[32 * kTP];
   constexpr int NCB = COB == 64 ? 2 : 1;    // 16-channel input blocks per wave
   constexpr int PARTS = COB / 8;            // 8-channel parts of one dz pixel
   constexpr int DZ_ITEMS = 64 * PARTS / 256;  // (4-pixel quad, part) items per thread
@@ -484,6 +489,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         const uint32_t v = (c & 1) ? hi_pair(word(xr[k][0], w), word(xr[k][1], w))
                                    : lo_pair(word(xr[k][0], w), word(xr[k][1], w));
         *reinterpret_cast<uint32_t*>(xt + (part * 8 + c) * kHP + hy * kHR + hx) = v;
+        if (hx == 8 || hx == 16) xtail[(part * 8 + c) * kTP + hy * 2 + (hx >> 4)] = v;
       }
     }
   };
@@ -500,9 +506,9 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     uint32_t ce[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      const uint16_t* col = xt + ((cb0 + cb) * 16 + lr) * kHP + (grp >> 1) * kHR + (grp & 1) * 8;
-      cv[cb] = *reinterpret_cast<const uint4*>(col);
-      ce[cb] = *reinterpret_cast<const uint32_t*>(col + 8);
+      const int ci = (cb0 + cb) * 16 + lr;
+      cv[cb] = *reinterpret_cast<const uint4*>(xt + ci * kHP + (grp >> 1) * kHR + (grp & 1) * 8);
+      ce[cb] = xtail[ci * kTP + (grp >> 1) * 2 + (grp & 1)];
     }
 #pragma unroll 1
     for (int ks = 0; ks < 8; ++ks) {
@@ -512,8 +518,9 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
                                                          grp * 8);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
-        const uint16_t* col = xt + ((cb0 + cb) * 16 + lr) * kHP + (2 * ks + (grp >> 1)) * kHR +
-                              (grp & 1) * 8;
+        const int ci = (cb0 + cb) * 16 + lr;
+        const uint16_t* col = xt + ci * kHP + (2 * ks + (grp >> 1)) * kHR + (grp & 1) * 8;
+        const uint32_t* tail = xtail + ci * kTP + (2 * ks + (grp >> 1)) * 2 + (grp & 1);
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
           uint4 v;
@@ -523,7 +530,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
             e = ce[cb];
           } else {
             v = *reinterpret_cast<const uint4*>(col + ky * kHR);
-            e = *reinterpret_cast<const uint32_t*>(col + ky * kHR + 8);
+            e = tail[ky * 2];
           }
           if (ky == 2) {
             cv[cb] = v;
