@@ -369,6 +369,12 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
 // global loads are issued before the current patch's MFMAs.  Results go to
 // per-split partials, summed later in split order.
 constexpr int kPP = 264;  // LDS pitch of one output channel's 256 patch pixels
+
+// Position of patch pixel px in the LDS row of output channel ch: the
+// 32-pixel groups are permuted by channel, so that the 64 lanes of one
+// transposing write (8-channel parts of 8 quads) spread over all banks; an
+// aligned 8-pixel block stays an aligned block.
+__device__ __forceinline__ int dz_pos(int ch, int px) { return px ^ (32 * ((ch >> 4) & 3)); }
 constexpr int kHR = 24;   // LDS pitch of one 18-pixel halo row (16-byte aligned)
 constexpr int kHP = 456;  // LDS pitch of one input channel's 18 halo rows
 constexpr int kHaloPairs = kHalo * kHalo / 2 * 4;  // (pixel pair, 8-channel part) items
@@ -474,7 +480,8 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
           pk.x = lo_pair(word(dzr[k][0], w), word(dzr[k][1], w));
           pk.y = lo_pair(word(dzr[k][2], w), word(dzr[k][3], w));
         }
-        *reinterpret_cast<uint2*>(dzt + (part * 8 + c) * kPP + quad * 4) = pk;
+        *reinterpret_cast<uint2*>(dzt + (part * 8 + c) * kPP + dz_pos(part * 8 + c, quad * 4)) =
+            pk;
       }
     }
 #pragma unroll
@@ -514,8 +521,8 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     for (int ks = 0; ks < 8; ++ks) {
       // K step ks: patch pixels 32 ks .. 32 ks + 31; lane group grp holds
       // pixels 32 ks + 8 grp .. + 7 = row 2 ks + grp / 2, columns 8 (grp % 2) ...
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(dzt + (mb * 16 + lr) * kPP + ks * 32 +
-                                                         grp * 8);
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(
+          dzt + (mb * 16 + lr) * kPP + dz_pos(mb * 16 + lr, ks * 32 + grp * 8));
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         const int ci = (cb0 + cb) * 16 + lr;
