@@ -233,6 +233,9 @@ def test_each_layer_matches_reference_on_the_gpus_own_inputs(shape):
         low = act[8] if level == 2 else act[14 + 3 * (k - 1)]
         cat = np.concatenate([S.up2(low), act[2 + 2 * level]], axis=-1)
         assert np.array_equal(act[12 + 3 * k], cat), f"concatenation at level {level}"
+        # The concatenation is assembled on request; a smaller batch gets the
+        # same leading grids.
+        assert np.array_equal(net.activation(12 + 3 * k, 1).astype(np.float64), cat[:1]), level
         conv_check(f"dec{level}a", 12 + 3 * k, 13 + 3 * k)
         conv_check(f"dec{level}b", 13 + 3 * k, 14 + 3 * k)
     wh, bh = P["head"]
