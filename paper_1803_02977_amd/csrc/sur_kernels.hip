@@ -364,16 +364,17 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
 // all nine taps, and loops over the 16x16-pixel patches s, s + splits, ....
 // Per patch it stages, channel-major (pixels contiguous), the patch's dz and
 // the 18x18 input halo around it; the halo rows are 16-byte aligned, so the
-// three column shifts of one tap row come from one aligned 16-byte read and
-// one 4-byte read (shifts by one pixel via alignbit).  The next patch's
-// global loads are issued before the current patch's MFMAs.  Results go to
-// per-split partials, summed later in split order.
+// three column shifts of one tap row come from one aligned 16-byte read of
+// the row and one 4-byte read of its tail (columns 8-9 or 16-17, also stored
+// apart; shifts by one pixel via alignbit).  The next patch's global loads
+// are issued before the current patch's MFMAs.  Results go to per-split
+// partials, summed later in split order.
 constexpr int kPP = 264;  // LDS pitch of one output channel's 256 patch pixels
 
 // Position of patch pixel px in the LDS row of output channel ch: the
 // 32-pixel groups are permuted by channel, so that the 64 lanes of one
-// transposing write (8-channel parts of 8 quads) spread over all banks; an
-// aligned 8-pixel block stays an aligned block.
+// transposing 8-byte write (8-channel parts of 8 quads) hit each bank at most
+// twice, the minimum for 512 bytes; an aligned 8-pixel block stays aligned.
 __device__ __forceinline__ int dz_pos(int ch, int px) { return px ^ (32 * ((ch >> 4) & 3)); }
 constexpr int kHR = 24;   // LDS pitch of one 18-pixel halo row (16-byte aligned)
 constexpr int kHP = 456;  // LDS pitch of one input channel's 18 halo rows
