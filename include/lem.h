@@ -46,7 +46,8 @@ typedef enum lem_status {
   LEM_E_ARG = 1,        /* a NULL pointer, a bad size or a bad parameter          */
   LEM_E_SIZE = 2,       /* the grid is too small (< 3x3) or too large (> 2^31-1)  */
   LEM_E_WORKSPACE = 3,  /* the workspace is missing, misaligned or too small      */
-  LEM_E_NONFINITE = 4,  /* LEM_F_VALIDATE found a NaN or infinity in an input     */
+  LEM_E_NONFINITE = 4,  /* LEM_F_VALIDATE found a NaN or infinity in an input, or
+                           a run to steady state produced one                     */
   LEM_E_CYCLE = 5,      /* receivers form a cycle (only possible with fixed routing) */
   LEM_E_HIP = 6,        /* a HIP runtime call failed                              */
   LEM_E_STATE = 7       /* the call needs state the context does not have yet     */
@@ -70,8 +71,10 @@ typedef enum lem_status {
  *   K       erodibility in 1/yr (>= 0), used where no K field is given;
  *   eps     Newton tolerance epsilon of Algorithm 6 in metres (> 0 when
  *           n != 1; ignored for n = 1): the loop stops once two iterates
- *           differ by at most eps, or once the iterate is no longer above
- *           the receiver;
+ *           differ by at most eps.  An iterate that would not lie above
+ *           the receiver's new height is replaced by the midpoint between
+ *           the receiver and the previous iterate; a cell whose uplifted
+ *           height is not above its receiver's new height keeps it;
  *   max_newton  iteration limit of that loop (>= 1 when n != 1);
  *   flags   LEM_F_* bits.                                                    */
 typedef struct lem_params {
@@ -234,7 +237,10 @@ lem_status lem_batch_run(lem_ctx* ctx, double* d_h, const double* d_K, const dou
  * a grid with h_steps[g] >= 0 on entry counts as steady already (it is not
  * stepped and its entry is kept), which lets a long run continue over
  * several calls; every other grid receives the number of steps this call
- * took it to converge, or -1.  Synchronizes the stream. */
+ * took it to converge, or -1.  A grid whose heights stop being finite (a
+ * NaN or infinity in its change or its heights) ends the call with
+ * LEM_E_NONFINITE; the heights are then unspecified.  Synchronizes the
+ * stream. */
 lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
                                    const double* d_U, double rtol, int64_t check_every,
                                    int64_t max_steps, int64_t* h_steps);

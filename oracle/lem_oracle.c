@@ -204,8 +204,13 @@ void lemo_erode(int32_t ny, int32_t nx, double dx, double dy, double dt, double 
 /* Algorithm 6 ("Calculate erosion") with its Newton-Raphson loop, for a
  * general slope exponent n > 0: starting from the uplifted height h0,
  * h <- h - (h - h0 + F*(h - h_r)^n) / (1 + F*n*(h - h_r)^(n-1)) until the
- * change is at most eps, with F = K*dt*A^m/dist^n.  A cell whose new height
- * would not stay above its receiver's stops at the first iterate. */
+ * change is at most eps or max_iter iterations have run, with
+ * F = K*dt*A^m/dist^n.  The equation h - h0 + F*(h - h_r)^n = 0 has exactly
+ * one root in (h_r, h0] when h0 > h_r; a Newton iterate that does not lie
+ * above the receiver (possible for n < 1, where the residual is concave) is
+ * replaced by the midpoint between the receiver and the previous iterate.
+ * A cell whose uplifted height is not above its receiver's new height keeps
+ * h0 (no positive slope, no erosion). */
 void lemo_erode_newton(int32_t ny, int32_t nx, double dx, double dy, double dt,
                        double m, double nexp, double eps, int32_t max_iter,
                        double K, const double* Kfield, const int32_t* rec,
@@ -224,15 +229,17 @@ void lemo_erode_newton(int32_t ny, int32_t nx, double dx, double dy, double dt,
     const double f = ((kc * dt) * pow(area, m)) / pow(d, nexp);
     const double h0 = h[c];
     const double hn = h[r];
-    double hnew = h0, hp = h0, delta = 2.0 * eps;
+    double hnew = h0, delta = 2.0 * eps;
     int32_t it = 0;
-    while (fabs(delta) > eps && it < max_iter) {
-      const double g = hnew - hn;
-      if (!(g > 0.0)) break;
-      hnew = hnew - (hnew - h0 + f * pow(g, nexp)) / (1.0 + f * nexp * pow(g, nexp - 1.0));
-      delta = hnew - hp;
-      hp = hnew;
-      ++it;
+    if (h0 - hn > 0.0) {
+      while (fabs(delta) > eps && it < max_iter) {
+        const double g = hnew - hn;
+        double next = hnew - (hnew - h0 + f * pow(g, nexp)) / (1.0 + f * nexp * pow(g, nexp - 1.0));
+        if (!(next - hn > 0.0)) next = 0.5 * (hnew + hn);
+        delta = next - hnew;
+        hnew = next;
+        ++it;
+      }
     }
     h[c] = hnew;
   }

@@ -519,6 +519,12 @@ lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
     if (e != hipSuccess) return hip_fail(ctx, e, "convergence check");
     bool changed = false;
     for (int32_t g = 0; g < ng; ++g) {
+      if (!done[g] && !(std::isfinite(conv[2 * g]) && std::isfinite(conv[2 * g + 1]))) {
+        st = fail(ctx, LEM_E_NONFINITE, "grid " + std::to_string(g) +
+                                            ": heights are no longer finite after step " +
+                                            std::to_string(s));
+        break;
+      }
       if (done[g] || !(conv[2 * g] <= rtol * conv[2 * g + 1])) continue;
       done[g] = 1;
       h_steps[g] = s;
@@ -530,6 +536,7 @@ lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
       if (e != hipSuccess) return hip_fail(ctx, e, "freeze copy");
       active_cells -= (int64_t)G.ny * G.nx;
     }
+    if (st != LEM_OK) break;
     if (changed && active_cells > 0) {
       ctx->active.clear();
       for (int32_t g = 0; g < ng; ++g) {

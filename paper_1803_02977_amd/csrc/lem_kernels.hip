@@ -19,8 +19,8 @@
 //      from one buffer and written to the other, so halo reads never see a
 //      neighbouring tile's new values.
 //
-//  k_global_levels   one cooperative (persistent) kernel of at most 128
-//      workgroups of 1024 threads for the crossing trees, with device-side
+//  k_global_levels   one cooperative (persistent) kernel of at most
+//      kGlobalMaxWGs workgroups of 1024 threads for the crossing trees, with device-side
 //      level loops: breadth-first expansion (a workgroup prefix scan per
 //      chunk and one atomic add per chunk to reserve its output), counts in
 //      reverse level order (each queue position pulls its donors' counts,
@@ -215,17 +215,21 @@ __device__ __forceinline__ void erosion_factor(const StepArgs& a, const GridDev&
 // its already updated receiver height hr.  For n = 1 the Newton iteration of
 // Algorithm 6 started at h0 reaches (h0 + F*hr)/(1 + F) in one step, so that
 // closed form is used; otherwise the loop runs until two iterates differ by
-// at most eps, the iteration limit is reached, or the iterate no longer lies
-// above the receiver.
+// at most eps or the iteration limit is reached.  The residual
+// h - h0 + F*(h - hr)^n has one root in (hr, h0] when h0 > hr; an iterate
+// that does not lie above the receiver (n < 1 can overshoot) is replaced by
+// the midpoint between the receiver and the previous iterate.  A cell not
+// above its receiver keeps h0.
 __device__ __noinline__ double newton_height(double h0, double hr, double f, double nexp,
                                              double eps, int max_iter) {
-  double hnew = h0, hp = h0, delta = 2.0 * eps;
+  double hnew = h0, delta = 2.0 * eps;
+  if (!(h0 - hr > 0.0)) return h0;
   for (int it = 0; fabs(delta) > eps && it < max_iter; ++it) {
     const double gap = hnew - hr;
-    if (!(gap > 0.0)) break;
-    hnew = hnew - (hnew - h0 + f * pow(gap, nexp)) / (1.0 + f * nexp * pow(gap, nexp - 1.0));
-    delta = hnew - hp;
-    hp = hnew;
+    double next = hnew - (hnew - h0 + f * pow(gap, nexp)) / (1.0 + f * nexp * pow(gap, nexp - 1.0));
+    if (!(next - hr > 0.0)) next = 0.5 * (hnew + hr);
+    delta = next - hnew;
+    hnew = next;
   }
   return hnew;
 }
@@ -1568,17 +1572,21 @@ __global__ __launch_bounds__(256) void k_export_cells(StepArgs a, int gi, int64_
 __global__ __launch_bounds__(256) void k_change(StepArgs a) {
   const GridDev& G = a.grids[blockIdx.y];
   const int64_t cells = (int64_t)G.ny * G.nx;
+  // Maxima that keep a NaN (fmax would drop it): a grid whose heights are
+  // no longer finite must not look steady; the host reports it.
   double dmax = 0.0, hmax = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double hn = a.h_out[G.offset + i];
-    dmax = fmax(dmax, fabs(hn - a.h_in[G.offset + i]));
-    hmax = fmax(hmax, fabs(hn));
+    const double dh = fabs(hn - a.h_in[G.offset + i]), ah = fabs(hn);
+    dmax = (dh > dmax || dh != dh) && dmax == dmax ? dh : dmax;
+    hmax = (ah > hmax || ah != ah) && hmax == hmax ? ah : hmax;
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
-    dmax = fmax(dmax, __shfl_xor(dmax, d, 64));
-    hmax = fmax(hmax, __shfl_xor(hmax, d, 64));
+    const double od = __shfl_xor(dmax, d, 64), oh = __shfl_xor(hmax, d, 64);
+    dmax = (od > dmax || od != od) && dmax == dmax ? od : dmax;
+    hmax = (oh > hmax || oh != oh) && hmax == hmax ? oh : hmax;
   }
   if ((threadIdx.x & 63) == 0) {
     unsigned long long* cv = (unsigned long long*)a.w.conv;

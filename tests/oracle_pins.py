@@ -387,6 +387,103 @@ def pin_newton_step_solves_the_implicit_equation(lib):
     assert checked > 0
 
 
+def _chain_routing(ny, nx):
+    """Fixed routing of a 1-D channel: every interior cell of the middle row
+    drains to its left neighbour; the left perimeter cell is the outlet."""
+    rec = np.arange(ny * nx, dtype=np.int32).reshape(ny, nx)
+    for x in range(1, nx - 1):
+        rec[1, x] = nx + x - 1
+    return rec
+
+
+def _newton_cells(h_in, out, rec, p, U):
+    """(c, h0, hr', F, h') for every non-root cell of a fixed-routing step."""
+    nx = p.nx
+    hn, cnt = out["h"].ravel(), out["count"].ravel()
+    recf, hin, uf = rec.ravel(), h_in.ravel(), np.ravel(U)
+    for c in range(hin.size):
+        r = recf[c]
+        if r == c:
+            continue
+        d = _dist(c, r, nx, p.dx, p.dy)
+        f = p.K * p.dt * (cnt[c] * p.dx * p.dy) ** p.m / d ** p.n
+        yield c, hin[c] + uf[c] * p.dt, hn[r], f, hn[c]
+
+
+def pin_newton_overshoot_stays_above_receiver(lib):
+    """n = 0.5 with a large F: the first Newton iterate from h0 falls below the
+    receiver for some cells.  The backward-Euler equation
+    h' - h0 + F (h' - h'_r)^n = 0 still has exactly one root in (h'_r, h0];
+    every cell's new height must be that root (found here by SciPy's brentq),
+    strictly above its receiver."""
+    from scipy.optimize import brentq
+    ny, nx = 3, 24
+    rec = _chain_routing(ny, nx)
+    h = np.zeros((ny, nx))
+    h[1, 1:-1] = np.linspace(0.4, 9.0, nx - 2)
+    p = oracle.Params(ny, nx, 100.0, 100.0, 5e4, 0.5, 0.5, 1e-4, 4e-5, eps=1e-13, max_newton=200)
+    U = np.full((ny, nx), p.U)
+    out = oracle.run_fixed_routing(h, rec, p, 1, U=U, lib=lib)
+    overshoots = 0
+    for c, h0, hr, f, got in _newton_cells(h, out, rec, p, U):
+        g = h0 - hr
+        first = h0 - (f * g ** p.n) / (1.0 + f * p.n * g ** (p.n - 1.0))
+        overshoots += first <= hr
+        assert got > hr, (c, got, hr)
+        root = brentq(lambda x: x - h0 + f * (x - hr) ** p.n, hr, h0, xtol=1e-15, rtol=1e-15)
+        assert abs(got - root) <= 1e-10 * max(abs(root), 1.0), (c, got, root)
+    assert overshoots >= 3, overshoots
+    # An iterate landing exactly on the receiver: h0 = 1 above an outlet at 0,
+    # F = K dt A^m / d^n = 0.5 * 4 * 1 / 1 = 2 and n = 0.5 give the first step
+    # 1 - 2 / (1 + 0.5 * 2) = 0 exactly; the root is (sqrt(2) - 1)^2.
+    rec = _chain_routing(3, 3)
+    h = np.zeros((3, 3))
+    h[1, 1] = 1.0
+    p = oracle.Params(3, 3, 1.0, 1.0, 4.0, 0.5, 0.5, 0.0, 0.5, eps=1e-15, max_newton=200)
+    got = oracle.run_fixed_routing(h, rec, p, 1, lib=lib)["h"][1, 1]
+    assert abs(got - (np.sqrt(2.0) - 1.0) ** 2) <= 1e-14, got
+
+
+def pin_newton_iteration_cap(lib):
+    """n = 2 with one permitted iteration: the residual is convex, so Newton
+    from h0 approaches the root from above; after one iteration each cell
+    with a noticeable slope lies strictly between the exact root (brentq)
+    and h0."""
+    from scipy.optimize import brentq
+    ny, nx = 3, 16
+    rec = _chain_routing(ny, nx)
+    h = np.zeros((ny, nx))
+    h[1, 1:-1] = np.linspace(2.0, 30.0, nx - 2)
+    p = oracle.Params(ny, nx, 100.0, 100.0, 1e4, 0.5, 2.0, 1e-4, 2e-4, eps=1e-14, max_newton=1)
+    U = np.full((ny, nx), p.U)
+    out = oracle.run_fixed_routing(h, rec, p, 1, U=U, lib=lib)
+    checked = 0
+    for c, h0, hr, f, got in _newton_cells(h, out, rec, p, U):
+        root = brentq(lambda x: x - h0 + f * (x - hr) ** 2, hr, h0, xtol=1e-15, rtol=1e-15)
+        assert root < got < h0, (c, root, got, h0)
+        assert got - root > 1e-6 * (h0 - root), (c, got, root)
+        checked += 1
+    assert checked == nx - 2
+
+
+def pin_newton_cell_not_above_receiver_keeps_height(lib):
+    """A U field that lifts a receiver above its donor: the donor has no
+    positive slope, so no erosion applies and it keeps its uplifted height
+    exactly; the cells that stay above their receivers erode."""
+    ny, nx = 3, 6
+    rec = _chain_routing(ny, nx)
+    h = np.zeros((ny, nx))
+    h[1, 1:-1] = [1.0, 2.0, 3.0, 4.0]
+    U = np.zeros((ny, nx))
+    U[1, 2] = 0.01  # the receiver of cell (1, 3) rises by 10 m
+    p = oracle.Params(ny, nx, 100.0, 100.0, 1e3, 0.5, 1.5, 0.0, 1e-6, eps=1e-12, max_newton=50)
+    out = oracle.run_fixed_routing(h, rec, p, 1, U=U, lib=lib)
+    hn = out["h"]
+    assert hn[1, 3] == 3.0, hn[1, 3]
+    assert hn[1, 2] > hn[1, 3]
+    assert 0.0 < hn[1, 1] < 1.0 and 3.0 < hn[1, 4] < 4.0, hn[1]
+
+
 def _mfd_receivers(h, dx, dy, pexp):
     """Receivers and shares of every interior cell by the definition:
     strictly lower neighbours, share proportional to slope**pexp."""
@@ -487,5 +584,7 @@ ALL_PINS = [pin_table1, pin_receivers_special_cases, pin_receivers_brute_force,
             pin_no_erosion_is_pure_uplift, pin_long_step_follows_receiver,
             pin_steady_state_slope_area, pin_channel_profile, pin_newton_matches_closed_form,
             pin_newton_channel_profile, pin_newton_step_solves_the_implicit_equation,
+            pin_newton_overshoot_stays_above_receiver, pin_newton_iteration_cap,
+            pin_newton_cell_not_above_receiver_keeps_height,
             pin_mfd_area_conservation_and_dense_solve, pin_mfd_levels_are_longest_paths,
             pin_mfd_step_solves_the_implicit_system, pin_mfd_without_erosion_is_pure_uplift]

@@ -230,3 +230,21 @@ def test_full_size_batch_sampled_realizations_match_oracle():
         ref = oracle.run(W.initial_heights(r.ny, r.nx, r.seed), p, 3)
         assert_routing_equal(b.routing(g), ref)
         assert_heights_close(b.view(h, g).cpu().numpy(), ref["h"])
+
+
+def test_run_to_steady_reports_heights_that_stop_being_finite():
+    """A NaN in one grid's heights (no input validation) never passes for a
+    steady state: the call ends with LEM_E_NONFINITE instead."""
+    torch = require_gpu()
+    from paper_1803_02977_amd.lem import LEM_E_NONFINITE, LemError
+    grids = [W.Realization(s, s, 100.0, 100.0, 2e4, 0.5, 1e-3, 5e-5, 70 + i)
+             for i, s in enumerate((24, 40))]
+    h0 = W.batch_initial_heights(grids)
+    h0[24 * 24 + 40 * 7 + 9] = np.nan
+    b = _batch(torch, grids)
+    h = torch.from_numpy(h0).to("cuda:0")
+    print("[gpu] run_to_steady with a NaN height", flush=True)
+    with pytest.raises(LemError) as e:
+        b.run_to_steady(h, rtol=1e-6, check_every=5, max_steps=200)
+    assert e.value.status == LEM_E_NONFINITE, e.value
+    b.close()

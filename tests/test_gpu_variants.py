@@ -95,3 +95,17 @@ def test_batch_of_mixed_exponents_equals_each_grid_alone():
         ref = oracle.run(hs, _params(w, g["ny"], g["nx"], g["n"]), 10)
         assert_heights_close(single, ref["h"])
     b.close()
+
+
+def test_newton_below_one_with_overshooting_iterates():
+    """n = 0.5 with a large K*dt: Newton overshoots below the receiver for many
+    cells and both sides replace such iterates by the midpoint towards the
+    receiver (Algorithm 6 with the safeguard); 300x260 spans several tiles."""
+    torch = require_gpu()
+    w = W.SMALL_256.with_(ny=300, nx=260, m=0.5, dt=5e4, K=4e-5, U=1e-4)
+    h0 = W.initial_heights(w.ny, w.nx, 34) * 30.0
+    print("[gpu] newton n=0.5 overshoot 300x260 6 steps", flush=True)
+    got, r = _gpu(torch, w, 0.5, h0, 6, eps=1e-13, max_newton=200)
+    ref = oracle.run(h0, _params(w, w.ny, w.nx, 0.5, 1e-13, 200), 6)
+    assert_routing_equal(r, ref)
+    assert_heights_close(got, ref["h"])

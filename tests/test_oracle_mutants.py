@@ -44,6 +44,20 @@ MUTANTS = [
      "(hnew - h0 - f * pow(g, nexp))"),
     ("Newton stops after one iteration", "fabs(delta) > eps && it < max_iter",
      "fabs(delta) > eps && it < 1"),
+    ("Newton iteration cap ignored", "fabs(delta) > eps && it < max_iter",
+     "fabs(delta) > eps && it < 1000"),
+    ("Newton iterate below the receiver kept",
+     "if (!(next - hn > 0.0)) next = 0.5 * (hnew + hn);", "(void)0;"),
+    ("Newton stops at the first iterate not above the receiver",
+     "if (!(next - hn > 0.0)) next = 0.5 * (hnew + hn);",
+     "if (!(next - hn > 0.0)) { hnew = next; break; }"),
+    ("Newton guard admits a zero gap",
+     "if (!(next - hn > 0.0)) next = 0.5 * (hnew + hn);",
+     "if (!(next - hn >= 0.0)) next = 0.5 * (hnew + hn);"),
+    ("Newton overshoot replaced by the midpoint towards h0",
+     "if (!(next - hn > 0.0)) next = 0.5 * (hnew + hn);",
+     "if (!(next - hn > 0.0)) next = 0.5 * (hnew + h0);"),
+    ("Newton erodes a cell not above its receiver", "if (h0 - hn > 0.0) {", "if (1) {"),
     ("MFD shares not normalised", "pexp) / wsum[d];", "pexp);"),
     ("MFD erosion with the old receiver height", "sumfh += f * h[r];", "sumfh += f * h0[r];"),
     ("MFD levels by the shallowest receiver", "if (h0[c] - h0[r] > 0.0 && level[r] + 1 > l) l = level[r] + 1;",
