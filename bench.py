@@ -104,10 +104,15 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="batch workload: skip the grid-by-grid comparison (counter runs)")
     ap.add_argument("--cpu-steps", type=int, default=None)
-    ap.add_argument("--repeats", type=int, default=1)
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain device-to-device copy of 2 GiB (three times) "
-                         "whose HBM counters calibrate FETCH_SIZE and WRITE_SIZE")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of the K steps (each from the same initial heights); "
+                         "the median is reported")
+    ap.add_argument("--no-copy-probe", action="store_true",
+                    help="skip the timed 2 GiB device-to-device copy (achievable HBM GB/s)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the serial oracle over the full length of the 256x256 and "
+                         "2048x2048 workloads (and, with --workload plain-10000x10000-fp64, "
+                         "over its 50 steps) instead of running the GPU benchmark")
     return ap.parse_args()
 
 
@@ -515,6 +520,20 @@ def bench_warmstart(args):
         "cpu_baseline": cpu}), flush=True)
 
 
+def host_cpu():
+    """Model name of the host CPU and the number of online cores."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(w, h0, K, steps):
     """The serial oracle (one host thread) on ``steps`` steps of the workload."""
     import oracle
@@ -522,9 +541,50 @@ def cpu_baseline(w, h0, K, steps):
     t = time.perf_counter()
     oracle.run(h0, p, steps, K=K)
     dt = time.perf_counter() - t
+    model, nproc = host_cpu()
     return dict(value=w.cells * steps / dt, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"{steps} step(s) of the full {w.ny}x{w.nx} grid from its initial "
-                       f"heights, serial C oracle, {dt:.2f} s")
+                sample=f"{steps} of the {w.steps} step(s) of the full {w.ny}x{w.nx} grid from "
+                       f"its initial heights, serial C oracle, {dt:.2f} s",
+                cpu_model=model, nproc=nproc, seconds=round(dt, 2), steps=steps)
+
+
+def cpu_full(args):
+    """The serial oracle over whole workloads (one JSON line each)."""
+    names = [W.SMALL_256.name, W.MEDIUM_2048.name]
+    if args.workload == W.LARGE_10000.name:
+        names.append(W.LARGE_10000.name)
+    for name in names:
+        w = W.WORKLOADS[name]
+        h0, K, _ = W.make_inputs(w, args.seed)
+        r = cpu_baseline(w, h0, K, w.steps)
+        r["workload"] = name
+        r["seconds_per_step"] = round(r["seconds"] / w.steps, 4)
+        print(json.dumps(r), flush=True)
+
+
+def copy_probe(dev, reps=5):
+    """Achievable HBM bandwidth on this GPU: a plain 2 GiB device-to-device
+    copy (2 GiB read + 2 GiB written), median of ``reps`` timed copies."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    nbytes = 2 * src.numel() * 8
+    del src, dst
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    med = float(np.median(times))
+    return {"bytes_per_copy": nbytes, "ms_median": round(med, 4),
+            "gbs": round(nbytes / (med * 1e-3) / 1e9, 1),
+            "note": "torch copy_ of 2 GiB float64 on the GPU (read + write counted)"}
 
 
 def main():
@@ -534,6 +594,9 @@ def main():
               "several GPUs is designed (row strips, boundary graphs) but not implemented",
               file=sys.stderr)
         sys.exit(2)
+    if args.cpu_full:
+        cpu_full(args)
+        return
     if args.workload == BATCH_NAME:
         bench_batch(args)
         return
@@ -567,7 +630,7 @@ def main():
     if args.warmup > 0:
         solver.run(h, args.warmup, K=Kt)
         solver.sync()
-    best = None
+    runs = []
     for _ in range(max(1, args.repeats)):
         h.copy_(h0)
         torch.cuda.synchronize()
@@ -579,11 +642,10 @@ def main():
         ev1.record(stream)
         solver.sync()
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = ev0.elapsed_time(ev1)
-        if best is None or ms < best[0]:
-            best = (ms, wall)
-    ms, wall = best
+        runs.append((ev0.elapsed_time(ev1), time.perf_counter() - t0))
+    runs.sort()
+    ms, wall = runs[len(runs) // 2]  # the median run (the middle one for an odd count)
+    run_ms = [r[0] / steps for r in runs]
     levels = solver.level_history(steps)
     # Level-size histogram of the last timed step (cells per level of Alg 3,
     # whole grid: trees inside a tile and crossing trees together).
@@ -648,6 +710,10 @@ def main():
                    "K_field": "lognormal" if Kt is not None else "scalar", "seed": args.seed},
         "roofline": roofline,
         "hbm_roofline_frac_65B": round(value * alg_step / (HBM_PEAK_GBS * 1e9), 4),
+        "repeats": {"count": len(runs), "reported": "median",
+                    "ms_per_step_min_median_max": [round(run_ms[0], 4),
+                                                   round(run_ms[len(run_ms) // 2], 4),
+                                                   round(run_ms[-1], 4)]},
         "wall_s": wall,
         "levels": {"min": int(levels.min()), "max": int(levels.max()),
                    "mean": float(levels.mean()), "per_step": [int(x) for x in levels],
@@ -659,14 +725,14 @@ def main():
         "crossing_cells_per_step": crossing,
         "crossing_frac": round(crossing / cells, 4),
     }
-    if args.copy_probe:
-        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+    roofline["frac_whole_step_65B"] = out["hbm_roofline_frac_65B"]
+    if not args.no_copy_probe:
+        del h, h0, Kt
         torch.cuda.synchronize()
-        out["copy_probe_bytes_each_way"] = src.numel() * 8
-        del src, dst
+        torch.cuda.empty_cache()
+        probe = copy_probe(dev)
+        out["copy_probe"] = probe
+        roofline["frac_of_copy_probe"] = round(achieved / probe["gbs"], 4)
     if not args.no_cpu:
         cpu_steps = args.cpu_steps or (2 if cells >= 10 ** 8 else max(1, min(steps, int(2e8 // cells))))
         out["cpu_baseline"] = cpu_baseline(w, h0_np, K_np, cpu_steps)
