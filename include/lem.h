@@ -298,6 +298,31 @@ const char* lem_status_str(lem_status s);
 /* Message of the most recent error on this context ("" if none). */
 const char* lem_last_error(const lem_ctx* ctx);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, serving loops, harnesses that forbid allocation): `steps` time
+ * steps of one grid as lem_create + lem_run + lem_sync + lem_destroy would
+ * run them, over a workspace held in a device array inside the library
+ * (LEM_STATIC_WORKSPACE_BYTES on each device the library runs on, kept until
+ * the process ends) instead of one the caller passes.  Nothing is allocated
+ * on the device and no allocating library routine is called.
+ *   p        grid and parameters as for lem_create; LEM_F_PHASE_TIMERS is
+ *            rejected (LEM_E_ARG);
+ *   d_h      float64 ny*nx heights on the current device, row-major,
+ *            updated in place; d_K, d_U optional per-cell fields (NULL:
+ *            the scalars in p);
+ *   hip_stream  a hipStream_t of the current device (NULL: default stream).
+ * Returns after the stream has finished the steps.  Grids whose
+ * lem_workspace_bytes(p) exceeds LEM_STATIC_WORKSPACE_BYTES (more than
+ * 262,144 cells, e.g. 512 x 512, in any shape) are rejected with
+ * LEM_E_WORKSPACE before anything is enqueued; invalid parameters give the
+ * status lem_create gives.  Every call on one device uses the same array,
+ * which keeps the last call's contents (the library clears what must start
+ * at zero): calls that overlap on one device, from several threads or
+ * streams, race and their results are unspecified. */
+#define LEM_STATIC_WORKSPACE_BYTES ((size_t)16 << 20)
+lem_status lem_run_static(const lem_params* p, double* d_h, const double* d_K,
+                          const double* d_U, int64_t steps, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB_PATH = os.path.join(HERE, "liblem.so")
 
-SOURCES = ["lem_kernels.hip", "lem_capi.cpp", "sur_kernels.hip", "sur_capi.cpp"]
+SOURCES = ["lem_kernels.hip", "lem_capi.cpp", "lem_static.hip", "sur_kernels.hip", "sur_capi.cpp"]
 
 # -ffp-contract=off: no fused multiply-add contraction anywhere, so every
 # expression rounds as written.  Packed FP32 instructions are disabled.

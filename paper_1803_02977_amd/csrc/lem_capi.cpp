@@ -38,7 +38,7 @@ struct lem_ctx {
   bool has_routing;
   double route_ms;                  // accumulated with LEM_F_PHASE_TIMERS
   double order_ms;
-  hipEvent_t ev0, ev1, ev2;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;  // LEM_F_PHASE_TIMERS only
   std::string err;
 };
 
@@ -301,9 +301,11 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
     if (per_cu_mfd < per_cu) per_cu = per_cu_mfd;
   }
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, ctx->device);
-  if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
-  if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
-  if (e == hipSuccess) e = hipEventCreate(&ctx->ev2);
+  if (ctx->flags & LEM_F_PHASE_TIMERS) {
+    if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->ev2);
+  }
   if (e != hipSuccess || per_cu < 1) return LEM_E_HIP;
   // The global level kernel uses at most kGlobalMaxWGs resident workgroups:
   // a grid-wide barrier's cost grows with the number of participants.
@@ -314,7 +316,7 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
   ctx->pergrid = auto_pergrid(ctx);
   ctx->level_threads = 0;
   ctx->tick_khz = (double)rate;
-  e = hipMemsetAsync(ctx->w.ctrl, 0, sizeof(lem::Ctrl), ctx->stream);
+  e = lem::launch_zero_words(ctx->w.ctrl, sizeof(lem::Ctrl) / 4, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->w.grids, ctx->grids.data(), sizeof(lem::GridDev) * ng,
                        hipMemcpyHostToDevice, ctx->stream);
@@ -726,9 +728,9 @@ lem_status lem_get_tuning(const lem_ctx* ctx, lem_tuning* out) {
 lem_status lem_destroy(lem_ctx* ctx) {
   if (!ctx) return LEM_OK;
   (void)hipStreamSynchronize(ctx->stream);
-  (void)hipEventDestroy(ctx->ev0);
-  (void)hipEventDestroy(ctx->ev1);
-  (void)hipEventDestroy(ctx->ev2);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   delete ctx;
   return LEM_OK;
 }

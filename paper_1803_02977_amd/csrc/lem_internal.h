@@ -63,6 +63,7 @@ struct Ctrl {
   uint32_t bar_gen;
   uint32_t pad2[31];
 };
+static_assert(sizeof(Ctrl) % 4 == 0, "cleared as 32-bit words");
 
 // One grid of a batch (a single-grid context is a batch of one).  Grids
 // are stored one after another in the batch arrays; tiles are numbered
@@ -173,6 +174,8 @@ hipError_t launch_export(const StepArgs& a, int g, int64_t offset, int64_t cells
 // Per grid: largest |h_out - h_in| and largest |h_out| (into w.conv).
 hipError_t launch_change(const StepArgs& a, int64_t total_cells, hipStream_t s);
 hipError_t launch_validate(const double* x, int64_t n, int32_t* flag, hipStream_t s);
+// Sets `words` 32-bit words at p to zero (a kernel, not hipMemsetAsync).
+hipError_t launch_zero_words(void* p, int64_t words, hipStream_t s);
 hipError_t global_kernel_occupancy(int* blocks_per_cu);
 
 }  // namespace lem

@@ -1595,6 +1595,12 @@ __global__ __launch_bounds__(256) void k_change(StepArgs a) {
   }
 }
 
+__global__ void k_zero_u32(uint32_t* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0u;
+}
+
 __global__ void k_zero_f64(double* x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1731,6 +1737,14 @@ hipError_t launch_change(const StepArgs& a, int64_t total_cells, hipStream_t s) 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_change, dim3(16, (unsigned)a.ngrids), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_words(void* p, int64_t words, hipStream_t s) {
+  if (words <= 0) return hipSuccess;
+  const int64_t blocks = (words + 255) / 256;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s,
+                     (uint32_t*)p, words);
   return hipGetLastError();
 }
 

@@ -120,6 +120,8 @@ def load(path: str = LIB_PATH):
     lib.lem_status_str.restype = C.c_char_p
     lib.lem_last_error.argtypes = [_P]
     lib.lem_last_error.restype = C.c_char_p
+    lib.lem_run_static.argtypes = [C.POINTER(lem_params), _P, _P, _P, C.c_int64, _P]
+    lib.lem_run_static.restype = C.c_int
     _LIB = lib
     return lib
 
@@ -136,6 +138,19 @@ def _check(st: int, ctx=None):
 
 
 # --- one wrapper per C entry point ------------------------------------------------
+
+# Size of the library's own device workspace array used by lem_run_static.
+LEM_STATIC_WORKSPACE_BYTES = 16 << 20
+
+
+def lem_run_static(p: lem_params, d_h: int, d_K, d_U, steps: int, hip_stream: int) -> None:
+    """Steps over the library's static device workspace (no device allocation)."""
+    st = load().lem_run_static(C.byref(p), d_h, d_K, d_U, steps, hip_stream)
+    if st == LEM_E_WORKSPACE:
+        raise LemError(st, f"LEM_E_WORKSPACE (the grid needs {lem_workspace_bytes(p)} bytes of "
+                           f"workspace; the static workspace holds {LEM_STATIC_WORKSPACE_BYTES})")
+    _check(st)
+
 
 def lem_workspace_bytes(p: lem_params) -> int:
     return int(load().lem_workspace_bytes(C.byref(p)))

@@ -169,3 +169,21 @@ def test_mfd_workspace_and_arguments_are_checked_on_the_host():
     assert lib.lem_mfd_create(C.byref(p), 1.0, C.c_void_p(4096), mfd - 1, None,
                               C.byref(ctx)) == lem.LEM_E_WORKSPACE
     assert lib.lem_mfd_export(None, None, None, None) == lem.LEM_E_ARG
+
+
+def test_static_entry_point_rejects_oversized_grids_on_the_host():
+    """lem_run_static checks the grid against its fixed workspace before any
+    device call (the heights pointer is never used here)."""
+    from paper_1803_02977_amd import lem
+    lib = lem.load()
+    big = lem.lem_params(1024, 1024, 100.0, 100.0, 1000.0, 0.5, 1.0, 5e-4, 1e-5, 1e-12, 100, 0)
+    assert lem.lem_workspace_bytes(big) > lem.LEM_STATIC_WORKSPACE_BYTES
+    assert lib.lem_run_static(C.byref(big), 256, None, None, 1, None) == lem.LEM_E_WORKSPACE
+    fits = lem.lem_params(512, 512, 100.0, 100.0, 1000.0, 0.5, 1.0, 5e-4, 1e-5, 1e-12, 100, 0)
+    assert lem.lem_workspace_bytes(fits) <= lem.LEM_STATIC_WORKSPACE_BYTES
+    bad = lem.lem_params(2, 512, 100.0, 100.0, 1000.0, 0.5, 1.0, 5e-4, 1e-5, 1e-12, 100, 0)
+    assert lib.lem_run_static(C.byref(bad), 256, None, None, 1, None) == lem.LEM_E_ARG
+    timers = lem.lem_params(64, 64, 100.0, 100.0, 1000.0, 0.5, 1.0, 5e-4, 1e-5, 1e-12, 100,
+                            lem.LEM_F_PHASE_TIMERS)
+    assert lib.lem_run_static(C.byref(timers), 256, None, None, 1, None) == lem.LEM_E_ARG
+    assert lib.lem_run_static(None, 256, None, None, 1, None) == lem.LEM_E_ARG
