@@ -37,9 +37,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 #  - k_global_levels: the 65 B formulation minus the receiver sweep's h read
 #    and the code/mask writes (55 B), for each cell of a tree that crosses a
 #    tile edge.
+#  - k_chunk_trees: the same trees with the queue, counts and queue-order
+#    heights in LDS: read the donor mask and h, write h (1 + 8 + 8 B per
+#    crossing-tree cell; +8 per K or U field read).
 ALG_BYTES_STEP = 65
 ALG_BYTES_TILE = 17
 ALG_BYTES_GLOBAL = 55
+ALG_BYTES_CHUNK = 17
 ALG_BYTES_FIELD = 8
 
 
@@ -187,13 +191,20 @@ def bench_batch(args):
     stt = bt.stats()
     bt.close()
     tile_ms = stt.kernel_ms[0] / steps
-    level_ms = stt.kernel_ms[1] / steps
+    chunk_ms = stt.kernel_ms[2] / steps
+    level_ms = (stt.kernel_ms[1] - stt.kernel_ms[2]) / steps
     cross = stt.crossing_run / steps
-    if level_ms >= tile_ms:
-        roof = {"bound": "hbm", "kernel": "k_grid_levels" if mode == 2 else "k_global_levels",
+    level_name = "k_grid_levels" if mode == 2 else "k_global_levels"
+    if level_ms >= max(tile_ms, chunk_ms):
+        roof = {"bound": "hbm", "kernel": level_name,
                 "achieved": ALG_BYTES_GLOBAL * cross / (level_ms * 1e-3) / 1e9,
                 "alg_bytes": f"{ALG_BYTES_GLOBAL} B per crossing-tree cell",
                 "avg_launch_ms": level_ms}
+    elif chunk_ms >= tile_ms:
+        roof = {"bound": "hbm", "kernel": "k_chunk_trees",
+                "achieved": ALG_BYTES_CHUNK * cross / (chunk_ms * 1e-3) / 1e9,
+                "alg_bytes": f"{ALG_BYTES_CHUNK} B per crossing-tree cell",
+                "avg_launch_ms": chunk_ms}
     else:
         roof = {"bound": "hbm", "kernel": "k_tile_step",
                 "achieved": ALG_BYTES_TILE * cells / (tile_ms * 1e-3) / 1e9,
@@ -234,8 +245,8 @@ def bench_batch(args):
                                  "one after another on the same GPU"} if one_value else None,
         "batch_speedup_vs_grid_by_grid": round(value / one_value, 2) if one_value else None,
         "level_pass": "one workgroup per grid" if mode == 2 else "one device-wide pass",
-        "kernel_ms_per_step": {"k_tile_step": tile_ms,
-                               ("k_grid_levels" if mode == 2 else "k_global_levels"): level_ms},
+        "kernel_ms_per_step": {"k_tile_step": tile_ms, "k_chunk_trees": chunk_ms,
+                               level_name: level_ms},
         "roofline": roof,
     }
     if not args.no_cpu:
@@ -664,7 +675,8 @@ def main():
     tsolver_crossing = st.crossing_run / steps
     tsolver.close()
     tile_ms = st.kernel_ms[0] / steps
-    global_ms = st.kernel_ms[1] / steps
+    chunk_ms = st.kernel_ms[2] / steps
+    global_ms = (st.kernel_ms[1] - st.kernel_ms[2]) / steps
     crossing = tsolver_crossing
 
     cells = w.cells
@@ -672,9 +684,13 @@ def main():
     fields = (Kt is not None)
     alg_step = ALG_BYTES_STEP + ALG_BYTES_FIELD * fields
     alg_tile = ALG_BYTES_TILE + ALG_BYTES_FIELD * fields
-    if tile_ms >= global_ms:
+    if tile_ms >= max(global_ms, chunk_ms):
         kname, kms, kbytes = "k_tile_step", tile_ms, alg_tile * cells
         per_unit = f"{alg_tile} B per cell"
+    elif chunk_ms >= global_ms:
+        alg_chunk = ALG_BYTES_CHUNK + ALG_BYTES_FIELD * fields
+        kname, kms, kbytes = "k_chunk_trees", chunk_ms, alg_chunk * crossing
+        per_unit = f"{alg_chunk} B per crossing-tree cell"
     else:
         kname, kms, kbytes = "k_global_levels", global_ms, ALG_BYTES_GLOBAL * crossing
         per_unit = f"{ALG_BYTES_GLOBAL} B per crossing-tree cell"
@@ -718,10 +734,13 @@ def main():
         "levels": {"min": int(levels.min()), "max": int(levels.max()),
                    "mean": float(levels.mean()), "per_step": [int(x) for x in levels],
                    "last_step_level_sizes": level_sizes} if len(levels) else None,
-        "kernel_ms_per_step": {"k_tile_step": tile_ms, "k_global_levels": global_ms},
-        "global_phase_ms_per_step": {"order": st.phase_ms[1] / steps,
-                                     "accumulate": st.phase_ms[2] / steps,
-                                     "erode": st.phase_ms[3] / steps},
+        "kernel_ms_per_step": {"k_tile_step": tile_ms, "k_chunk_trees": chunk_ms,
+                               "k_global_levels": global_ms},
+        # Device clock of the first workgroup of the crossing-tree work (the
+        # chunk stage's when it runs): its time in each phase per step.
+        "crossing_wg0_phase_ms_per_step": {"order": st.phase_ms[1] / steps,
+                                           "accumulate": st.phase_ms[2] / steps,
+                                           "erode": st.phase_ms[3] / steps},
         "crossing_cells_per_step": crossing,
         "crossing_frac": round(crossing / cells, 4),
     }

@@ -100,10 +100,14 @@ typedef struct lem_stats_t {
                               heights of trees inside one tile), [1] level
                               ordering, [2] accumulation, [3] uplift+erosion of the
                               trees that cross tile edges (1-3 by the device clock
-                              inside the global level kernel)                      */
-  double kernel_ms[2];     /* HIP-event ms of the last run with LEM_F_PHASE_TIMERS,
+                              of one workgroup: the chunk stage's first workgroup
+                              when that stage runs, else the global level kernel's
+                              first)                                               */
+  double kernel_ms[3];     /* HIP-event ms of the last run with LEM_F_PHASE_TIMERS,
                               summed over its steps: [0] the tile pass, [1] the
-                              global level pass                                    */
+                              trees that cross tile edges (chunk stage and level
+                              pass together), [2] the chunk stage alone (0 when it
+                              is off)                                              */
   int64_t crossing_last;   /* cells of the most recent step whose drainage tree
                               crosses a tile edge (resolved by the global pass)     */
   int64_t crossing_run;    /* the same, summed over the steps of the last run       */
@@ -260,7 +264,13 @@ lem_status lem_level_history(lem_ctx* ctx, int32_t* h_levels, int64_t cap, int64
 lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out);
 
 /* Launch tuning of a context (performance only; results are identical for
- * every setting).  global_workgroups: workgroups of 1024 threads in the
+ * every setting).  chunk_pass: LEM_CHUNKS_ON (or 0, the default) runs a
+ * first stage for the trees that cross tile edges: workgroups take chunks
+ * of chunk_roots of their roots (1..256; 0 = default 128) from a device work
+ * counter and finish those trees in on-chip memory with workgroup barriers
+ * only; chunks whose trees need more room go on to the level pass below.
+ * LEM_CHUNKS_OFF leaves every such tree to the level pass.
+ * global_workgroups: workgroups of 1024 threads in the
  * cooperative level kernel for trees that cross tile edges (0 = default,
  * clamped to what the device can keep resident); tail_level: levels with
  * fewer cells than this are handled by one workgroup without grid-wide
@@ -275,11 +285,16 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out);
 #define LEM_LEVELS_AUTO 0
 #define LEM_LEVELS_GLOBAL 1
 #define LEM_LEVELS_PER_GRID 2
+#define LEM_CHUNKS_AUTO 0
+#define LEM_CHUNKS_ON 1
+#define LEM_CHUNKS_OFF 2
 typedef struct lem_tuning {
   int32_t global_workgroups;
   int32_t tail_level;
   int32_t level_pass;
   int32_t level_threads;
+  int32_t chunk_pass;
+  int32_t chunk_roots;
 } lem_tuning;
 
 /* Applies *t to later runs on ctx.  LEM_E_ARG for negative fields. */

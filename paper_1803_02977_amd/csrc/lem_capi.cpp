@@ -31,6 +31,9 @@ struct lem_ctx {
   int level_pass;                   // LEM_LEVELS_* as set (0 = automatic)
   bool pergrid;                     // level pass in use: one workgroup per grid
   int level_threads;                // threads per workgroup of that pass (0 = automatic)
+  bool chunked;                     // chunk stage before the level pass
+  int chunk_roots;                  // roots per chunk of that stage
+  int chunk_grid;                   // workgroups of that stage (resident on the device)
   int device;
   double tick_khz;                  // device wall-clock rate
   int64_t steps_done;
@@ -38,7 +41,8 @@ struct lem_ctx {
   bool has_routing;
   double route_ms;                  // accumulated with LEM_F_PHASE_TIMERS
   double order_ms;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;  // LEM_F_PHASE_TIMERS only
+  double chunk_ms;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;  // PHASE_TIMERS only
   std::string err;
 };
 
@@ -160,6 +164,8 @@ lem::StepArgs make_args(const lem_ctx* ctx, const double* d_K, const double* d_U
   a.w = ctx->w;
   a.tail_level = ctx->tail_level;
   a.pergrid = ctx->pergrid ? 1 : 0;
+  a.chunked = (ctx->chunked && !ctx->mfd) ? 1 : 0;
+  a.chunk_roots = ctx->chunk_roots;
   a.mfd = ctx->mfd ? 1 : 0;
   a.mfd_p = ctx->mfd_p;
   return a;
@@ -211,19 +217,26 @@ lem_status step(lem_ctx* ctx, lem::StepArgs& a, bool timers) {
                           : lem::launch_tile_step(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, ctx->mfd ? "routing launch" : "tile launch");
   if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
+  if (a.chunked) {
+    e = lem::launch_chunk_trees(a, ctx->chunk_grid, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "chunk-stage launch");
+  }
+  if (timers) (void)hipEventRecord(ctx->ev2, ctx->stream);
   e = ctx->mfd      ? lem::launch_mfd_levels(a, ctx->grid, ctx->stream)
       : ctx->pergrid ? lem::launch_grid_levels(a, pergrid_threads(ctx), ctx->stream)
                      : lem::launch_global_levels(a, ctx->grid, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "level-pass launch");
   if (timers) {
-    (void)hipEventRecord(ctx->ev2, ctx->stream);
-    e = hipEventSynchronize(ctx->ev2);
+    (void)hipEventRecord(ctx->ev3, ctx->stream);
+    e = hipEventSynchronize(ctx->ev3);
     if (e != hipSuccess) return hip_fail(ctx, e, "timer event");
-    float ms0 = 0.f, ms1 = 0.f;
+    float ms0 = 0.f, ms1 = 0.f, ms2 = 0.f;
     (void)hipEventElapsedTime(&ms0, ctx->ev0, ctx->ev1);
-    (void)hipEventElapsedTime(&ms1, ctx->ev1, ctx->ev2);
+    (void)hipEventElapsedTime(&ms1, ctx->ev1, ctx->ev3);
+    (void)hipEventElapsedTime(&ms2, ctx->ev1, ctx->ev2);
     ctx->route_ms += ms0;
     ctx->order_ms += ms1;
+    ctx->chunk_ms += ms2;
   }
   return LEM_OK;
 }
@@ -262,6 +275,7 @@ lem_status run_impl(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode, const dou
   const bool timers = (ctx->flags & LEM_F_PHASE_TIMERS) != 0;
   ctx->route_ms = 0.0;
   ctx->order_ms = 0.0;
+  ctx->chunk_ms = 0.0;
   // Steps alternate between the caller's buffer and the workspace copy, so a
   // tile never reads a neighbour's already-updated halo.
   for (int64_t s = 0; s < steps; ++s) {
@@ -292,9 +306,10 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
   ctx->tiles.resize(ctx->ntiles);
   for (int32_t t = 0; t < ctx->ntiles; ++t) ctx->tiles[t] = t;
   hipError_t e = hipGetDevice(&ctx->device);
-  int cus = 0, per_cu = 0, rate = 0;
+  int cus = 0, per_cu = 0, rate = 0, per_cu_chunk = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
   if (e == hipSuccess) e = lem::global_kernel_occupancy(&per_cu);
+  if (e == hipSuccess) e = lem::chunk_kernel_occupancy(&per_cu_chunk);
   if (e == hipSuccess && ctx->mfd) {
     int per_cu_mfd = 0;
     e = lem::mfd_kernel_occupancy(&per_cu_mfd);
@@ -305,8 +320,18 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev2);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->ev3);
   }
-  if (e != hipSuccess || per_cu < 1) return LEM_E_HIP;
+  if (e != hipSuccess || per_cu < 1 || per_cu_chunk < 1) return LEM_E_HIP;
+  // Chunk stage: every resident workgroup, but no more than one per 4096
+  // cells (small grids have few crossing roots).
+  {
+    const int64_t cap = (int64_t)cus * per_cu_chunk;
+    const int64_t want = (ctx->cells + 4095) / 4096;
+    ctx->chunk_grid = (int)(want < cap ? (want < 1 ? 1 : want) : cap);
+  }
+  ctx->chunked = !ctx->mfd;
+  ctx->chunk_roots = lem::kChunkRootsDefault;
   // The global level kernel uses at most kGlobalMaxWGs resident workgroups:
   // a grid-wide barrier's cost grows with the number of participants.
   ctx->grid_max = cus * per_cu;
@@ -472,7 +497,7 @@ lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
   e = lem::launch_begin_run(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "begin-run launch");
   const bool timers = (ctx->flags & LEM_F_PHASE_TIMERS) != 0;
-  ctx->route_ms = ctx->order_ms = 0.0;
+  ctx->route_ms = ctx->order_ms = ctx->chunk_ms = 0.0;
   std::vector<double> conv(2 * (size_t)ng);
   int64_t s = 0;
   double* cur = d_h;  // buffer holding the latest heights
@@ -693,6 +718,7 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out) {
   out->phase_ms[0] = ctx->route_ms;
   out->kernel_ms[0] = ctx->route_ms;
   out->kernel_ms[1] = ctx->order_ms;
+  out->kernel_ms[2] = ctx->chunk_ms;
   out->crossing_last = ct.dirty_total;
   out->crossing_run = ct.crossing_run;
   for (int k = 1; k < 4; ++k)
@@ -703,9 +729,14 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out) {
 lem_status lem_set_tuning(lem_ctx* ctx, const lem_tuning* t) {
   if (!ctx || !t) return LEM_E_ARG;
   if (t->global_workgroups < 0 || t->tail_level < 0 || t->level_pass < 0 || t->level_pass > 2 ||
-      (t->level_threads != 0 && t->level_threads != 256 && t->level_threads != lem::kBlock))
+      (t->level_threads != 0 && t->level_threads != 256 && t->level_threads != lem::kBlock) ||
+      t->chunk_pass < 0 || t->chunk_pass > 2 || t->chunk_roots < 0 ||
+      t->chunk_roots > lem::kChunkMaxRoots)
     return fail(ctx, LEM_E_ARG,
-                "tuning fields must be >= 0 (level_pass 0, 1 or 2; level_threads 0, 256 or 1024)");
+                "tuning fields must be >= 0 (level_pass 0, 1 or 2; level_threads 0, 256 or 1024; "
+                "chunk_pass 0, 1 or 2; chunk_roots at most 256)");
+  ctx->chunked = !ctx->mfd && t->chunk_pass != LEM_CHUNKS_OFF;
+  ctx->chunk_roots = t->chunk_roots ? t->chunk_roots : lem::kChunkRootsDefault;
   ctx->level_threads = t->level_threads;
   int g = t->global_workgroups ? t->global_workgroups : lem::kGlobalMaxWGs;
   ctx->grid = g < ctx->grid_max ? g : ctx->grid_max;
@@ -722,6 +753,8 @@ lem_status lem_get_tuning(const lem_ctx* ctx, lem_tuning* out) {
   out->tail_level = ctx->tail_level;
   out->level_pass = ctx->pergrid ? LEM_LEVELS_PER_GRID : LEM_LEVELS_GLOBAL;
   out->level_threads = pergrid_threads(ctx);
+  out->chunk_pass = ctx->chunked ? LEM_CHUNKS_ON : LEM_CHUNKS_OFF;
+  out->chunk_roots = ctx->chunk_roots;
   return LEM_OK;
 }
 
@@ -731,6 +764,7 @@ lem_status lem_destroy(lem_ctx* ctx) {
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
+  if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
   delete ctx;
   return LEM_OK;
 }

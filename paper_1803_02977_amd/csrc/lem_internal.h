@@ -42,6 +42,20 @@ constexpr int kExpandItems = 4;
 constexpr int kGlobalMaxWGs = 192;
 constexpr int kTailLevel = 8192;  // default; lem_set_tuning changes it per context
 
+// Crossing trees, first stage: workgroups of kChunkThreads take chunks of
+// consecutive crossing roots from a device work counter and finish their
+// trees in LDS (at most kChunkCap cells and kChunkLevCap levels per chunk;
+// a chunk that needs more is handed to the level pass).  Roots per chunk:
+// 1..kChunkMaxRoots (kChunkMaxRoots <= kChunkLevCap and <= kChunkCap / 2,
+// so the roots handed on fit in the queue behind the chunk roots).
+constexpr int kChunkThreads = 256;
+constexpr int kChunkCap = 2048;
+constexpr int kChunkLevCap = 256;
+constexpr int kChunkMaxRoots = 256;
+constexpr int kChunkRootsDefault = 128;
+static_assert(kChunkMaxRoots <= kChunkLevCap && 2 * kChunkMaxRoots <= kChunkCap,
+              "roots handed on must fit behind the chunk roots");
+
 // Device-side control block (one per context, in the workspace).
 struct Ctrl {
   int32_t status;          // lem_status of device-detected errors (0 = OK)
@@ -56,7 +70,12 @@ struct Ctrl {
   uint64_t ticks[4];       // device wall-clock ticks per phase (accumulated)
   int32_t tail_lo, tail_hi, tail_L, tail_done;  // state handed back by a one-workgroup run
   int64_t crossing_run;    // crossing-tree cells summed over the current run
-  int32_t pad[38];
+  int64_t chunk_total;     // cells finished by the chunk stage (current step)
+  int32_t chunk_next;      // work counter of the chunk stage (current step)
+  int32_t ovf_count;       // roots the chunk stage handed to the level pass
+  int32_t chunk_nl;        // deepest chunk's levels (current step)
+  int32_t glob_total;      // cells ordered by the global level pass (current step)
+  int32_t pad[32];
   // Grid-wide barrier of the global level kernel (own cache lines).
   uint32_t bar_count;
   uint32_t pad1[31];
@@ -148,6 +167,8 @@ struct StepArgs {
   int32_t tail_level;    // levels smaller than this run in one workgroup
   int32_t pergrid;       // crossing trees: one workgroup per grid (else the global pass)
   int32_t mfd;           // multiple flow directions (single grid)
+  int32_t chunked;       // crossing trees go through the chunk stage first
+  int32_t chunk_roots;   // roots per chunk of that stage
   int32_t pad2;
   double mfd_p;          // exponent of the slope in the flow shares
 };
@@ -160,6 +181,9 @@ hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user_rcode, hi
 hipError_t launch_tile_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s);
+// Chunk stage of the crossing trees (before the level pass) on `grid` workgroups.
+hipError_t launch_chunk_trees(const StepArgs& a, int grid, hipStream_t s);
+hipError_t chunk_kernel_occupancy(int* blocks_per_cu);
 // Multiple flow directions: routing (weight sums, receiver counters, roots),
 // then levels, areas and heights in one cooperative launch of `grid`
 // workgroups.

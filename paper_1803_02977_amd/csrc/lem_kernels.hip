@@ -660,12 +660,15 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
     if (a.export_routing && !a.fixed) w.rcode[c] = (uint8_t)code;
   }
   atomicAdd(&s_clean, my_clean);
+  // Roots go to the grid's own queue slice for the per-grid level pass, to
+  // the one shared queue otherwise (the chunk stage takes them from there).
+  const bool pergrid_roots = a.pergrid && !a.chunked;
   int tot;
   const int pre = block_exclusive_scan<kTileThreads>(my_roots, wsum, &tot);
   if (tid == 0)
-    s_base = tot ? atomicAdd(a.pergrid ? &w.gcnt[gi] : &w.lcnt[0], tot) : 0;
+    s_base = tot ? atomicAdd(pergrid_roots ? &w.gcnt[gi] : &w.lcnt[0], tot) : 0;
   __syncthreads();
-  int pos = (a.pergrid ? (int)off : 0) + s_base + pre;
+  int pos = (pergrid_roots ? (int)off : 0) + s_base + pre;
   while (root_bits) {
     const int t = __ffs(root_bits) - 1;
     root_bits &= root_bits - 1;
@@ -818,6 +821,40 @@ __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32
   }
 }
 
+// End of a step's crossing-tree work (one thread): the step's level count
+// and statistics from the tile pass, the chunk stage (when it ran) and the
+// level pass that ran last (`cross_total` cells in `nl_cross` levels, of
+// which `glob_total` sit in the global queue for the routing export), then
+// the per-step counters are cleared for the next step.
+__device__ void finish_step(const StepArgs& a, Ctrl* ct, int64_t cross_total, int32_t nl_cross,
+                            int32_t glob_total) {
+  const Work& w = a.w;
+  int64_t total = cross_total;
+  if (a.chunked) {
+    total += ct->chunk_total;
+    nl_cross = nl_cross > ct->chunk_nl ? nl_cross : ct->chunk_nl;
+  }
+  const int32_t clean = ct->clean;
+  const int32_t nl_clean = clean ? ct->clean_maxdepth + 1 : 0;
+  const int32_t nl = nl_clean > nl_cross ? nl_clean : nl_cross;
+  ct->nlevels = nl;
+  ct->dirty_total = (int32_t)total;
+  ct->glob_total = glob_total;
+  ct->crossing_run += total;
+  if (nl > ct->max_nlevels) ct->max_nlevels = nl;
+  if (a.step < kHistCap) w.hist[a.step] = nl;
+  ct->steps = a.step + 1;
+  if ((int64_t)clean + total != (int64_t)a.n) atomicMax(&ct->status, 5);
+  ct->clean = 0;
+  ct->clean_maxdepth = 0;
+  ct->chunk_total = 0;
+  ct->chunk_nl = 0;
+  ct->chunk_next = 0;
+  ct->ovf_count = 0;
+  w.lcnt[0] = 0;
+  w.lcnt[1] = 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
   __shared__ uint64_t wsum64[4 * kBlock / 64 + 4];
   __shared__ int s_base;
@@ -833,6 +870,26 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
   // lcnt[L+1]; the workgroup-0 lead clears lcnt[L+2] while level L runs
   // (nobody else touches it then) and records lev[L+1].
   int32_t lo = 0, hi = load_acquire(&w.lcnt[0]), L = 0;
+  if (a.chunked) {
+    // The chunk stage finished most trees; the roots of the chunks it could
+    // not hold were staged behind the chunk roots.  Move them to the front.
+    const int32_t novf = ct->ovf_count;
+    if (novf == 0) {
+      if (lead) {
+        ct->dirty_nlevels = 0;
+        finish_step(a, ct, 0, 0, 0);
+      }
+      return;
+    }
+    for (int64_t j = (int64_t)wg * kBlock + tid; j < novf; j += (int64_t)nwg * kBlock) {
+      w.q[j] = w.q[hi + j];
+      w.gq[j] = w.gq[hi + j];
+      w.kq[j] = w.kq[hi + j];
+      w.par[j] = -1;
+    }
+    grid_barrier(ct);
+    hi = novf;
+  }
   bool done = false;
   if (lead) w.lev[0] = 0;
   while (!done) {
@@ -949,23 +1006,9 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
   }
 
   if (lead) {
-    const int32_t clean = ct->clean;
-    const int32_t nl_clean = clean ? ct->clean_maxdepth + 1 : 0;
     const int32_t nl_cross = total ? nlevels : 0;
-    const int32_t nl = nl_clean > nl_cross ? nl_clean : nl_cross;
-    ct->nlevels = nl;
-    ct->dirty_total = total;
     ct->dirty_nlevels = nl_cross;
-    ct->crossing_run += total;
-    if (nl > ct->max_nlevels) ct->max_nlevels = nl;
-    if (a.step < kHistCap) w.hist[a.step] = nl;
-    ct->steps = a.step + 1;
-    if ((int64_t)clean + total != (int64_t)a.n) atomicMax(&ct->status, 5);
-    // Reset the per-step counters for the next step's tile pass.
-    ct->clean = 0;
-    ct->clean_maxdepth = 0;
-    w.lcnt[0] = 0;
-    w.lcnt[1] = 0;
+    finish_step(a, ct, total, nl_cross, total);
     if (a.timers) {
       const uint64_t t3 = wall_clock64();
       ct->ticks[1] += t1 - t0;
@@ -1055,6 +1098,16 @@ __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
   }
   const int32_t base = (int32_t)G.offset;
   int32_t* lev = w.lev + G.offset + 2 * (int64_t)gi;
+  if (a.chunked) {
+    // Roots of the chunks the chunk stage could not hold, staged in fc/mq.
+    for (int32_t j = tid; j < nroots; j += NT) {
+      w.q[base + j] = w.fc[base + j];
+      w.kq[base + j] = w.mq[base + j];
+      w.gq[base + j] = (uint16_t)gi;
+      w.par[base + j] = -1;
+    }
+    __syncthreads();
+  }
   int32_t lo = base, hi = base + nroots, L = 0;
   if (tid == 0) {
     lev[0] = lo;
@@ -1130,24 +1183,200 @@ __global__ __launch_bounds__(1024) void k_grid_levels_finish(StepArgs a) {
   }
   if (threadIdx.x == 0) {
     Ctrl* ct = w.ctrl;
-    const int32_t clean = ct->clean;
-    const int32_t nl_clean = clean ? ct->clean_maxdepth + 1 : 0;
-    const int32_t nl_cross = smax[0];
-    const int64_t total = ssum[0];
-    const int32_t nl = nl_clean > nl_cross ? nl_clean : nl_cross;
-    ct->nlevels = nl;
-    ct->dirty_total = (int32_t)total;
-    ct->dirty_nlevels = nl_cross;
-    ct->crossing_run += total;
-    if (nl > ct->max_nlevels) ct->max_nlevels = nl;
-    if (a.step < kHistCap) w.hist[a.step] = nl;
-    ct->steps = a.step + 1;
-    if ((int64_t)clean + total != (int64_t)a.n) atomicMax(&ct->status, 5);
-    ct->clean = 0;
-    ct->clean_maxdepth = 0;
+    ct->dirty_nlevels = smax[0];
+    finish_step(a, ct, ssum[0], smax[0], 0);
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Crossing trees, chunk stage.  The tile pass queued the root of every tree
+// that crosses a tile edge (q[0, lcnt[0]), tile by tile).  Such trees are
+// small on the paper's workloads (about a dozen cells on average), so a
+// workgroup takes a chunk of consecutive roots from a device work counter
+// and carries out Steps 4-7 for their whole trees in LDS: breadth-first
+// levels (Algorithm 3; each level's cells gather their donor masks and
+// starting heights from HBM), counts from the deepest level up
+// (Algorithm 4; each cell adds its count to its receiver's), then uplift
+// and the implicit update from the roots outward (Algorithms 5-6).  Only
+// workgroup barriers separate levels, so chunks proceed independently.  A
+// chunk whose trees need more than kChunkCap cells or kChunkLevCap levels
+// writes nothing; its roots are staged for the level pass that follows
+// (the global pass: behind the chunk roots in q/gq/kq; the per-grid pass:
+// in the grid's slice of fc/mq), which orders those trees as before.
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_trees(StepArgs a) {
+  constexpr int NT = kChunkThreads;
+  __shared__ int32_t s_cell[kChunkCap];      // cell of each entry, level-major
+  __shared__ double s_h[kChunkCap];          // uplifted start height, then new height
+  __shared__ uint16_t s_par[kChunkCap];      // entry of the receiver
+  __shared__ uint16_t s_grid[kChunkCap];     // grid of the entry
+  __shared__ uint32_t s_cnt[kChunkCap / 2];  // upstream counts, two 16-bit halves a word
+  __shared__ uint8_t s_k[kChunkCap];         // receiver code (roots: kSink or kBase)
+  __shared__ uint16_t s_lev[kChunkLevCap + 2];
+  __shared__ int wsum[NT / 64];
+  __shared__ int s_chunk, s_slot;
+  static_assert(kChunkCap < 65536, "16-bit entries and counts");
+
+  const Work w = a.w;
+  Ctrl* ct = w.ctrl;
+  const int tid = threadIdx.x;
+  const int32_t nroots = w.lcnt[0];  // final: written by the tile pass
+  const int R = a.chunk_roots;
+  const bool multi = a.ngrids > 1;
+  int64_t my_total = 0;
+  int32_t my_nl = 0;
+  uint64_t tk[3] = {0, 0, 0};
+  const bool clock = a.timers && blockIdx.x == 0 && tid == 0;
+
+  for (;;) {
+    if (tid == 0) s_chunk = atomicAdd(&ct->chunk_next, 1);
+    __syncthreads();
+    const int64_t r0 = (int64_t)s_chunk * R;
+    if (r0 >= nroots) break;
+    const int nr = (int)(nroots - r0 < R ? nroots - r0 : R);
+    uint64_t t0 = clock ? wall_clock64() : 0;
+
+    // Level 0: the chunk's roots.  Every count starts at 1 (the cell itself).
+    for (int j = tid; j < kChunkCap / 2; j += NT) s_cnt[j] = 0x00010001u;
+    for (int j = tid; j < nr; j += NT) {
+      s_cell[j] = w.q[r0 + j];
+      s_k[j] = w.kq[r0 + j];
+      s_grid[j] = multi ? w.gq[r0 + j] : 0;
+    }
+    if (tid == 0) {
+      s_lev[0] = 0;
+      s_lev[1] = (uint16_t)nr;
+    }
+    __syncthreads();
+
+    // Step 4: breadth-first levels.  Each entry of level L gathers its donor
+    // mask and its height (uplifted unless it is a perimeter root) and
+    // appends its donors, in the order of the entries.
+    int lo = 0, hi = nr, next = nr, L = 0;
+    bool ovf = false;
+    for (;;) {
+      for (int base = lo; base < hi; base += NT) {
+        const int i = base + tid;
+        uint32_t m = 0;
+        int32_t c = 0;
+        int g = 0;
+        if (i < hi) {
+          c = s_cell[i];
+          g = s_grid[i];
+          m = w.dmask[c];
+          double hv = a.h_in[c];
+          if (s_k[i] != kBase) hv = hv + (a.Uf ? a.Uf[c] * a.grids[g].dt : a.grids[g].udt);
+          s_h[i] = hv;
+        }
+        int tot;
+        const int pre = block_exclusive_scan<NT>(__popc(m), wsum, &tot);
+        if (next + tot > kChunkCap) {  // tot is the same in every thread
+          ovf = true;
+          break;
+        }
+        if (m) {
+          const int nx = a.grids[g].nx;
+          int pos = next + pre;
+          while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1;
+            s_cell[pos] = (int32_t)(c + neighbour_offset(b, nx));
+            s_par[pos] = (uint16_t)i;
+            s_grid[pos] = (uint16_t)g;
+            s_k[pos] = (uint8_t)(7 - b);
+            ++pos;
+          }
+        }
+        next += tot;
+      }
+      if (ovf) break;
+      __syncthreads();
+      if (next == hi) break;
+      if (L + 1 >= kChunkLevCap) {
+        ovf = true;
+        break;
+      }
+      ++L;
+      lo = hi;
+      hi = next;
+      if (tid == 0) s_lev[L + 1] = (uint16_t)hi;
+    }
+    uint64_t t1 = clock ? wall_clock64() : 0;
+
+    if (ovf) {
+      // Hand the chunk's roots to the level pass; nothing of it was written.
+      if (a.pergrid) {
+        for (int j = tid; j < nr; j += NT) {
+          const int gi = multi ? w.gq[r0 + j] : 0;
+          const int64_t o = a.grids[gi].offset;
+          const int32_t k = atomicAdd(&w.gcnt[gi], 1);
+          w.fc[o + k] = w.q[r0 + j];
+          w.mq[o + k] = w.kq[r0 + j];
+        }
+      } else {
+        if (tid == 0) s_slot = atomicAdd(&ct->ovf_count, nr);
+        __syncthreads();
+        const int64_t dst = (int64_t)nroots + s_slot;
+        for (int j = tid; j < nr; j += NT) {
+          w.q[dst + j] = w.q[r0 + j];
+          w.gq[dst + j] = multi ? w.gq[r0 + j] : 0;
+          w.kq[dst + j] = w.kq[r0 + j];
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+
+    // Step 5: counts, deepest level first (a cell's donors are one level deeper).
+    for (int l = L; l >= 1; --l) {
+      for (int i = s_lev[l] + tid; i < s_lev[l + 1]; i += NT) {
+        const uint32_t v = (s_cnt[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
+        const int p = s_par[i];
+        atomicAdd(&s_cnt[p >> 1], v << ((p & 1) * 16));
+      }
+      __syncthreads();
+    }
+    uint64_t t2 = clock ? wall_clock64() : 0;
+
+    // Steps 6-7: roots keep their (uplifted) height; every other level takes
+    // the implicit update towards its receiver's new height.
+    for (int l = 0; l <= L; ++l) {
+      for (int i = s_lev[l] + tid; i < s_lev[l + 1]; i += NT) {
+        const int32_t c = s_cell[i];
+        const uint32_t count = (s_cnt[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
+        double hn = s_h[i];
+        if (l > 0) {
+          const int gi = s_grid[i];
+          const GridDev& G = a.grids[gi];
+          double f, g;
+          erosion_factor(a, G, gi, count, s_k[i], c, &f, &g);
+          hn = eroded_height(G, hn, s_h[s_par[i]], f, g);
+          s_h[i] = hn;
+        }
+        a.h_out[c] = hn;
+        if (a.export_routing) {
+          w.dep_g[c] = l;
+          w.cnt_g[c] = count;
+        }
+      }
+      __syncthreads();
+    }
+    my_total += next;
+    my_nl = my_nl > L + 1 ? my_nl : L + 1;
+    if (clock) {
+      const uint64_t t3 = wall_clock64();
+      tk[0] += t1 - t0;
+      tk[1] += t2 - t1;
+      tk[2] += t3 - t2;
+    }
+  }
+  if (tid == 0) {
+    if (my_total) atomicAdd((unsigned long long*)&ct->chunk_total, (unsigned long long)my_total);
+    if (my_nl) atomicMax(&ct->chunk_nl, my_nl);
+    if (clock)
+      for (int k = 0; k < 3; ++k) ct->ticks[k + 1] += tk[k];
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Multiple flow directions (section "Multiple Flow Directions"): every
@@ -1478,6 +1707,10 @@ __global__ void k_begin_run(StepArgs a) {
     ct->clean = 0;
     ct->clean_maxdepth = 0;
     ct->crossing_run = 0;
+    ct->chunk_total = 0;
+    ct->chunk_next = 0;
+    ct->ovf_count = 0;
+    ct->chunk_nl = 0;
     for (int k = 0; k < 4; ++k) ct->ticks[k] = 0;
     a.w.lcnt[0] = 0;
     a.w.lcnt[1] = 0;
@@ -1512,7 +1745,7 @@ __global__ __launch_bounds__(256) void k_export_cross(StepArgs a) {
   const Work w = a.w;
   const int32_t nlev = w.ctrl->dirty_nlevels;
   // The per-grid level pass writes levels and counts itself.
-  const int32_t total = a.pergrid ? 0 : w.ctrl->dirty_total;
+  const int32_t total = a.pergrid ? 0 : w.ctrl->glob_total;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
     int32_t lo = 0, hi = nlev;  // largest l with lev[l] <= i
@@ -1685,6 +1918,16 @@ hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_grid_levels_finish, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_chunk_trees(const StepArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_trees, dim3((unsigned)grid), dim3(kChunkThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t chunk_kernel_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_chunk_trees,
+                                                      kChunkThreads, 0);
 }
 
 hipError_t launch_mfd_route(const StepArgs& a, hipStream_t s) {

@@ -37,7 +37,7 @@ class lem_params(C.Structure):
 class lem_stats_t(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("last_nlevels", C.c_int64),
                 ("max_nlevels", C.c_int64), ("last_run_steps", C.c_int64),
-                ("phase_ms", C.c_double * 4), ("kernel_ms", C.c_double * 2),
+                ("phase_ms", C.c_double * 4), ("kernel_ms", C.c_double * 3),
                 ("crossing_last", C.c_int64), ("crossing_run", C.c_int64)]
 
 
@@ -49,11 +49,13 @@ class lem_grid(C.Structure):
 
 
 LEM_LEVELS_AUTO, LEM_LEVELS_GLOBAL, LEM_LEVELS_PER_GRID = 0, 1, 2
+LEM_CHUNKS_AUTO, LEM_CHUNKS_ON, LEM_CHUNKS_OFF = 0, 1, 2
 
 
 class lem_tuning(C.Structure):
     _fields_ = [("global_workgroups", C.c_int32), ("tail_level", C.c_int32),
-                ("level_pass", C.c_int32), ("level_threads", C.c_int32)]
+                ("level_pass", C.c_int32), ("level_threads", C.c_int32),
+                ("chunk_pass", C.c_int32), ("chunk_roots", C.c_int32)]
 
 
 class LemError(RuntimeError):
@@ -261,9 +263,15 @@ def _dptr(t):
     return None if t is None else t.data_ptr()
 
 
+def _set_tuning(ctx, *fields):
+    lem_set_tuning(ctx, lem_tuning(*fields))
+    t = lem_get_tuning(ctx)
+    return {name: getattr(t, name) for name, _ in lem_tuning._fields_}
+
+
 def _apply_tuning(obj, cells, tuning):
-    """tuning: None (library defaults), "auto" (tuning.json if present) or
-    a (global_workgroups, tail_level[, level_pass]) tuple."""
+    """tuning: None (library defaults), "auto" (tuning.json if present), a
+    tuple of lem_tuning fields in order or a dict of them by name."""
     if tuning is None:
         return
     if tuning == "auto":
@@ -271,7 +279,10 @@ def _apply_tuning(obj, cells, tuning):
         tuning = tune.lookup(cells)
         if tuning is None:
             return
-    obj.set_tuning(*tuning)
+    if isinstance(tuning, dict):
+        obj.set_tuning(**tuning)
+    else:
+        obj.set_tuning(*tuning)
 
 
 class Solver:
@@ -345,12 +356,10 @@ class Solver:
     def stats(self) -> lem_stats_t:
         return lem_stats(self.ctx)
 
-    def set_tuning(self, global_workgroups=0, tail_level=0, level_pass=0, level_threads=0):
-        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level, level_pass,
-                                            level_threads))
-        t = lem_get_tuning(self.ctx)
-        return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level,
-                    level_pass=t.level_pass, level_threads=t.level_threads)
+    def set_tuning(self, global_workgroups=0, tail_level=0, level_pass=0, level_threads=0,
+                   chunk_pass=0, chunk_roots=0):
+        return _set_tuning(self.ctx, global_workgroups, tail_level, level_pass, level_threads,
+                           chunk_pass, chunk_roots)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -467,12 +476,10 @@ class Batch:
         offsets, _ = lem_batch_routing(self.ctx, g, None, None, None, nl + 1)
         return dict(rec=rec, depth=depth, count=count, offsets=offsets, nlevels=nl)
 
-    def set_tuning(self, global_workgroups=0, tail_level=0, level_pass=0, level_threads=0):
-        lem_set_tuning(self.ctx, lem_tuning(global_workgroups, tail_level, level_pass,
-                                            level_threads))
-        t = lem_get_tuning(self.ctx)
-        return dict(global_workgroups=t.global_workgroups, tail_level=t.tail_level,
-                    level_pass=t.level_pass, level_threads=t.level_threads)
+    def set_tuning(self, global_workgroups=0, tail_level=0, level_pass=0, level_threads=0,
+                   chunk_pass=0, chunk_roots=0):
+        return _set_tuning(self.ctx, global_workgroups, tail_level, level_pass, level_threads,
+                           chunk_pass, chunk_roots)
 
     def stats(self) -> lem_stats_t:
         return lem_stats(self.ctx)
