@@ -741,6 +741,11 @@ def main():
         "crossing_wg0_phase_ms_per_step": {"order": st.phase_ms[1] / steps,
                                            "accumulate": st.phase_ms[2] / steps,
                                            "erode": st.phase_ms[3] / steps},
+        # Device clock of a tile workgroup, mean over workgroups, per phase.
+        "tile_wg_phase_us_per_step": {
+            k: round(st.tile_phase_ms[i] / steps * 1e3, 3)
+            for i, k in enumerate(("stage", "receivers", "donors_walks", "clean",
+                                   "erosion", "writeback"))},
         "crossing_cells_per_step": crossing,
         "crossing_frac": round(crossing / cells, 4),
     }

@@ -111,6 +111,13 @@ typedef struct lem_stats_t {
   int64_t crossing_last;   /* cells of the most recent step whose drainage tree
                               crosses a tile edge (resolved by the global pass)     */
   int64_t crossing_run;    /* the same, summed over the steps of the last run       */
+  double tile_phase_ms[6]; /* with LEM_F_PHASE_TIMERS: device-clock ms of one tile
+                              workgroup on average, summed over the steps of the last
+                              run, per phase: [0] staging the heights, [1] receivers,
+                              [2] donor masks, walks to the tile-local roots and
+                              counts, [3] trees inside the tile and their depth,
+                              [4] uplift and erosion level by level, [5] write-back
+                              and the crossing roots' queue                         */
 } lem_stats_t;
 
 typedef struct lem_ctx lem_ctx;

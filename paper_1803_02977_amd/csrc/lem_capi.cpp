@@ -34,6 +34,7 @@ struct lem_ctx {
   bool chunked;                     // chunk stage before the level pass
   int chunk_roots;                  // roots per chunk of that stage
   int chunk_grid;                   // workgroups of that stage (resident on the device)
+  int tile_grid;                    // persistent workgroups of the tile pass
   int device;
   double tick_khz;                  // device wall-clock rate
   int64_t steps_done;
@@ -214,7 +215,7 @@ int pergrid_threads(const lem_ctx* ctx) {
 lem_status step(lem_ctx* ctx, lem::StepArgs& a, bool timers) {
   if (timers) (void)hipEventRecord(ctx->ev0, ctx->stream);
   hipError_t e = ctx->mfd ? lem::launch_mfd_route(a, ctx->stream)
-                          : lem::launch_tile_step(a, ctx->stream);
+                          : lem::launch_tile_step(a, ctx->tile_grid, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, ctx->mfd ? "routing launch" : "tile launch");
   if (timers) (void)hipEventRecord(ctx->ev1, ctx->stream);
   if (a.chunked) {
@@ -310,6 +311,8 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
   if (e == hipSuccess) e = lem::global_kernel_occupancy(&per_cu);
   if (e == hipSuccess) e = lem::chunk_kernel_occupancy(&per_cu_chunk);
+  int per_cu_tile = 0;
+  if (e == hipSuccess) e = lem::tile_kernel_occupancy(&per_cu_tile);
   if (e == hipSuccess && ctx->mfd) {
     int per_cu_mfd = 0;
     e = lem::mfd_kernel_occupancy(&per_cu_mfd);
@@ -322,7 +325,9 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev2);
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev3);
   }
-  if (e != hipSuccess || per_cu < 1 || per_cu_chunk < 1) return LEM_E_HIP;
+  if (e != hipSuccess || per_cu < 1 || per_cu_chunk < 1 || per_cu_tile < 1) return LEM_E_HIP;
+  ctx->tile_grid = cus * per_cu_tile;
+  if (ctx->tile_grid >= 8) ctx->tile_grid &= ~7;
   // Chunk stage: every resident workgroup, but no more than one per 4096
   // cells (small grids have few crossing roots).
   {
@@ -723,6 +728,11 @@ lem_status lem_stats(lem_ctx* ctx, lem_stats_t* out) {
   out->crossing_run = ct.crossing_run;
   for (int k = 1; k < 4; ++k)
     out->phase_ms[k] = ctx->tick_khz > 0 ? (double)ct.ticks[k] / ctx->tick_khz : 0.0;
+  for (int k = 0; k < lem::kTilePhases; ++k)
+    out->tile_phase_ms[k] = ctx->tick_khz > 0 && ct.tile_wgs
+                                ? (double)ct.tile_ticks[k] / ctx->tick_khz / (double)ct.tile_wgs *
+                                      (double)ct.steps
+                                : 0.0;
   return LEM_OK;
 }
 

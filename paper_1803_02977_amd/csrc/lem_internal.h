@@ -56,6 +56,9 @@ constexpr int kChunkRootsDefault = 128;
 static_assert(kChunkMaxRoots <= kChunkLevCap && 2 * kChunkMaxRoots <= kChunkCap,
               "roots handed on must fit behind the chunk roots");
 
+// Phases of the tile pass timed with LEM_F_PHASE_TIMERS.
+constexpr int kTilePhases = 6;
+
 // Device-side control block (one per context, in the workspace).
 struct Ctrl {
   int32_t status;          // lem_status of device-detected errors (0 = OK)
@@ -75,7 +78,9 @@ struct Ctrl {
   int32_t ovf_count;       // roots the chunk stage handed to the level pass
   int32_t chunk_nl;        // deepest chunk's levels (current step)
   int32_t glob_total;      // cells ordered by the global level pass (current step)
-  int32_t pad[32];
+  uint64_t tile_ticks[kTilePhases];  // tile pass: device clock per phase, summed over workgroups
+  uint64_t tile_wgs;       // tile-pass workgroups timed
+  int32_t pad[18];
   // Grid-wide barrier of the global level kernel (own cache lines).
   uint32_t bar_count;
   uint32_t pad1[31];
@@ -178,7 +183,9 @@ void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w, bool 
 
 hipError_t launch_begin_run(const StepArgs& a, hipStream_t s);
 hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user_rcode, hipStream_t s);
-hipError_t launch_tile_step(const StepArgs& a, hipStream_t s);
+// Tile pass on at most `grid` persistent workgroups (a multiple of 8).
+hipError_t launch_tile_step(const StepArgs& a, int grid, hipStream_t s);
+hipError_t tile_kernel_occupancy(int* blocks_per_cu);
 hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s);
 // Chunk stage of the crossing trees (before the level pass) on `grid` workgroups.

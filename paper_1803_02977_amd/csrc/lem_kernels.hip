@@ -50,17 +50,7 @@ namespace lem {
 
 namespace {
 
-constexpr int kHW = kTW + 4;  // width of the staged height region
-constexpr int kHH = kTH + 4;
-constexpr int kRW = kTW + 2;  // width of the receiver region (tile + ring)
-constexpr int kRH = kTH + 2;
-constexpr int kTileCells = kTH * kTW;
-constexpr int kCellsPerThread = kTileCells / kTileThreads;
-constexpr int kStageLoads = (kHH * kHW + kTileThreads - 1) / kTileThreads;
 constexpr uint32_t kSpinLimit = 1u << 26;  // about 2 s of polling
-
-static_assert(kTileCells % kTileThreads == 0, "tile cells must split evenly over threads");
-static_assert(kCellsPerThread <= 32, "root bit mask holds 32 cells per thread");
 
 // Row and column offsets of neighbour k, as 2-bit fields (offset + 1) packed
 // in one word so that a run-time k costs a shift and a mask, not branches:
@@ -84,19 +74,21 @@ __device__ __noinline__ double area_power_call(double area, int use_sqrt, double
   return area_power(area, use_sqrt, m);
 }
 
-// Step 2 / Algorithm 1 by the definition: eight quotients (h_c - h_n)/dist
+// Step 2 / Algorithm 1 by the definition: eight quotients (h_c - h_k)/dist
 // in neighbour order, strict ">" against a running maximum starting at 0.
-__device__ __noinline__ uint8_t receiver_code_by_definition(const double* h, int ci, int W,
+// hk are the neighbours' heights in neighbour order k = 0..7.
+__device__ __noinline__ uint8_t receiver_code_by_definition(double hc, double h0, double h1,
+                                                            double h2, double h3, double h4,
+                                                            double h5, double h6, double h7,
                                                             double dx, double dy, double dd) {
-  const double hc = h[ci];
-  const double s0 = (hc - h[ci - W - 1]) / dd;
-  const double s1 = (hc - h[ci - W]) / dy;
-  const double s2 = (hc - h[ci - W + 1]) / dd;
-  const double s3 = (hc - h[ci - 1]) / dx;
-  const double s4 = (hc - h[ci + 1]) / dx;
-  const double s5 = (hc - h[ci + W - 1]) / dd;
-  const double s6 = (hc - h[ci + W]) / dy;
-  const double s7 = (hc - h[ci + W + 1]) / dd;
+  const double s0 = (hc - h0) / dd;
+  const double s1 = (hc - h1) / dy;
+  const double s2 = (hc - h2) / dd;
+  const double s3 = (hc - h3) / dx;
+  const double s4 = (hc - h4) / dx;
+  const double s5 = (hc - h5) / dd;
+  const double s6 = (hc - h6) / dy;
+  const double s7 = (hc - h7) / dd;
   double smax = 0.0;
   uint8_t code = kSink;
   if (s0 > smax) { smax = s0; code = 0; }
@@ -132,12 +124,11 @@ struct RecvConst {
 // Anything else (near-ties across classes, near-ties inside the class, or
 // quotients outside [2^-1000, 2^1000]) is decided by the definition itself.
 template <bool kSquare>
-__device__ __forceinline__ uint8_t receiver_code(const double* h, int ci, int W,
-                                                 const RecvConst& rk) {
-  const double hc = h[ci];
-  const double a0 = hc - h[ci - W - 1], a1 = hc - h[ci - W], a2 = hc - h[ci - W + 1];
-  const double a3 = hc - h[ci - 1], a4 = hc - h[ci + 1];
-  const double a5 = hc - h[ci + W - 1], a6 = hc - h[ci + W], a7 = hc - h[ci + W + 1];
+__device__ __forceinline__ uint8_t receiver_code(double hc, double h0, double h1, double h2,
+                                                 double h3, double h4, double h5, double h6,
+                                                 double h7, const RecvConst& rk) {
+  const double a0 = hc - h0, a1 = hc - h1, a2 = hc - h2, a3 = hc - h3, a4 = hc - h4;
+  const double a5 = hc - h5, a6 = hc - h6, a7 = hc - h7;
   constexpr double kNear = 1.0 - 0x1p-49;
   constexpr double kMargin = 1.0 - 0x1p-48;
   const double md = fmax(fmax(a0, a2), fmax(a5, a7));
@@ -184,7 +175,16 @@ __device__ __forceinline__ uint8_t receiver_code(const double* h, int ci, int W,
   const bool fast = q >= 0x1p-1000 && q <= 0x1p1000 && !(q2 >= q * kMargin) &&
                     !(q3 >= q * kMargin) && near == 0u;
   if (fast) return (uint8_t)(__ffs(eq) - 1);
-  return receiver_code_by_definition(h, ci, W, rk.dx, rk.dy, rk.dd);
+  return receiver_code_by_definition(hc, h0, h1, h2, h3, h4, h5, h6, h7, rk.dx, rk.dy, rk.dd);
+}
+
+// Receiver code of the cell at index ci of a row-major array of heights with
+// row stride W (every neighbour present).
+template <bool kSquare>
+__device__ __forceinline__ uint8_t receiver_code_at(const double* h, int ci, int W,
+                                                    const RecvConst& rk) {
+  return receiver_code<kSquare>(h[ci], h[ci - W - 1], h[ci - W], h[ci - W + 1], h[ci - 1],
+                                h[ci + 1], h[ci + W - 1], h[ci + W], h[ci + W + 1], rk);
 }
 
 // F = K*dt*A^m/d and 1 + F for a cell of grid gi (descriptor G) with
@@ -236,6 +236,24 @@ __device__ __noinline__ double newton_height(double h0, double hr, double f, dou
 
 __device__ __forceinline__ double eroded_height(const GridDev& G, double h0, double hr, double f,
                                                 double g) {
+  return G.newton ? newton_height(h0, hr, f, G.nexp, G.eps, G.max_newton) : (h0 + f * hr) / g;
+}
+
+// Step 7 for one cell of grid gi in full generality (per-cell K, counts past
+// the tables, n != 1): erosion_factor and eroded_height in one out-of-line
+// call, for kernels whose common case reads F from a table in LDS.
+__device__ __noinline__ double eroded_height_general(const GridDev* grids, int gi,
+                                                     const double* Kf, const double* amtab,
+                                                     uint32_t count, int k, int64_t c, double h0,
+                                                     double hr) {
+  const GridDev& G = grids[gi];
+  const int cls = code_class(k);
+  const double d = cls == 0 ? G.dn[0] : (cls == 1 ? G.dn[1] : G.dn[2]);
+  const double am = count < (uint32_t)kAmTab ? amtab[gi * kAmTab + count]
+                                             : area_power((double)count * G.dxdy, G.use_sqrt, G.m);
+  const double kc = Kf ? Kf[c] : G.K;
+  const double f = ((kc * G.dt) * am) / d;
+  const double g = 1.0 + f;
   return G.newton ? newton_height(h0, hr, f, G.nexp, G.eps, G.max_newton) : (h0 + f * hr) / g;
 }
 
@@ -362,328 +380,483 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
-  __shared__ double hs[kHH * kHW];            // heights, tile + 2-cell halo
-  __shared__ uint16_t nxt[kTileCells];        // pointer jumping: ends as the local root
-  __shared__ uint32_t clw[kTileCells / 2];    // upstream counts, two 16-bit halves a word
-  __shared__ uint8_t rc[kRH * kRW];           // receiver codes, tile + ring
-  __shared__ uint8_t dm[kTileCells];          // donor masks
-  __shared__ uint8_t dp[kTileCells];          // level within the tile
-  __shared__ double ftl[3 * kAmTab];          // F for small counts (scalar K), per distance class
-  __shared__ uint8_t crossing[kTileCells];    // per local root: tree leaves/enters the tile
-  __shared__ int wsum[kTileThreads / 64];
-  __shared__ int s_flag[2];
-  __shared__ int s_all, s_clean, s_cmax, s_base;
+// Tile pass.  Every per-cell LDS array uses the row stride of the staged
+// region (the tile plus a 2-cell halo), so one index serves them all.  Each
+// thread owns a vertical strip of kStrip cells of one column: the wave's 64
+// lanes are the tile's 64 columns, so LDS rows are read without conflicts
+// and the receivers of a strip reuse a sliding 3x3 window of registers.
+constexpr int kSW = kTW + 4;
+constexpr int kSH = kTH + 4;
+constexpr int kSN = kSW * kSH;
+constexpr int kStrip = kTH / (kTileThreads / kTW);
+constexpr int kRing = 2 * (kTW + 2) + 2 * kTH;  // cells of the ring around the tile
+constexpr uint32_t kRingFlag = 0x10;            // rc bit: the cell lies on the ring
+static_assert(kTileThreads % kTW == 0 && kTH % (kTileThreads / kTW) == 0, "strip layout");
+static_assert(kStrip == 8, "codes packed 4 bits a cell in one word, levels 8 bits in two");
+static_assert(kRing <= kTileThreads, "one ring cell per thread");
+static_assert(kSN % 4 == 0, "byte arrays cleared as words");
 
-  const int tid = threadIdx.x;
-  const Work w = a.w;
-  const int tile = w.tiles[xcd_tile(blockIdx.x, a.ntiles)];
-  const int gi = grid_of_tile(a.grids, a.ngrids, tile);
-  const GridDev& G = a.grids[gi];  // read through the scalar cache, not copied
-  const int lt = tile - G.tile_base;
-  const int y0 = (lt / G.tiles_x) * kTH, x0 = (lt % G.tiles_x) * kTW;
-  const int ny = G.ny, nx = G.nx;
-  const int64_t off = G.offset;
-
-  if (tid == 0) {
-    s_flag[0] = 0;
-    s_flag[1] = 0;
-    s_all = 0;
-    s_clean = 0;
-    s_cmax = 0;
+// Offset of neighbour k in the tile pass's LDS layout: eight signed bytes in
+// one word, so a run-time k costs a shift and a sign extension.
+constexpr uint64_t lds_off_table() {
+  uint64_t t = 0;
+  for (int k = 0; k < 8; ++k) {
+    const int dy = (int)((0xA940u >> (2 * k)) & 3u) - 1, dx = (int)((0x9224u >> (2 * k)) & 3u) - 1;
+    t |= (uint64_t)(uint8_t)(int8_t)(dy * kSW + dx) << (8 * k);
   }
-  for (int i = tid; i < kTileCells / 2; i += kTileThreads) clw[i] = 0u;
-  // Heights of the tile and a 2-cell halo (positions outside the grid hold 0
-  // and are never used).  All loads are issued before the LDS stores.
-  {
-    double v[kStageLoads];
-#pragma unroll
-    for (int j = 0; j < kStageLoads; ++j) {
-      const int i = tid + j * kTileThreads;
-      const int gy = y0 - 2 + i / kHW, gx = x0 - 2 + i % kHW;
-      v[j] = (i < kHH * kHW && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
-                 ? a.h_in[off + (int64_t)gy * nx + gx] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < kStageLoads; ++j) {
-      const int i = tid + j * kTileThreads;
-      if (i < kHH * kHW) hs[i] = v[j];
-    }
-  }
-  __syncthreads();
+  return t;
+}
+static_assert(kSW + 1 <= 127, "neighbour offsets fit a signed byte");
+__device__ __forceinline__ int lds_off(int k) {
+  return (int)(int8_t)(uint8_t)(lds_off_table() >> (8 * k));
+}
 
-  // Receiver codes of the tile and its ring.
-  const bool square = G.square != 0;
-  RecvConst rk;
-  rk.dx = G.dx;
-  rk.dy = G.dy;
-  rk.dd = G.ddiag;
-  rk.inv_dx = G.inv_dx;
-  rk.inv_dy = G.inv_dy;
-  rk.inv_dd = G.inv_dd;
-  for (int i = tid; i < kRH * kRW; i += kTileThreads) {
-    const int ly = i / kRW, lx = i % kRW;
-    const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
-    uint8_t code;
-    if (gy < 0 || gy >= ny || gx < 0 || gx >= nx)
+// Codes of the kStrip cells of a strip whose first cell has LDS index li0,
+// from the staged heights (a sliding window of three rows of three), stored
+// in rc and returned 4 bits a cell.  Cells outside the grid get kNone and
+// perimeter cells kBase; `inner` says neither occurs.
+template <bool kSquare>
+__device__ __forceinline__ uint32_t strip_codes(const double* hs, uint8_t* rc, int li0,
+                                                const RecvConst& rk, bool inner, int gy0, int gx,
+                                                int ny, int nx) {
+  double l0 = hs[li0 - kSW - 1], c0 = hs[li0 - kSW], r0 = hs[li0 - kSW + 1];
+  double l1 = hs[li0 - 1], c1 = hs[li0], r1 = hs[li0 + 1];
+  uint32_t codes = 0;
+#pragma unroll 2
+  for (int t = 0; t < kStrip; ++t) {
+    const int li = li0 + t * kSW;
+    const double l2 = hs[li + kSW - 1], c2 = hs[li + kSW], r2 = hs[li + kSW + 1];
+    uint32_t code;
+    const int gy = gy0 + t;
+    if (!inner && (gy >= ny || gx >= nx))
       code = kNone;
-    else if (a.fixed)
-      code = w.rcode[off + (int64_t)gy * nx + gx];
-    else if (gy == 0 || gx == 0 || gy == ny - 1 || gx == nx - 1)
+    else if (!inner && (gy == 0 || gx == 0 || gy == ny - 1 || gx == nx - 1))
       code = kBase;
-    else if (square)
-      code = receiver_code<true>(hs, (ly + 1) * kHW + (lx + 1), kHW, rk);
     else
-      code = receiver_code<false>(hs, (ly + 1) * kHW + (lx + 1), kHW, rk);
-    rc[i] = code;
+      code = receiver_code<kSquare>(c1, l0, c0, r0, l1, r1, l2, c2, r2, rk);
+    codes |= code << (4 * t);
+    rc[li] = (uint8_t)code;
+    l0 = l1; c0 = c1; r0 = r1;
+    l1 = l2; c1 = c2; r1 = r2;
   }
-  __syncthreads();
+  return codes;
+}
 
-  // The grid's F table goes to LDS; its loads are issued here and stored at
-  // the end of this phase, so that their latency hides behind its work.
+// Geometry of tile b of the launch (tiles are visited in XCD-contiguous order).
+struct TileGeo {
+  int gi, y0, x0;
+  bool inner;    // tile, ring and 2-cell halo inside the grid
+  bool paired;   // inner, and every staged row starts 16-byte aligned
+};
+
+__device__ __forceinline__ TileGeo tile_geo(const StepArgs& a, int b) {
+  TileGeo t;
+  const int tile = a.w.tiles[xcd_tile(b, a.ntiles)];
+  t.gi = grid_of_tile(a.grids, a.ngrids, tile);
+  const GridDev& G = a.grids[t.gi];
+  const int lt = tile - G.tile_base;
+  t.y0 = (lt / G.tiles_x) * kTH;
+  t.x0 = (lt % G.tiles_x) * kTW;
+  t.inner = t.y0 >= 2 && t.x0 >= 2 && t.y0 + kTH + 2 <= G.ny && t.x0 + kTW + 2 <= G.nx;
+  t.paired = t.inner && (G.nx & 1) == 0 && ((G.offset + t.x0) & 1) == 0;
+  return t;
+}
+
+// Staged heights of a paired tile as pairs of doubles, loaded by one thread.
+constexpr int kPairs = kSW / 2;
+constexpr int kPairTotal = kSH * kPairs;
+constexpr int kPairLoads = (kPairTotal + kTileThreads - 1) / kTileThreads;
+
+__device__ __forceinline__ void load_pairs(const double* hin, int nx, int y0, int x0, int tid,
+                                           double2* v) {
+#pragma unroll
+  for (int j = 0; j < kPairLoads; ++j) {
+    // Threads past the region reload its last pair (never stored), so that
+    // every element is written and the array stays in registers.
+    const int p = min(tid + j * kTileThreads, kPairTotal - 1);
+    const int r = p / kPairs, cp = p - r * kPairs;
+    v[j] = *(const double2*)(hin + (int64_t)(y0 - 2 + r) * nx + (x0 - 2) + 2 * cp);
+  }
+}
+
+__device__ __forceinline__ void store_pairs(double* hs, int tid, const double2* v) {
+#pragma unroll
+  for (int j = 0; j < kPairLoads; ++j) {
+    const int p = tid + j * kTileThreads;
+    if (p < kPairTotal) {
+      const int r = p / kPairs, cp = p - r * kPairs;
+      *(double2*)(hs + r * kSW + 2 * cp) = v[j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
+  __shared__ __align__(16) double hs[kSN];  // heights, tile + 2-cell halo; new heights
+  __shared__ uint32_t clw[kSN / 2];         // upstream counts, two 16-bit halves a word
+  __shared__ uint32_t rc32[kSN / 4];        // receiver codes, tile and ring (ring: | kRingFlag)
+  __shared__ __align__(8) uint32_t xr32[kSN / 4];  // per local root: its tree crosses the tile edge
+  __shared__ double ftl[3 * kAmTab];        // F for small counts (scalar K), per distance class
+  __shared__ uint16_t wlist[kTH * kTW];     // per wave: its cells of one level
+  __shared__ int wsum[kTileThreads / 64];
+  __shared__ int s_all, s_clean, s_cmax, s_base;
+  uint8_t* rc = (uint8_t*)rc32;
+  uint8_t* xr = (uint8_t*)xr32;
+
+  const int tid = threadIdx.x, tx = tid % kTW, ty = tid / kTW, lane = tid & 63;
+  const Work& w = a.w;
+  const int sy0 = kStrip * ty;                // first strip row within the tile
+  const int li0 = (sy0 + 2) * kSW + tx + 2;   // LDS index of the strip's first cell
+  uint16_t* wl = wlist + (tid / 64) * (64 * kStrip);
+  const bool clock = a.timers && tid == 0;    // per-phase device clock (LEM_F_PHASE_TIMERS)
   static_assert(3 * kAmTab <= 2 * kTileThreads, "at most two table entries per thread");
   const bool has_ft0 = tid < 3 * kAmTab, has_ft1 = tid + kTileThreads < 3 * kAmTab;
-  double ft0 = 0.0, ft1 = 0.0;
-  if (!a.Kf) {
-    if (has_ft0) ft0 = w.ftab[gi * 3 * kAmTab + tid];
-    if (has_ft1) ft1 = w.ftab[gi * 3 * kAmTab + tid + kTileThreads];
-  }
-  // Donor masks.  Tile-local roots (cells without a receiver, and cells
-  // whose receiver is outside the tile) point to themselves at distance 0;
-  // every other cell points to its receiver at distance 1.
-#pragma unroll
-  for (int t = 0; t < kCellsPerThread; ++t) {
-    const int i = tid + t * kTileThreads;
-    const int ly = i / kTW, lx = i % kTW;
-    crossing[i] = 0;
-    if (y0 + ly >= ny || x0 + lx >= nx) {
-      nxt[i] = (uint16_t)i;
-      dp[i] = 0;
-      dm[i] = 0;
-      continue;
+  {
+    const TileGeo tg = tile_geo(a, blockIdx.x);
+    const int gi = tg.gi, y0 = tg.y0, x0 = tg.x0;
+    const bool inner = tg.inner;
+    const GridDev& G = a.grids[gi];  // read through the scalar cache, not copied
+    const int ny = G.ny, nx = G.nx;
+    const int64_t off = G.offset;
+    uint64_t tk[kTilePhases + 1];
+    if (clock) tk[0] = wall_clock64();
+
+    if (tid == 0) {
+      s_all = 0;
+      s_clean = 0;
+      s_cmax = 0;
     }
-    const int ri = (ly + 1) * kRW + (lx + 1);
-    uint32_t m = 0;
+    for (int i = tid; i < kSN / 2; i += kTileThreads) clw[i] = 0x00010001u;  // counts start at 1
+    for (int i = tid; i < kSN / 4; i += kTileThreads) xr32[i] = 0u;
+    // The grid's F table goes to LDS; its loads are issued first and stored
+    // after the staging stores.
+    const bool new_table = !a.Kf;
+    double ft0 = 0.0, ft1 = 0.0;
+    if (new_table) {
+      if (has_ft0) ft0 = w.ftab[gi * 3 * kAmTab + tid];
+      if (has_ft1) ft1 = w.ftab[gi * 3 * kAmTab + tid + kTileThreads];
+    }
+
+    // Heights of the tile and a 2-cell halo (positions outside the grid hold
+    // 0 and are never used).  All loads are issued before the LDS stores.
+    const double* hin = a.h_in + off;
+    if (tg.paired) {
+      double2 pr[kPairLoads];
+      load_pairs(hin, nx, y0, x0, tid, pr);
+      store_pairs(hs, tid, pr);
+    } else {
+      // Two rounds of loads then stores (one round's values in registers).
+      constexpr int kN = (kSN + kTileThreads - 1) / kTileThreads, kHalf = (kN + 1) / 2;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (rc[ri + code_dy(k) * kRW + code_dx(k)] == 7 - k) m |= 1u << k;
-    dm[i] = (uint8_t)m;
-    const int code = rc[ri];
-    int target = i, dist = 0;
-    if (code < kSink) {
-      const int ry = ly + code_dy(code), rx = lx + code_dx(code);
-      if (ry < 0 || ry >= kTH || rx < 0 || rx >= kTW)
-        crossing[i] = 1;  // exits the tile: a crossing tree's local root
-      else {
-        target = ry * kTW + rx;
-        dist = 1;
+      for (int h = 0; h < 2; ++h) {
+        double v[kHalf];
+#pragma unroll
+        for (int j = 0; j < kHalf; ++j) {
+          const int i = tid + (h * kHalf + j) * kTileThreads;
+          const int r = i / kSW, cl = i - r * kSW;
+          const int gy = y0 - 2 + r, gxh = x0 - 2 + cl;
+          const bool in = i < kSN && gy >= 0 && gy < ny && gxh >= 0 && gxh < nx;
+          v[j] = in ? hin[(int64_t)gy * nx + gxh] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kHalf; ++j) {
+          const int i = tid + (h * kHalf + j) * kTileThreads;
+          if (i < kSN) hs[i] = v[j];
+        }
       }
     }
-    nxt[i] = (uint16_t)target;
-    dp[i] = (uint8_t)dist;
-  }
-  if (!a.Kf) {
-    if (has_ft0) ftl[tid] = ft0;
-    if (has_ft1) ftl[tid + kTileThreads] = ft1;
-  }
-  __syncthreads();
-
-  // Pointer jumping: after r rounds every cell points 2^r receivers down (or
-  // to its local root) and dp holds that distance, so dp ends as the level
-  // of the cell within its tile-local tree.  Depths beyond kLocalDepthCap
-  // and receiver cycles (possible only with fixed routing) leave cells
-  // unresolved and send the whole tile to the global pass.
-  for (int r = 0; r <= 8; ++r) {
-    uint16_t np[kCellsPerThread];
-    int nd[kCellsPerThread];
-    uint32_t upd = 0;
-#pragma unroll
-    for (int t = 0; t < kCellsPerThread; ++t) {
-      const int i = tid + t * kTileThreads;
-      const int p = nxt[i];
-      const int pp = nxt[p];
-      np[t] = (uint16_t)pp;
-      nd[t] = dp[i] + dp[p];
-      if (p != pp) upd |= 1u << t;
+    if (new_table) {
+      if (has_ft0) ftl[tid] = ft0;
+      if (has_ft1) ftl[tid + kTileThreads] = ft1;
     }
-    if (upd) s_flag[r & 1] = 1;
     __syncthreads();
-    const bool go = s_flag[r & 1] != 0;
-    if (go && r == 8 && tid == 0) s_all = 1;  // still unresolved after 8 rounds
-#pragma unroll
-    for (int t = 0; t < kCellsPerThread; ++t) {
-      if (!(upd & (1u << t))) continue;
-      const int i = tid + t * kTileThreads;
-      nxt[i] = np[t];
-      dp[i] = (uint8_t)(nd[t] > kLocalDepthCap ? kLocalDepthCap : nd[t]);
-      if (nd[t] > kLocalDepthCap) s_all = 1;
-    }
-    if (tid == 0) s_flag[(r + 1) & 1] = 0;
-    __syncthreads();
-    if (!go) break;
-  }
+    if (clock) tk[1] = wall_clock64();
 
-  // Every cell must now point at a genuine local root: a cell without a
-  // receiver or one whose receiver is outside the tile.  Pointer jumping maps
-  // a receiver cycle (fixed routing only) onto cells that point at
-  // themselves without being roots; such a tile goes to the global pass,
-  // which reports the cycle.  A tree crosses the tile edge if its local root
-  // exits the tile (marked above) or if any of its cells has a donor outside
-  // the tile.
+    // Step 2 / Algorithm 1: receiver codes of the thread's strip, then one
+    // cell of the ring per thread.
+    RecvConst rk;
+    rk.dx = G.dx;
+    rk.dy = G.dy;
+    rk.dd = G.ddiag;
+    rk.inv_dx = G.inv_dx;
+    rk.inv_dy = G.inv_dy;
+    rk.inv_dd = G.inv_dd;
+    const bool square = G.square != 0;
+    const int gx = x0 + tx;
+    uint32_t codes = 0;
+    if (a.fixed) {
 #pragma unroll
-  for (int t = 0; t < kCellsPerThread; ++t) {
-    const int i = tid + t * kTileThreads;
-    const int r = nxt[i];
-    const int rcode = rc[(r / kTW + 1) * kRW + (r % kTW + 1)];
-    if (rcode < kSink && !crossing[r]) s_all = 1;
-    // A donor outside the tile: only border cells have neighbours outside,
-    // in the directions 0-2 (top row), 5-7 (bottom row), 0, 3, 5 (left
-    // column) and 2, 4, 7 (right column).
-    const int ly = i / kTW, lx = i % kTW;
-    const uint32_t out = (ly == 0 ? 0x07u : 0u) | (ly == kTH - 1 ? 0xE0u : 0u) |
-                         (lx == 0 ? 0x29u : 0u) | (lx == kTW - 1 ? 0x94u : 0u);
-    if (dm[i] & out) crossing[r] = 1;
-  }
-  __syncthreads();
-  const bool all_cross = s_all != 0;
-
-  // Cells of trees that stay in the tile ("clean") and their deepest level.
-  uint32_t clean_bits = 0;
-  int my_max = -1;
-#pragma unroll
-  for (int t = 0; t < kCellsPerThread; ++t) {
-    const int i = tid + t * kTileThreads;
-    const int ly = i / kTW, lx = i % kTW;
-    if (all_cross || y0 + ly >= ny || x0 + lx >= nx || crossing[nxt[i]]) continue;
-    clean_bits |= 1u << t;
-    my_max = max(my_max, (int)dp[i]);
-  }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) my_max = max(my_max, __shfl_xor(my_max, d, 64));
-  if ((tid & 63) == 0 && my_max >= 0) atomicMax(&s_cmax, my_max);
-  // Step 5: each clean cell adds one to the count of every cell on its path
-  // to the root (itself included): count = number of upstream cells.
-#pragma unroll
-  for (int t = 0; t < kCellsPerThread; ++t) {
-    if (!(clean_bits & (1u << t))) continue;
-    int v = tid + t * kTileThreads;
-    for (int s = 0; s <= kLocalDepthCap; ++s) {
-      atomicAdd(&clw[v >> 1], 1u << ((v & 1) * 16));
-      const int code = rc[(v / kTW + 1) * kRW + (v % kTW + 1)];
-      if (code >= kSink) break;
-      v += code_dy(code) * kTW + code_dx(code);
-    }
-  }
-  __syncthreads();
-
-  // Steps 6-7 for clean trees: uplift of interior roots (level 0), then the
-  // implicit update level by level from the root.  Each thread keeps its own
-  // cells; F comes from the grid's table staged in LDS (scalar K, counts
-  // below kAmTab) or is computed as in erosion_factor.
-  const int cmax = min(s_cmax, kLocalDepthCap);
-  // Levels of this thread's cells, one byte each, so that finding the cells
-  // of a level takes register arithmetic only.
-  static_assert(kCellsPerThread <= 8, "one byte per cell in a 64-bit word");
-  uint16_t* wlist = nxt + (tid >> 6) * (64 * kCellsPerThread);
-  uint64_t my_levels = 0;
-#pragma unroll
-  for (int t = 0; t < kCellsPerThread; ++t)
-    my_levels |= (uint64_t)dp[tid + t * kTileThreads] << (8 * t);
-  for (int l = 0; l <= cmax; ++l) {
-    uint32_t at_l = 0;
-#pragma unroll
-    for (int t = 0; t < kCellsPerThread; ++t)
-      at_l |= (uint32_t)(((my_levels >> (8 * t)) & 0xFFu) == (uint64_t)l) << t;
-    at_l &= clean_bits;
-    // The wave's cells of level l, compacted into its slice of nxt (free by
-    // now) and spread over its 64 lanes.
-    const int cnt = __popc(at_l);
-    const int incl = wave_inclusive_scan(cnt);
-    const int total = __shfl(incl, 63, 64);
-    int pos = incl - cnt;
-    while (at_l) {
-      const int t = __ffs(at_l) - 1;
-      at_l &= at_l - 1;
-      wlist[pos++] = (uint16_t)(tid + t * kTileThreads);
-    }
-    __builtin_amdgcn_wave_barrier();
-    for (int j = (tid & 63); j < total; j += 64) {
-      const int i = wlist[j];
-      const int ly = i / kTW, lx = i % kTW;
-      const int code = rc[(ly + 1) * kRW + (lx + 1)];
-      if (code == kBase) continue;
-      const int64_t c = off + (int64_t)(y0 + ly) * nx + (x0 + lx);
-      const int hidx = (ly + 2) * kHW + (lx + 2);
-      const double up = a.Uf ? a.Uf[c] * G.dt : G.udt;
-      if (code == kSink) {
-        hs[hidx] = hs[hidx] + up;
-        continue;
+      for (int t = 0; t < kStrip; ++t) {
+        const int gy = y0 + sy0 + t;
+        const uint32_t code = (gy < ny && gx < nx) ? w.rcode[off + (int64_t)gy * nx + gx] : kNone;
+        codes |= code << (4 * t);
+        rc[li0 + t * kSW] = (uint8_t)code;
       }
-      const uint32_t count = (clw[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
-      double f, g;
-      if (!a.Kf && count < (uint32_t)kAmTab) {
-        f = ftl[code_class(code) * kAmTab + count];
-        g = 1.0 + f;
+    } else if (square) {
+      codes = strip_codes<true>(hs, rc, li0, rk, inner, y0 + sy0, gx, ny, nx);
+    } else {
+      codes = strip_codes<false>(hs, rc, li0, rk, inner, y0 + sy0, gx, ny, nx);
+    }
+    if (tid < kRing) {
+      int ly, lx;  // ring cell within the tile's frame: rows -1 and kTH, columns -1 and kTW
+      if (tid < kTW + 2) {
+        ly = -1;
+        lx = tid - 1;
+      } else if (tid < 2 * (kTW + 2)) {
+        ly = kTH;
+        lx = tid - (kTW + 2) - 1;
+      } else if (tid < 2 * (kTW + 2) + kTH) {
+        ly = tid - 2 * (kTW + 2);
+        lx = -1;
       } else {
-        erosion_factor(a, G, gi, count, code, c, &f, &g);
+        ly = tid - 2 * (kTW + 2) - kTH;
+        lx = kTW;
       }
-      const double h0 = hs[hidx] + up;
-      hs[hidx] = eroded_height(G, h0, hs[hidx + code_dy(code) * kHW + code_dx(code)], f, g);
+      const int li = (ly + 2) * kSW + lx + 2;
+      const int gy = y0 + ly, gxr = x0 + lx;
+      uint32_t code;
+      if (gy < 0 || gy >= ny || gxr < 0 || gxr >= nx)
+        code = kNone;
+      else if (a.fixed)
+        code = w.rcode[off + (int64_t)gy * nx + gxr];
+      else if (gy == 0 || gxr == 0 || gy == ny - 1 || gxr == nx - 1)
+        code = kBase;
+      else if (square)
+        code = receiver_code_at<true>(hs, li, kSW, rk);
+      else
+        code = receiver_code_at<false>(hs, li, kSW, rk);
+      rc[li] = (uint8_t)(code | kRingFlag);
     }
     __syncthreads();
-  }
+    if (clock) tk[2] = wall_clock64();
 
-  // Write the tile back; queue the roots of crossing trees for the global
-  // pass; count the cells resolved here.
-  int my_clean = 0, my_roots = 0;
-  uint32_t root_bits = 0;
+    // Step 3 / Algorithm 2: donor masks of the strip (neighbour k drains
+    // here when its code is 7 - k), from a sliding window of the codes.
+    uint64_t dms = 0;
+    {
+      uint32_t l0 = rc[li0 - kSW - 1] & 15u, c0 = rc[li0 - kSW] & 15u,
+               r0 = rc[li0 - kSW + 1] & 15u;
+      uint32_t l1 = rc[li0 - 1] & 15u, r1 = rc[li0 + 1] & 15u;
 #pragma unroll
-  for (int t = 0; t < kCellsPerThread; ++t) {
-    const int i = tid + t * kTileThreads;
-    const int ly = i / kTW, lx = i % kTW;
-    if (y0 + ly >= ny || x0 + lx >= nx) continue;
-    const int64_t c = off + (int64_t)(y0 + ly) * nx + (x0 + lx);
-    const int code = rc[(ly + 1) * kRW + (lx + 1)];
-    const bool clean = (clean_bits >> t) & 1u;
-    a.h_out[c] = hs[(ly + 2) * kHW + (lx + 2)];
-    w.dmask[c] = dm[i];
-    if (clean) {
-      ++my_clean;
-      if (a.export_routing) {
-        w.dep_g[c] = dp[i];
-        w.cnt_g[c] = (clw[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
+      for (int t = 0; t < kStrip; ++t) {
+        const int li = li0 + t * kSW;
+        const uint32_t l2 = rc[li + kSW - 1] & 15u, c2 = rc[li + kSW] & 15u,
+                       r2 = rc[li + kSW + 1] & 15u;
+        const uint32_t m = (uint32_t)(l0 == 7u) | ((uint32_t)(c0 == 6u) << 1) |
+                           ((uint32_t)(r0 == 5u) << 2) | ((uint32_t)(l1 == 4u) << 3) |
+                           ((uint32_t)(r1 == 3u) << 4) | ((uint32_t)(l2 == 2u) << 5) |
+                           ((uint32_t)(c2 == 1u) << 6) | ((uint32_t)(r2 == 0u) << 7);
+        dms |= (uint64_t)m << (8 * t);
+        l0 = l1; c0 = (codes >> (4 * t)) & 15u; r0 = r1;
+        l1 = l2; r1 = r2;
       }
-    } else if (code >= kSink) {
-      root_bits |= 1u << t;
-      ++my_roots;
     }
-    if (a.export_routing && !a.fixed) w.rcode[c] = (uint8_t)code;
-  }
-  atomicAdd(&s_clean, my_clean);
-  // Roots go to the grid's own queue slice for the per-grid level pass, to
-  // the one shared queue otherwise (the chunk stage takes them from there).
-  const bool pergrid_roots = a.pergrid && !a.chunked;
-  int tot;
-  const int pre = block_exclusive_scan<kTileThreads>(my_roots, wsum, &tot);
-  if (tid == 0)
-    s_base = tot ? atomicAdd(pergrid_roots ? &w.gcnt[gi] : &w.lcnt[0], tot) : 0;
-  __syncthreads();
-  int pos = (pergrid_roots ? (int)off : 0) + s_base + pre;
-  while (root_bits) {
-    const int t = __ffs(root_bits) - 1;
-    root_bits &= root_bits - 1;
-    const int i = tid + t * kTileThreads;
-    const int ly = i / kTW, lx = i % kTW;
-    const int64_t c = off + (int64_t)(y0 + ly) * nx + (x0 + lx);
-    w.q[pos] = (int32_t)c;
-    w.gq[pos] = (uint16_t)gi;
-    w.par[pos] = -1;
-    w.kq[pos] = rc[(ly + 1) * kRW + (lx + 1)];
-    ++pos;
-  }
-  if (tid == 0 && s_clean) {
-    atomicAdd(&w.ctrl->clean, s_clean);
-    atomicMax(&w.ctrl->clean_maxdepth, cmax);
+
+    // Steps 4-5 inside the tile: each cell walks down its receivers to its
+    // tile-local root -- a cell without a receiver, or one whose receiver is
+    // outside the tile -- adding one to the count of every cell it passes (a
+    // cell's count = the cells upstream of it, itself included) and counting
+    // its steps (its level in the local tree).  A tree crosses the tile edge
+    // if its local root drains out of the tile or one of its border cells
+    // has a donor outside; such trees are marked at their local root.  A
+    // walk longer than kLocalDepthCap (a receiver cycle under fixed routing,
+    // or a very deep tree) sends the whole tile to the crossing-tree passes.
+    uint64_t deps = 0;
+    uint32_t roots[kStrip / 2];
+#pragma unroll
+    for (int t = 0; t < kStrip; ++t) {
+      int v = li0 + t * kSW;
+      uint32_t cv = (codes >> (4 * t)) & 15u;
+      uint32_t d = 0;
+      bool exits = false;
+      if (cv < kSink) {
+        for (;;) {
+          const int u = v + lds_off((int)cv);
+          const uint32_t cu = rc[u];
+          if (cu & kRingFlag) {
+            exits = true;
+            break;
+          }
+          atomicAdd(&clw[u >> 1], 1u << ((u & 1) * 16));
+          ++d;
+          v = u;
+          cv = cu;
+          if (cu >= kSink) break;
+          if (d >= (uint32_t)kLocalDepthCap) {
+            s_all = 1;
+            break;
+          }
+        }
+      }
+      // Outward directions of a border cell: 0-2 (top row), 5-7 (bottom
+      // row), 0, 3, 5 (left column), 2, 4, 7 (right column).
+      const int sy = sy0 + t;
+      const uint32_t out = (sy == 0 ? 0x07u : 0u) | (sy == kTH - 1 ? 0xE0u : 0u) |
+                           (tx == 0 ? 0x29u : 0u) | (tx == kTW - 1 ? 0x94u : 0u);
+      if (exits || (((dms >> (8 * t)) & out) != 0)) xr[v] = 1;
+      deps |= (uint64_t)d << (8 * t);
+      if (t & 1)
+        roots[t >> 1] |= (uint32_t)v << 16;
+      else
+        roots[t >> 1] = (uint32_t)v;
+    }
+    __syncthreads();
+    if (clock) tk[3] = wall_clock64();
+
+    // Cells of trees that stay in the tile ("clean") and their deepest
+    // level; the roots of the other trees are counted and their queue slots
+    // reserved now (the atomic's reply is first needed at write-back).
+    const uint32_t all_ok = s_all ? 0u : 0xFFu;
+    uint32_t clean = 0, my_max = 0, root_bits = 0;
+#pragma unroll
+    for (int t = 0; t < kStrip; ++t) {
+      const int r = (roots[t >> 1] >> (16 * (t & 1))) & 0xFFFF;
+      const uint32_t code = (codes >> (4 * t)) & 15u;
+      const uint32_t ok = (uint32_t)(code != kNone) & (uint32_t)(xr[r] == 0) & all_ok;
+      clean |= ok << t;
+      const uint32_t d = (uint32_t)((deps >> (8 * t)) & 0xFFu);
+      my_max = max(my_max, ok ? d : 0u);
+      root_bits |= (uint32_t)(!ok && code >= kSink && code != kNone) << t;
+    }
+    int my_clean = __popc(clean);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      my_max = max(my_max, (uint32_t)__shfl_xor((int)my_max, d, 64));
+      my_clean += __shfl_xor(my_clean, d, 64);
+    }
+    if (lane == 0) {
+      atomicMax(&s_cmax, (int)my_max);
+      atomicAdd(&s_clean, my_clean);
+    }
+    // Roots go to the grid's own queue slice for the per-grid level pass, to
+    // the one shared queue otherwise (the chunk stage takes them from there).
+    const bool pergrid_roots = a.pergrid && !a.chunked;
+    int nroots_tile;
+    const int root_pre = block_exclusive_scan<kTileThreads>(__popc(root_bits), wsum, &nroots_tile);
+    int root_base = 0;
+    if (tid == 0 && nroots_tile)
+      root_base = atomicAdd(pergrid_roots ? &w.gcnt[gi] : &w.lcnt[0], nroots_tile);
+    // Donor masks of the tile, row-major in the crossing flags' LDS (free
+    // now), so that no register holds them through the erosion and rows can
+    // be stored 8 bytes at a time at write-back.
+    const bool wide_masks = inner && ((off + x0) & 7) == 0 && (nx & 7) == 0;
+#pragma unroll
+    for (int t = 0; t < kStrip; ++t) xr[(sy0 + t) * kTW + tx] = (uint8_t)((dms >> (8 * t)) & 0xFFu);
+    if (clock) tk[4] = wall_clock64();
+
+    // Steps 6-7 for clean trees, level by level from the roots outward.
+    // Interior roots are only uplifted (at write-back: their level-1 donors
+    // add the uplift to the root's height themselves, and nothing else reads
+    // a root's new height).  Each wave compacts its cells of the level into
+    // a list in LDS and spreads it over its 64 lanes.  F comes from the
+    // grid's table staged in LDS (scalar K, n = 1, counts below kAmTab) or
+    // from eroded_height_general.
+    const bool table_f = !a.Kf && !G.newton;
+    const bool need_c = a.Kf || a.Uf || !table_f;
+    const int cmax = s_cmax;
+    for (int l = 1; l <= cmax; ++l) {
+      // The levels pass through an empty asm so that their bytes are not
+      // extracted once before the loop and held (spilled) through it.
+      uint64_t dl = deps;
+      asm volatile("" : "+v"(dl));
+      uint32_t at = 0;
+#pragma unroll
+      for (int t = 0; t < kStrip; ++t)
+        at |= (uint32_t)(((dl >> (8 * t)) & 0xFFu) == (uint64_t)l) << t;
+      at &= clean;
+      const int cnt = __popc(at);
+      const int incl = wave_inclusive_scan(cnt);
+      const int total = __shfl(incl, 63, 64);
+      int pos = incl - cnt;
+      while (at) {
+        const int t = __ffs(at) - 1;
+        at &= at - 1;
+        wl[pos++] = (uint16_t)(li0 + t * kSW);
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int j = lane; j < total; j += 64) {
+        const int li = wl[j];
+        const int code = rc[li];
+        const int u = li + lds_off(code);
+        int64_t c = 0;
+        if (need_c) {
+          const int row = li / kSW;
+          c = off + (int64_t)(y0 + row - 2) * nx + (x0 + (li - row * kSW) - 2);
+        }
+        double hr = hs[u];
+        if (l == 1 && rc[u] == kSink)  // the receiver is an interior root: add its uplift
+          hr = hr + (a.Uf ? a.Uf[c + neighbour_offset(code, nx)] * G.dt : G.udt);
+        const uint32_t count = (clw[li >> 1] >> ((li & 1) * 16)) & 0xFFFFu;
+        const double h0 = hs[li] + (a.Uf ? a.Uf[c] * G.dt : G.udt);
+        double hn;
+        if (table_f && count < (uint32_t)kAmTab) {
+          const double f = ftl[code_class(code) * kAmTab + count];
+          const double g = 1.0 + f;
+          hn = (h0 + f * hr) / g;
+        } else {
+          hn = eroded_height_general(a.grids, gi, a.Kf, w.amtab, count, code, c, h0, hr);
+        }
+        hs[li] = hn;
+      }
+      __syncthreads();
+    }
+    if (clock) tk[5] = wall_clock64();
+
+    // Write the tile back (heights of crossing trees unchanged here: the
+    // crossing-tree passes overwrite them); queue the roots of crossing trees.
+    // Addresses are formed here, from a column index the compiler cannot
+    // trace back (an empty asm), so that they are not computed early and
+    // kept through the erosion.
+    int gx_wb = gx, li0_wb = li0;
+    asm volatile("" : "+v"(gx_wb), "+v"(li0_wb));
+    const int64_t cw = off + (int64_t)(y0 + sy0) * nx + gx_wb;
+#pragma unroll
+    for (int t = 0; t < kStrip; ++t) {
+      const int li = li0_wb + t * kSW;
+      const uint32_t code = rc[li];
+      if (code == kNone) continue;
+      const int64_t c = cw + (int64_t)t * nx;
+      const bool cl = (clean >> t) & 1u;
+      double hv = hs[li];
+      if (cl && code == kSink) hv = hv + (a.Uf ? a.Uf[c] * G.dt : G.udt);
+      a.h_out[c] = hv;
+      if (!wide_masks) w.dmask[c] = xr[(sy0 + t) * kTW + tx];
+      if (a.export_routing) {
+        if (cl) {
+          w.dep_g[c] = (int32_t)((deps >> (8 * t)) & 0xFFu);
+          w.cnt_g[c] = (clw[li >> 1] >> ((li & 1) * 16)) & 0xFFFFu;
+        }
+        if (!a.fixed) w.rcode[c] = (uint8_t)code;
+      }
+    }
+    if (tid == 0) s_base = root_base;
+    __syncthreads();
+    if (wide_masks) {
+      static_assert(kTH * kTW == 8 * kTileThreads, "eight mask bytes per thread");
+      const int r = tid / (kTW / 8), cb = (tid % (kTW / 8)) * 8;
+      *(uint64_t*)(w.dmask + off + (int64_t)(y0 + r) * nx + x0 + cb) =
+          *(const uint64_t*)(xr + r * kTW + cb);
+    }
+    int pos = (pergrid_roots ? (int)off : 0) + s_base + root_pre;
+    while (root_bits) {
+      const int t = __ffs(root_bits) - 1;
+      root_bits &= root_bits - 1;
+      w.q[pos] = (int32_t)(cw + (int64_t)t * nx);
+      w.gq[pos] = (uint16_t)gi;
+      w.par[pos] = -1;
+      w.kq[pos] = rc[li0_wb + t * kSW];
+      ++pos;
+    }
+    if (tid == 0 && s_clean) {
+      atomicAdd(&w.ctrl->clean, s_clean);
+      atomicMax(&w.ctrl->clean_maxdepth, s_cmax);
+    }
+    if (clock) {
+      tk[6] = wall_clock64();
+      for (int k = 0; k < kTilePhases; ++k)
+        atomicAdd((unsigned long long*)&w.ctrl->tile_ticks[k],
+                  (unsigned long long)(tk[k + 1] - tk[k]));
+      atomicAdd((unsigned long long*)&w.ctrl->tile_wgs, 1ull);
+    }
   }
 }
 
@@ -1707,6 +1880,8 @@ __global__ void k_begin_run(StepArgs a) {
     ct->clean = 0;
     ct->clean_maxdepth = 0;
     ct->crossing_run = 0;
+    for (int k = 0; k < kTilePhases; ++k) ct->tile_ticks[k] = 0;
+    ct->tile_wgs = 0;
     ct->chunk_total = 0;
     ct->chunk_next = 0;
     ct->ovf_count = 0;
@@ -1903,10 +2078,16 @@ hipError_t launch_fixed_routing(const StepArgs& a, const uint8_t* user, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_tile_step(const StepArgs& a, hipStream_t s) {
+hipError_t launch_tile_step(const StepArgs& a, int grid, hipStream_t s) {
+  (void)grid;
   if (a.ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_step, dim3((unsigned)a.ntiles), dim3(kTileThreads), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t tile_kernel_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_tile_step,
+                                                      kTileThreads, 0);
 }
 
 hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s) {

@@ -38,7 +38,8 @@ class lem_stats_t(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("last_nlevels", C.c_int64),
                 ("max_nlevels", C.c_int64), ("last_run_steps", C.c_int64),
                 ("phase_ms", C.c_double * 4), ("kernel_ms", C.c_double * 3),
-                ("crossing_last", C.c_int64), ("crossing_run", C.c_int64)]
+                ("crossing_last", C.c_int64), ("crossing_run", C.c_int64),
+                ("tile_phase_ms", C.c_double * 6)]
 
 
 class lem_grid(C.Structure):

@@ -69,11 +69,11 @@ def test_chunk_sizes_match_stage_off_and_oracle(roots):
     assert_heights_close(h, ref["h"])
 
 
-@pytest.mark.parametrize("shape,roots", [((300, 340), 128), ((300, 340), 1), ((640, 600), 4)])
+@pytest.mark.parametrize("shape,roots", [((300, 340), 128), ((200, 220), 1), ((640, 600), 4)])
 def test_chunks_that_do_not_fit_go_to_the_level_pass(shape, roots):
     """Pyramids: fans of about 150 cells per root overflow a 128-root chunk's
     cell capacity; at 600 cells a side they run deeper than the stage's
-    level limit.  One root per chunk at 300 cells a side fits."""
+    level limit.  One root per chunk at 200 cells a side fits."""
     torch = require_gpu()
     w = W.SMALL_256
     ny, nx = shape

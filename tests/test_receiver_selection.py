@@ -74,8 +74,10 @@ int main(int argc, char** argv) {
     RecvConst rk;
     rk.dx = dx; rk.dy = dy; rk.dd = dd;
     rk.inv_dx = 1.0 / dx; rk.inv_dy = 1.0 / dy; rk.inv_dd = 1.0 / dd;
-    const uint8_t got = (dx == dy) ? receiver_code<true>(h, 4, 3, rk) : receiver_code<false>(h, 4, 3, rk);
-    if (got != receiver_code_by_definition(h, 4, 3, dx, dy, dd)) ++bad;
+    const uint8_t got = (dx == dy) ? receiver_code_at<true>(h, 4, 3, rk)
+                                   : receiver_code_at<false>(h, 4, 3, rk);
+    if (got != receiver_code_by_definition(h[4], h[0], h[1], h[2], h[3], h[5], h[6], h[7], h[8],
+                                           dx, dy, dd)) ++bad;
   }
   printf("mismatches %ld of %ld\n", bad, n);
   return bad != 0;
