@@ -21,6 +21,7 @@ struct lem_ctx {
   std::vector<lem::GridDev> grids;  // host copy of the grid descriptors
   std::vector<int32_t> tiles;       // all tiles, in order
   std::vector<int32_t> active;      // tiles of unfinished grids (steady-state driver)
+  std::vector<int32_t> tgrid_host;  // grid of each uploaded tile (kept until the copy ends)
   int64_t cells;                    // cells of all grids
   int32_t ntiles;
   hipStream_t stream;
@@ -242,10 +243,28 @@ lem_status step(lem_ctx* ctx, lem::StepArgs& a, bool timers) {
   return LEM_OK;
 }
 
+// The grid of every tile in `tiles` (grids hold consecutive tile ranges).
+std::vector<int32_t> tile_grids(const lem_ctx* ctx, const std::vector<int32_t>& tiles) {
+  std::vector<int32_t> g(tiles.size());
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    int32_t lo = 0, hi = (int32_t)ctx->grids.size();
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) / 2;
+      if (ctx->grids[mid].tile_base <= tiles[i]) lo = mid; else hi = mid;
+    }
+    g[i] = lo;
+  }
+  return g;
+}
+
 lem_status upload_tiles(lem_ctx* ctx, const std::vector<int32_t>& tiles) {
   if (tiles.empty()) return LEM_OK;
+  ctx->tgrid_host = tile_grids(ctx, tiles);
   hipError_t e = hipMemcpyAsync(ctx->w.tiles, tiles.data(), sizeof(int32_t) * tiles.size(),
                                 hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->w.tgrid, ctx->tgrid_host.data(), sizeof(int32_t) * tiles.size(),
+                       hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "tile list upload");
   return LEM_OK;
@@ -350,11 +369,9 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->w.grids, ctx->grids.data(), sizeof(lem::GridDev) * ng,
                        hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ctx->w.tiles, ctx->tiles.data(), sizeof(int32_t) * ctx->ntiles,
-                       hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return LEM_E_HIP;
+  if (upload_tiles(ctx, ctx->tiles) != LEM_OK) return LEM_E_HIP;
   return LEM_OK;
 }
 

@@ -124,6 +124,7 @@ struct Work {
   uint8_t* dmask;    // [N] donor mask per cell: bit k set <=> neighbour k drains here
   GridDev* grids;    // [ngrids] grid descriptors
   int32_t* tiles;    // [ntiles] tiles to process (all, or those of unfinished grids)
+  int32_t* tgrid;    // [ntiles] grid of each entry of tiles
   double* conv;      // [2*ngrids] per grid: largest |change| and largest |h| of a step
   int32_t* q;        // [N] global queue: cell per position, level-major
   uint16_t* gq;      // [N] grid of each queue position

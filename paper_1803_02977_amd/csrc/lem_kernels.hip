@@ -257,16 +257,6 @@ __device__ __noinline__ double eroded_height_general(const GridDev* grids, int g
   return G.newton ? newton_height(h0, hr, f, G.nexp, G.eps, G.max_newton) : (h0 + f * hr) / g;
 }
 
-// Grid of a tile: the last grid whose first tile is at or before it.
-__device__ __forceinline__ int grid_of_tile(const GridDev* grids, int ngrids, int tile) {
-  int lo = 0, hi = ngrids;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (grids[mid].tile_base <= tile) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -451,8 +441,9 @@ struct TileGeo {
 
 __device__ __forceinline__ TileGeo tile_geo(const StepArgs& a, int b) {
   TileGeo t;
-  const int tile = a.w.tiles[xcd_tile(b, a.ntiles)];
-  t.gi = grid_of_tile(a.grids, a.ngrids, tile);
+  const int k = xcd_tile(b, a.ntiles);
+  const int tile = a.w.tiles[k];
+  t.gi = a.w.tgrid[k];
   const GridDev& G = a.grids[t.gi];
   const int lt = tile - G.tile_base;
   t.y0 = (lt / G.tiles_x) * kTH;
@@ -2041,6 +2032,7 @@ void carve(void* base, int64_t n, int64_t ngrids, int64_t ntiles, Work* w, bool 
   w->dmask = (uint8_t*)take(n);
   w->grids = (GridDev*)take((int64_t)sizeof(GridDev) * ngrids);
   w->tiles = (int32_t*)take(4 * ntiles);
+  w->tgrid = (int32_t*)take(4 * ntiles);
   w->conv = (double*)take(8 * 2 * ngrids);
   w->q = (int32_t*)take(4 * n);
   w->gq = (uint16_t*)take(2 * n);

@@ -98,3 +98,26 @@ def test_large_grid_properties_after_benchmark_steps():
     rhs = b[nr] + udt
     scale = np.maximum(np.abs(rhs), 1.0) * (1 + 2 * F)
     assert np.all(np.abs(lhs - rhs) <= 4 * H_RTOL * scale)
+
+
+@pytest.mark.parametrize("edge", [12649, 16000])
+def test_size_sweep_region_d_first_step_matches_oracle(edge):
+    """The two largest rasters of the size sweep (region D of the paper's GPU
+    scaling table: 1.6e8 and 2.56e8 cells), one step from seeded noise with
+    the sweep's parameters, every cell against the oracle."""
+    torch = require_gpu()
+    from paper_1803_02977_amd import Solver
+    w = W.SMALL_256.with_(ny=edge, nx=edge)
+    h0 = W.initial_heights(edge, edge, 0)
+    print(f"[gpu] {edge}x{edge} one step vs oracle", flush=True)
+    h = torch.from_numpy(h0).to("cuda:0")
+    s = Solver(edge, edge, w.dx, w.dy, w.dt, w.m, w.U, w.K, device=torch.device("cuda:0"))
+    s.run(h, 1)
+    s.sync()
+    r = s.routing()
+    got = h.cpu().numpy()
+    s.close()
+    del h
+    ref = oracle.run(h0, oracle_params(w), 1)
+    assert_routing_equal(r, ref)
+    assert_heights_close(got, ref["h"])

@@ -297,3 +297,86 @@ def test_argument_errors():
     with pytest.raises(LemError):
         net.set_params(np.zeros(10, np.float32))
     net.close()
+
+
+def _gamma(n):
+    """Bound on the relative error of a float32 sum of n terms in any order."""
+    u = 2.0 ** -24
+    return n * u / (1.0 - n * u)
+
+
+def test_last_layers_gradients_elementwise_on_the_gpus_own_values():
+    """Every element of the head's gradient and of the last convolution's
+    weight gradient against FP64 sums of the GPU's own bfloat16 activations
+    and output.  Bounds per element: a float32 sum of N terms in any order
+    (|err| <= gamma_N * sum |terms|), the float32 rounding of the output
+    gradient, and -- for the convolution, whose output gradient is rounded to
+    bfloat16 -- one bfloat16 step at pixels whose exact value lies within
+    float32 error of a rounding boundary (the same flips as in the forward
+    layer test)."""
+    torch = require_gpu()
+    B, H, W = 2, 32, 48
+    print("[gpu] surrogate last-layer gradients element by element", flush=True)
+    p, K, U, h0, ht = _problem(2, B, H, W)
+    net = _net(torch, B, H, W)
+    net.set_params(p)
+    args = [_dev(torch, a) for a in (K, U, h0, ht)]
+    _, y = net.predict(*args[:3], want_y=True)
+    net.sync()
+    y = y.cpu().numpy().astype(np.float64)
+    d0 = net.activation(20, B).astype(np.float64)   # last decoder output
+    a0 = net.activation(19, B).astype(np.float64)   # its first convolution's output
+    _, g = net.loss_grad(*args)
+    g = g.cpu().numpy().astype(np.float64)
+    layout, _ = S.param_layout()
+    P = S.unpack(p.astype(np.float64))
+    r = S.bf16_round
+    mask = S.interior_mask(y.shape)
+    n = mask.sum()
+    t = S.target(ht, U)
+    dy = np.where(mask, 2.0 * (y - t) / n, 0.0)
+    # float32 error of the GPU's dy: a few roundings of y - t and the scaling.
+    e_dy = np.where(mask, 8 * 2.0 ** -24 * (np.abs(y) + np.abs(t)) * 2.0 / n, 0.0)
+    N = B * H * W
+    # Head: weight gradient and bias gradient.
+    ho = layout["head"][0]
+    C0 = d0.shape[-1]
+    ref_w = (d0 * dy[..., None]).sum(axis=(0, 1, 2))
+    tol_w = (_gamma(N) * (np.abs(d0) * np.abs(dy)[..., None]).sum(axis=(0, 1, 2)) +
+             (np.abs(d0) * e_dy[..., None]).sum(axis=(0, 1, 2)) + 1e-30)
+    assert np.all(np.abs(g[ho:ho + C0] - ref_w) <= tol_w), \
+        float(np.max(np.abs(g[ho:ho + C0] - ref_w) / tol_w))
+    ref_b = dy.sum()
+    tol_b = _gamma(N) * np.abs(dy).sum() + e_dy.sum()
+    assert abs(g[ho + C0] - ref_b) <= tol_b, (g[ho + C0], ref_b, tol_b)
+    # Last convolution (dec0b): output gradient gz = dy * w_head * [d0 > 0],
+    # rounded to bfloat16, against its input a0.
+    wh = r(P["head"][0])
+    active = d0 > 0
+    gz = dy[..., None] * wh[None, None, None, :] * active
+    e_gz = (e_dy[..., None] * np.abs(wh)[None, None, None, :] + np.abs(gz) * 2.0 ** -23) * active
+    gzr = r(gz)
+    # A flip is possible where the exact value is within e_gz of a midpoint.
+    lo, hi = r(gz - e_gz), r(gz + e_gz)
+    flip = (lo != hi)
+    step = np.where(flip, np.maximum(np.abs(hi - gzr), np.abs(lo - gzr)), 0.0)
+    wname = "dec0b"
+    off = layout[wname][0]
+    cout, cin = gz.shape[-1], a0.shape[-1]
+    nw = cout * 9 * cin
+    ref_dw, _ = S.conv3x3_backward(a0, np.zeros((cout, 3, 3, cin)), gzr)
+    abs_dw, _ = S.conv3x3_backward(np.abs(a0), np.zeros((cout, 3, 3, cin)), np.abs(gzr))
+    flip_dw, _ = S.conv3x3_backward(np.abs(a0), np.zeros((cout, 3, 3, cin)), step)
+    tol_dw = _gamma(N) * abs_dw + flip_dw + 1e-30
+    got_dw = g[off:off + nw].reshape(cout, 3, 3, cin)
+    ratio = np.abs(got_dw - ref_dw) / tol_dw
+    assert np.all(ratio <= 1.0), float(ratio.max())
+    # Its bias gradient: the sum of gz (float32, before rounding).
+    ref_db = gz.sum(axis=(0, 1, 2))
+    tol_db = _gamma(N) * np.abs(gz).sum(axis=(0, 1, 2)) + e_gz.sum(axis=(0, 1, 2))
+    got_db = g[off + nw:off + nw + cout]
+    assert np.all(np.abs(got_db - ref_db) <= tol_db), float(np.max(np.abs(got_db - ref_db) / tol_db))
+    frac = float(flip[active].mean())
+    print(f"[gpu] flip-prone output-gradient elements {frac:.2e}", flush=True)
+    assert frac < 5e-2, frac
+    net.close()
