@@ -66,6 +66,8 @@ def _declare(lib):
     lib.lemo_run.restype = C.c_int
     lib.lemo_run_fixed_routing.argtypes = [C.POINTER(_Params), _P, _P, _P, _P, C.c_int64,
                                            _P, _P]
+    lib.lemo_project.argtypes = [C.POINTER(_Params), _P, _P, _P, C.c_int64, _P, _P, _P]
+    lib.lemo_project.restype = C.c_int
     lib.lemo_run_fixed_routing.restype = C.c_int
     lib.lemo_routing.argtypes = [C.POINTER(_Params), _P, _P, _P, _P, _P, C.c_int64, _P]
     lib.lemo_mfd_run.argtypes = [C.POINTER(_Params), C.c_double, _P, _P, _P, C.c_int64, _P, _P,
@@ -219,6 +221,24 @@ def run(h0, params: Params, steps: int, K=None, U=None, lib=None):
                         C.byref(nlev)))
     return dict(h=h, rec=rec, depth=depth, count=count,
                 offsets=offsets[: nlev.value + 1].copy(), nlevels=nlev.value)
+
+
+def project(h0, params: Params, iters: int, K=None, U=None, lib=None):
+    """Steady-state projections (an accelerator of runs to steady state, not
+    a step of the paper's method): each computes the routing of the current
+    heights as Steps 2-5 do, uplifts as Step 6 (Algorithm 5) does, then gives
+    every cell with a receiver the height at which Algorithm 6 would leave it
+    unchanged: h_c = h_r + U_c*dt/F (n = 1) or h_r + (U_c*dt/F)^(1/n), in
+    receiver-first order.  Returns the heights and the last routing."""
+    lib = lib or load()
+    h = np.array(h0, dtype=np.float64, copy=True, order="C")
+    rec = np.empty(h.shape, np.int32)
+    depth = np.empty(h.shape, np.int32)
+    count = np.empty(h.shape, np.uint32)
+    p = params.c()
+    _check(lib.lemo_project(C.byref(p), _ptr(h), _ptr(_f64(K)), _ptr(_f64(U)), int(iters),
+                            _ptr(rec), _ptr(depth), _ptr(count)))
+    return dict(h=h, rec=rec, depth=depth, count=count)
 
 
 def run_fixed_routing(h0, rec, params: Params, steps: int, K=None, U=None, lib=None):

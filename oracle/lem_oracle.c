@@ -245,6 +245,42 @@ void lemo_erode_newton(int32_t ny, int32_t nx, double dx, double dy, double dt,
   }
 }
 
+/* Steady-state projection (an accelerator of runs to steady state, not a
+ * step of the paper's method): with the receivers, counts and stack order of
+ * the step, every cell with a receiver takes the height at which one step of
+ * Algorithm 6 would leave it unchanged given its receiver's new height,
+ * F*(h_c - h_r)^n = U_c*dt, i.e. h_c = h_r + U_c*dt/F for n = 1 and
+ * h_r + (U_c*dt/F)^(1/n) otherwise (F as in Algorithm 6).  Cells without a
+ * receiver keep their uplifted height (interior sinks rise by U*dt, as in a
+ * step).  F = 0 (K = 0) leaves the uplifted height. */
+void lemo_project_heights(int32_t ny, int32_t nx, double dx, double dy, double dt,
+                          double m, double nexp, double U, const double* Ufield, double K,
+                          const double* Kfield, const int32_t* rec, const uint32_t* count,
+                          const int32_t* order, double* h) {
+  const int64_t n = (int64_t)ny * nx;
+  const double ddiag = sqrt(dx * dx + dy * dy);
+  const double dxdy = dx * dy;
+  const double udt = U * dt;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t c = order[i];
+    const int32_t r = rec[c];
+    if (r == c) continue;
+    const int32_t cy = c / nx, cx = c % nx, ry = r / nx, rx = r % nx;
+    const double d = (cy != ry && cx != rx) ? ddiag : (cy != ry ? dy : dx);
+    const double area = (double)count[c] * dxdy;
+    const double kc = Kfield ? Kfield[c] : K;
+    const double uc = Ufield ? Ufield[c] * dt : udt;
+    if (nexp == 1.0) {
+      const double am = (m == 0.5) ? sqrt(area) : pow(area, m);
+      const double f = ((kc * dt) * am) / d;
+      if (f > 0.0) h[c] = h[r] + uc / f;
+    } else {
+      const double f = ((kc * dt) * pow(area, m)) / pow(d, nexp);
+      if (f > 0.0) h[c] = h[r] + pow(uc / f, 1.0 / nexp);
+    }
+  }
+}
+
 /* Step 4, Algorithm 3 ("Generate Queue") for a general forest given by rec[]
  * (rec[c] == c marks a cell without receiver) and donor lists: the cells
  * without receiver form the first level; then the donors of each level, in
@@ -401,6 +437,35 @@ int lemo_run(const lemo_params* p, double* h, const double* K, const double* U,
   if (st == LEMO_OK && steps > 0)
     lemo_export(n, &w, rec_out, depth_out, count_out, offsets_out, offsets_cap,
                 nlevels_out);
+  lemo_work_free(&w);
+  return st;
+}
+
+/* `iters` steady-state projections: receivers from the current heights,
+ * donors, order and counts as in a step, uplift, then lemo_project_heights.
+ * Routing of the last one is exported as by lemo_run. */
+int lemo_project(const lemo_params* p, double* h, const double* K, const double* U,
+                 int64_t iters, int32_t* rec_out, int32_t* depth_out, uint32_t* count_out) {
+  int st = lemo_check(p);
+  if (st != LEMO_OK) return st;
+  if (!h || iters < 0) return LEMO_E_ARG;
+  const int64_t n = (int64_t)p->ny * p->nx;
+  struct lemo_work w;
+  if (lemo_work_alloc(&w, n) != LEMO_OK) return LEMO_E_ALLOC;
+  for (int64_t s = 0; s < iters && st == LEMO_OK; ++s) {
+    lemo_receivers(p->ny, p->nx, p->dx, p->dy, h, w.rec);
+    lemo_donors(p->ny, p->nx, w.rec, w.donor, w.dnum);
+    if (lemo_stack_order(n, w.rec, w.donor, w.dnum, w.order, w.depth, w.stack) != n) {
+      st = LEMO_E_CYCLE;
+      break;
+    }
+    lemo_accumulate(n, w.order, w.donor, w.dnum, w.count);
+    lemo_uplift(p->ny, p->nx, p->dt, p->U, U, h);
+    lemo_project_heights(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->n, p->U, U, p->K, K,
+                         w.rec, w.count, w.order, h);
+  }
+  if (st == LEMO_OK && iters > 0)
+    lemo_export(n, &w, rec_out, depth_out, count_out, NULL, 0, NULL);
   lemo_work_free(&w);
   return st;
 }

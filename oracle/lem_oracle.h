@@ -55,6 +55,15 @@ int64_t lemo_graph_order(int64_t n, const int32_t* rec, int32_t* donor, uint8_t*
 int lemo_run(const lemo_params* p, double* h, const double* K, const double* U,
              int64_t steps, int32_t* rec_out, int32_t* depth_out, uint32_t* count_out,
              int64_t* offsets_out, int64_t offsets_cap, int64_t* nlevels_out);
+/* Steady-state projection: h_c = h_r + U_c*dt/F (n = 1), h_r + (U_c*dt/F)^(1/n)
+ * otherwise, for every cell with a receiver, in receiver-first order. */
+void lemo_project_heights(int32_t ny, int32_t nx, double dx, double dy, double dt,
+                          double m, double nexp, double U, const double* Ufield, double K,
+                          const double* Kfield, const int32_t* rec, const uint32_t* count,
+                          const int32_t* order, double* h);
+/* `iters` projections, each from the routing of the current heights. */
+int lemo_project(const lemo_params* p, double* h, const double* K, const double* U,
+                 int64_t iters, int32_t* rec_out, int32_t* depth_out, uint32_t* count_out);
 int lemo_run_fixed_routing(const lemo_params* p, double* h, const int32_t* rec,
                            const double* K, const double* U, int64_t steps,
                            int32_t* depth_out, uint32_t* count_out);

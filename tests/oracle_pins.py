@@ -579,6 +579,73 @@ def pin_mfd_without_erosion_is_pure_uplift(lib):
     assert np.allclose(got, ref, rtol=0, atol=1e-12)
 
 
+def pin_projection_solves_the_steady_equation(lib):
+    """One steady-state projection with fields: every cell with a receiver
+    satisfies F (h_c - h_r)^n = U_c dt with the routing of the heights it
+    started from and F of Algorithm 6, each receiver's new height on the
+    right; cells without a receiver are only uplifted."""
+    ny, nx = 23, 31
+    rng = np.random.default_rng(11)
+    h0 = W.initial_heights(ny, nx, 5) * 7.0
+    K = 1e-5 * np.exp(0.5 * rng.standard_normal((ny, nx)))
+    U = rng.uniform(1e-4, 2e-3, (ny, nx))
+    for nexp in (1.0, 1.5):
+        p = oracle.Params(ny, nx, 100.0, 70.0, 1e4, 0.45, nexp, 0.0, 1e-5)
+        r0 = oracle.routing(h0, p, lib=lib)
+        out = oracle.project(h0, p, 1, K=K, U=U, lib=lib)
+        assert np.array_equal(out["rec"], r0["rec"])
+        rec, cnt = r0["rec"].ravel(), r0["count"].ravel()
+        a, b = out["h"].ravel(), h0.ravel()
+        checked = 0
+        for c in range(a.size):
+            y, x = divmod(c, nx)
+            if not (0 < y < ny - 1 and 0 < x < nx - 1):
+                assert a[c] == b[c]
+                continue
+            udt = U.ravel()[c] * p.dt
+            if rec[c] == c:
+                assert a[c] == b[c] + udt
+                continue
+            d = _dist(c, rec[c], nx, p.dx, p.dy)
+            F = K.ravel()[c] * p.dt * (cnt[c] * p.dx * p.dy) ** p.m / d ** nexp
+            lhs = F * (a[c] - a[rec[c]]) ** nexp
+            assert abs(lhs - udt) <= 1e-11 * udt, (nexp, c, lhs, udt)
+            checked += 1
+        assert checked > 0.8 * (ny - 2) * (nx - 2)
+
+
+def pin_projection_fixed_point_is_a_steady_state(lib):
+    """Repeated projections from a noisy cone stop changing; the result obeys
+    the slope-area law S = (U/K) A^-m on every interior cell and one step of
+    the method (uplift and implicit erosion) leaves it unchanged."""
+    ny = nx = 24
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    cone = np.minimum.reduce([yy, xx, ny - 1 - yy, nx - 1 - xx]).astype(np.float64)
+    h = cone + 0.3 * np.random.default_rng(4).random((ny, nx))
+    h[0, :] = h[-1, :] = h[:, 0] = h[:, -1] = 0.0
+    U, K, m, dx = 1e-3, 2e-5, 0.45, 30.0
+    p = oracle.Params(ny, nx, dx, dx, 5e3, m, 1.0, U, K)
+    for _ in range(400):
+        nxt = oracle.project(h, p, 1, lib=lib)["h"]
+        change = np.abs(nxt - h).max() / np.abs(nxt).max()
+        h = nxt
+        if change == 0.0:
+            break
+    assert change == 0.0, change
+    r = oracle.routing(h, p, lib=lib)
+    rec, cnt, hf = r["rec"].ravel(), r["count"].ravel(), h.ravel()
+    for c in range(hf.size):
+        y, x = divmod(c, nx)
+        if not (0 < y < ny - 1 and 0 < x < nx - 1):
+            continue
+        assert rec[c] != c, "an interior sink survived"
+        S = (hf[c] - hf[rec[c]]) / _dist(c, rec[c], nx, dx, dx)
+        law = (U / K) * (cnt[c] * dx * dx) ** (-m)
+        assert abs(S - law) <= 1e-9 * law, (c, S, law)
+    stepped = oracle.run(h, p, 1, lib=lib)["h"]
+    assert np.abs(stepped - h).max() <= 1e-12 * np.abs(h).max()
+
+
 ALL_PINS = [pin_table1, pin_receivers_special_cases, pin_receivers_brute_force,
             pin_levels_and_areas_brute_force, pin_forest_invariants, pin_one_step_dense_solve,
             pin_no_erosion_is_pure_uplift, pin_long_step_follows_receiver,
@@ -587,4 +654,6 @@ ALL_PINS = [pin_table1, pin_receivers_special_cases, pin_receivers_brute_force,
             pin_newton_overshoot_stays_above_receiver, pin_newton_iteration_cap,
             pin_newton_cell_not_above_receiver_keeps_height,
             pin_mfd_area_conservation_and_dense_solve, pin_mfd_levels_are_longest_paths,
-            pin_mfd_step_solves_the_implicit_system, pin_mfd_without_erosion_is_pure_uplift]
+            pin_mfd_step_solves_the_implicit_system, pin_mfd_without_erosion_is_pure_uplift,
+            pin_projection_solves_the_steady_equation,
+            pin_projection_fixed_point_is_a_steady_state]

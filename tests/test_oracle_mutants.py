@@ -60,6 +60,17 @@ MUTANTS = [
     ("Newton erodes a cell not above its receiver", "if (h0 - hn > 0.0) {", "if (1) {"),
     ("MFD shares not normalised", "pexp) / wsum[d];", "pexp);"),
     ("MFD erosion with the old receiver height", "sumfh += f * h[r];", "sumfh += f * h0[r];"),
+    ("projection multiplies by F", "if (f > 0.0) h[c] = h[r] + uc / f;",
+     "if (f > 0.0) h[c] = h[r] + uc * f;"),
+    ("projection with the exponent n, not 1/n", "h[r] + pow(uc / f, 1.0 / nexp)",
+     "h[r] + pow(uc / f, nexp)"),
+    ("projection ignores the U field", "const double uc = Ufield ? Ufield[c] * dt : udt;",
+     "const double uc = udt;"),
+    ("projection without uplift of sinks",
+     "lemo_uplift(p->ny, p->nx, p->dt, p->U, U, h);\n    lemo_project_heights",
+     "lemo_project_heights"),
+    ("projection measures the slope to the old receiver height",
+     "if (f > 0.0) h[c] = h[r] + uc / f;", "if (f > 0.0) h[c] = h[c] + uc / f;"),
     ("MFD levels by the shallowest receiver", "if (h0[c] - h0[r] > 0.0 && level[r] + 1 > l) l = level[r] + 1;",
      "if (h0[c] - h0[r] > 0.0 && (l == 0 || level[r] + 1 < l)) l = level[r] + 1;"),
 ]
