@@ -256,6 +256,22 @@ lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
                                    const double* d_U, double rtol, int64_t check_every,
                                    int64_t max_steps, int64_t* h_steps);
 
+/* As lem_batch_run_to_steady, with steady-state projections in place of
+ * time steps (an accelerator of runs to steady state, not part of the paper's
+ * method).  A projection computes the routing of the current heights as a
+ * step does (Steps 2-5), uplifts cells without a receiver (Step 6), and gives
+ * every cell with a receiver, in level order, the height at which the
+ * implicit update of Step 7 would leave it unchanged given its receiver's
+ * new height: h_r + U*dt/F for n = 1, h_r + (U*dt/F)^(1/n) otherwise (F as in
+ * Algorithm 6; F = 0 keeps the uplifted height).  Once the routing stops
+ * changing the heights are a steady state of the method, which a following
+ * lem_batch_run_to_steady confirms in a few steps.  h_iters receives the
+ * projections each grid took (-1: not converged within max_iters).
+ * LEM_E_ARG on a multiple-flow-direction context. */
+lem_status lem_batch_project_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
+                                       const double* d_U, double rtol, int64_t check_every,
+                                       int64_t max_iters, int64_t* h_iters);
+
 /* lem_routing for grid `grid` of the batch (after lem_batch_run); d_rec,
  * d_depth and d_count hold that grid's cells only and indices are local to
  * the grid. */

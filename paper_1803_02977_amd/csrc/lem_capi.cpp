@@ -412,6 +412,10 @@ lem_status routing_impl(lem_ctx* ctx, int32_t g, int32_t* d_rec, int32_t* d_dept
   return LEM_OK;
 }
 
+lem_status steady_impl(lem_ctx* ctx, double* d_h, const double* d_K, const double* d_U,
+                       double rtol, int64_t check_every, int64_t max_steps, int64_t* h_steps,
+                       bool project);
+
 }  // namespace
 
 extern "C" {
@@ -494,6 +498,25 @@ lem_status lem_batch_run(lem_ctx* ctx, double* d_h, const double* d_K, const dou
 lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
                                    const double* d_U, double rtol, int64_t check_every,
                                    int64_t max_steps, int64_t* h_steps) {
+  return steady_impl(ctx, d_h, d_K, d_U, rtol, check_every, max_steps, h_steps, false);
+}
+
+lem_status lem_batch_project_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
+                                       const double* d_U, double rtol, int64_t check_every,
+                                       int64_t max_iters, int64_t* h_iters) {
+  if (ctx && ctx->mfd) return fail(ctx, LEM_E_ARG, "projection needs a D8 context");
+  return steady_impl(ctx, d_h, d_K, d_U, rtol, check_every, max_iters, h_iters, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Runs to steady state: time steps of the method, or (project) steady-state
+// projections, until each grid changes by at most rtol of its largest height.
+lem_status steady_impl(lem_ctx* ctx, double* d_h, const double* d_K, const double* d_U,
+                       double rtol, int64_t check_every, int64_t max_steps, int64_t* h_steps,
+                       bool project) {
   if (!ctx) return LEM_E_ARG;
   if (!d_h || !h_steps) return fail(ctx, LEM_E_ARG, "d_h and h_steps must not be NULL");
   if (!(rtol > 0.0) || check_every < 1 || max_steps < 1)
@@ -516,6 +539,7 @@ lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
     }
   }
   lem::StepArgs a = make_args(ctx, d_K, d_U);
+  a.project = project ? 1 : 0;
   e = lem::launch_begin_run(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "begin-run launch");
   const bool timers = (ctx->flags & LEM_F_PHASE_TIMERS) != 0;
@@ -611,6 +635,10 @@ lem_status lem_batch_run_to_steady(lem_ctx* ctx, double* d_h, const double* d_K,
   ctx->last_run_steps = s;
   return LEM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 lem_status lem_run_fixed_routing(lem_ctx* ctx, double* d_h, const uint8_t* d_rcode,
                                  const double* d_K, const double* d_U, int64_t steps) {

@@ -175,7 +175,7 @@ struct StepArgs {
   int32_t mfd;           // multiple flow directions (single grid)
   int32_t chunked;       // crossing trees go through the chunk stage first
   int32_t chunk_roots;   // roots per chunk of that stage
-  int32_t pad2;
+  int32_t project;       // steady-state projection instead of the implicit update
   double mfd_p;          // exponent of the slope in the flow shares
 };
 

@@ -239,13 +239,30 @@ __device__ __forceinline__ double eroded_height(const GridDev& G, double h0, dou
   return G.newton ? newton_height(h0, hr, f, G.nexp, G.eps, G.max_newton) : (h0 + f * hr) / g;
 }
 
+// Steady-state projection of one cell (an accelerator of runs to steady
+// state, not part of a time step of the method): the height at which the
+// implicit update leaves the cell unchanged given its receiver's new height
+// hr, F (h - hr)^n = udt (udt = U*dt of the cell): hr + udt/F for n = 1,
+// hr + (udt/F)^(1/n) otherwise.  F = 0 keeps the uplifted height h0.
+__device__ __forceinline__ double steady_height(const GridDev& G, double h0, double hr, double f,
+                                                double udt) {
+  if (!(f > 0.0)) return h0;
+  return G.newton ? hr + pow(udt / f, 1.0 / G.nexp) : hr + udt / f;
+}
+
+// Step 7, or the projection, for one cell.
+__device__ __forceinline__ double new_height(const GridDev& G, bool project, double h0, double hr,
+                                             double f, double g, double udt) {
+  return project ? steady_height(G, h0, hr, f, udt) : eroded_height(G, h0, hr, f, g);
+}
+
 // Step 7 for one cell of grid gi in full generality (per-cell K, counts past
 // the tables, n != 1): erosion_factor and eroded_height in one out-of-line
 // call, for kernels whose common case reads F from a table in LDS.
 __device__ __noinline__ double eroded_height_general(const GridDev* grids, int gi,
                                                      const double* Kf, const double* amtab,
                                                      uint32_t count, int k, int64_t c, double h0,
-                                                     double hr) {
+                                                     double hr, int project, double udt) {
   const GridDev& G = grids[gi];
   const int cls = code_class(k);
   const double d = cls == 0 ? G.dn[0] : (cls == 1 ? G.dn[1] : G.dn[2]);
@@ -254,7 +271,7 @@ __device__ __noinline__ double eroded_height_general(const GridDev* grids, int g
   const double kc = Kf ? Kf[c] : G.K;
   const double f = ((kc * G.dt) * am) / d;
   const double g = 1.0 + f;
-  return G.newton ? newton_height(h0, hr, f, G.nexp, G.eps, G.max_newton) : (h0 + f * hr) / g;
+  return new_height(G, project != 0, h0, hr, f, g, udt);
 }
 
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
@@ -777,14 +794,20 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
         if (l == 1 && rc[u] == kSink)  // the receiver is an interior root: add its uplift
           hr = hr + (a.Uf ? a.Uf[c + neighbour_offset(code, nx)] * G.dt : G.udt);
         const uint32_t count = (clw[li >> 1] >> ((li & 1) * 16)) & 0xFFFFu;
-        const double h0 = hs[li] + (a.Uf ? a.Uf[c] * G.dt : G.udt);
+        const double udt = a.Uf ? a.Uf[c] * G.dt : G.udt;
+        const double h0 = hs[li] + udt;
         double hn;
         if (table_f && count < (uint32_t)kAmTab) {
           const double f = ftl[code_class(code) * kAmTab + count];
-          const double g = 1.0 + f;
-          hn = (h0 + f * hr) / g;
+          if (a.project) {
+            hn = f > 0.0 ? hr + udt / f : h0;
+          } else {
+            const double g = 1.0 + f;
+            hn = (h0 + f * hr) / g;
+          }
         } else {
-          hn = eroded_height_general(a.grids, gi, a.Kf, w.amtab, count, code, c, h0, hr);
+          hn = eroded_height_general(a.grids, gi, a.Kf, w.amtab, count, code, c, h0, hr,
+                                     a.project, udt);
         }
         hs[li] = hn;
       }
@@ -978,8 +1001,9 @@ __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32
     const double hr = w.hq[w.par[i]];
     double f, g;
     erosion_factor(a, G, gi, w.cnt[i], w.kq[i], c, &f, &g);
-    const double h0 = a.h_in[c] + (a.Uf ? a.Uf[c] * G.dt : G.udt);
-    const double hn = eroded_height(G, h0, hr, f, g);
+    const double udt = a.Uf ? a.Uf[c] * G.dt : G.udt;
+    const double h0 = a.h_in[c] + udt;
+    const double hn = new_height(G, a.project != 0, h0, hr, f, g, udt);
     w.hq[i] = hn;
     a.h_out[c] = hn;
   }
@@ -1514,7 +1538,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_trees(StepArgs a) {
           const GridDev& G = a.grids[gi];
           double f, g;
           erosion_factor(a, G, gi, count, s_k[i], c, &f, &g);
-          hn = eroded_height(G, hn, s_h[s_par[i]], f, g);
+          const double udt = a.Uf ? a.Uf[c] * G.dt : G.udt;
+          hn = new_height(G, a.project != 0, hn, s_h[s_par[i]], f, g, udt);
           s_h[i] = hn;
         }
         a.h_out[c] = hn;

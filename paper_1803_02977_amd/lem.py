@@ -21,7 +21,8 @@ LEM_F_VALIDATE, LEM_F_PHASE_TIMERS = 0x1, 0x2
 # Symbols declared in include/lem.h.
 EXPORTS = ("lem_workspace_bytes", "lem_create", "lem_run", "lem_run_fixed_routing",
            "lem_sync", "lem_routing", "lem_batch_workspace_bytes", "lem_batch_create",
-           "lem_batch_run", "lem_batch_run_to_steady", "lem_batch_routing",
+           "lem_batch_run", "lem_batch_run_to_steady", "lem_batch_project_to_steady",
+           "lem_batch_routing",
            "lem_level_history", "lem_stats", "lem_set_tuning", "lem_get_tuning", "lem_destroy",
            "lem_status_str", "lem_last_error", "lem_mfd_workspace_bytes", "lem_mfd_create",
            "lem_mfd_export")
@@ -103,6 +104,9 @@ def load(path: str = LIB_PATH):
     lib.lem_batch_run.restype = C.c_int
     lib.lem_batch_run_to_steady.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int64, C.c_int64, _P]
     lib.lem_batch_run_to_steady.restype = C.c_int
+    lib.lem_batch_project_to_steady.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int64,
+                                                C.c_int64, _P]
+    lib.lem_batch_project_to_steady.restype = C.c_int
     lib.lem_batch_routing.argtypes = [_P, C.c_int32, _P, _P, _P, _P, C.c_int64,
                                       C.POINTER(C.c_int64)]
     lib.lem_batch_routing.restype = C.c_int
@@ -210,6 +214,16 @@ def lem_batch_run_to_steady(ctx: int, d_h: int, d_K, d_U, rtol: float, check_eve
            else np.ascontiguousarray(steps_in, np.int64).copy())
     _check(load().lem_batch_run_to_steady(ctx, d_h, d_K, d_U, rtol, check_every, max_steps,
                                           out.ctypes.data_as(_P)), ctx)
+    return out
+
+
+def lem_batch_project_to_steady(ctx: int, d_h: int, d_K, d_U, rtol: float, check_every: int,
+                                max_iters: int, count: int, iters_in=None):
+    import numpy as np
+    out = (np.full(count, -1, np.int64) if iters_in is None
+           else np.ascontiguousarray(iters_in, np.int64).copy())
+    _check(load().lem_batch_project_to_steady(ctx, d_h, d_K, d_U, rtol, check_every, max_iters,
+                                              out.ctypes.data_as(_P)), ctx)
     return out
 
 
@@ -460,6 +474,18 @@ class Batch:
             if progress:
                 progress(done, int((total >= 0).sum()))
         return total
+
+    def project_to_steady(self, h, rtol=1e-6, check_every=10, max_iters=100000, K=None, U=None):
+        """Steady-state projections until every grid changes by at most rtol
+        of its largest height (lem_batch_project_to_steady); returns the
+        projections per grid (-1: not converged)."""
+        self._check_h(h)
+        for f in (K, U):
+            if f is not None:
+                self._check_h(f)
+        return lem_batch_project_to_steady(self.ctx, h.data_ptr(), _dptr(K), _dptr(U),
+                                           float(rtol), int(check_every), int(max_iters),
+                                           len(self.descs))
 
     def sync(self):
         lem_sync(self.ctx)

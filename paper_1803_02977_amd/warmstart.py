@@ -54,9 +54,13 @@ def _grids(u, ny, nx, dt):
 
 
 def steady_states(K, U, h0, dt=GEN_DT, check_every=10, max_steps=200000, chunk=None,
-                  label="steady"):
+                  label="steady", project=False, stats=None):
     """Runs the batch solver from h0 (device tensors [n, ny, nx]) with the K
-    and U fields until every grid is steady; returns (h, steps per grid)."""
+    and U fields until every grid is steady; returns (h, steps per grid).
+    With ``project`` the run starts with steady-state projections until they
+    stop changing the heights (lem_batch_project_to_steady), then the
+    method's steps confirm the steady state; ``stats`` (a dict) receives the
+    projections per grid and the seconds of both parts."""
     import torch
     n, ny, nx = K.shape
     b = Batch(_grids(U[:, 0, 0].cpu().numpy(), ny, nx, dt), device=K.device)
@@ -66,9 +70,21 @@ def steady_states(K, U, h0, dt=GEN_DT, check_every=10, max_steps=200000, chunk=N
     def progress(done, conv):
         _log(f"{label}: {done} steps, {conv}/{n} grids steady, {time.perf_counter() - t0:.1f} s")
 
+    if project:
+        its = b.project_to_steady(h, rtol=RTOL, check_every=check_every, max_iters=max_steps,
+                                  K=K.reshape(-1), U=U.reshape(-1))
+        torch.cuda.synchronize()
+        if stats is not None:
+            stats["projections"] = its
+            stats["project_s"] = time.perf_counter() - t0
+        _log(f"{label}: projections done ({int(np.max(its))} at most), "
+             f"{time.perf_counter() - t0:.1f} s")
+    t1 = time.perf_counter()
     steps = b.run_to_steady(h, rtol=RTOL, check_every=check_every, max_steps=max_steps,
                             K=K.reshape(-1), U=U.reshape(-1), chunk=chunk, progress=progress)
     torch.cuda.synchronize()
+    if stats is not None:
+        stats["steps_s"] = time.perf_counter() - t1
     b.close()
     return h.reshape(K.shape), steps
 
@@ -193,14 +209,17 @@ def predict(net, K, U, h0, batch):
 
 
 def evaluate(net, grids, first_seed=W.WARMSTART_TEST_SEED, batch=16, dt=DT, check_every=10,
-             max_steps=200000, chunk=2000, device="cuda:0", slots=None, plain_sample=0):
+             max_steps=200000, chunk=2000, device="cuda:0", slots=None, plain_sample=0,
+             project=False):
     """Steps and device time to steady state from the noise surface (cold)
     and from the network's prediction (warm), on held-out realizations, with
     the same solver, dt and stopping rule.  slots=None runs all realizations
     as one batch (time = slowest realization); otherwise a batch of `slots`
     grids is refilled as realizations converge (steady_states_queue).
     plain_sample > 0 also runs that many realizations from the noise surface
-    one after another through the single-grid path (the plain solver)."""
+    one after another through the single-grid path (the plain solver).
+    project=True also times both starts with steady-state projections before
+    the steps (one batch)."""
     import torch
     dev = torch.device(device)
     K, U, h0 = make_dataset(grids, first_seed, dev)
@@ -237,7 +256,27 @@ def evaluate(net, grids, first_seed=W.WARMSTART_TEST_SEED, batch=16, dt=DT, chec
                  "s_per_realization": t_plain / plain_sample,
                  "steps_match_batch": ps == [int(v) for v in s_cold[:plain_sample]]}
     rel = lambda a, b: float((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item())
+    projected = None
+    if project:
+        projected = {}
+        for label, h_start, extra in (("cold", h0, 0.0), ("warm", hp, t_pred)):
+            st = {}
+            t = time.perf_counter()
+            h_fin, s_fin = steady_states(K, U, h_start, dt=dt, check_every=check_every,
+                                         max_steps=max_steps, chunk=chunk,
+                                         label=f"{label}+projection", project=True, stats=st)
+            total = time.perf_counter() - t + extra
+            its = st["projections"]
+            projected[label] = {
+                "s": total, "project_s": st["project_s"], "steps_s": st["steps_s"],
+                "projections_mean": float(np.mean(its)), "projections_max": int(np.max(its)),
+                "steps_after_mean": float(np.mean(s_fin)), "steps_after_max": int(np.max(s_fin)),
+                "all_converged": bool((its >= 0).all() and (s_fin >= 0).all()),
+                "rel_l2_vs_cold_steady": rel(h_fin, h_cold)}
+        projected["time_ratio_warm_over_cold"] = projected["warm"]["s"] / projected["cold"]["s"]
+        projected["time_ratio_warm_projected_over_cold_steps"] = projected["warm"]["s"] / t_cold
     return {
+        "projected": projected,
         "plain": plain,
         "grids": grids, "side": int(K.shape[1]), "dt": dt, "rtol": RTOL,
         "check_every": check_every,
