@@ -7,14 +7,15 @@ arrays and drives the loops.
     python -m paper_1803_02977_amd.warmstart train --samples 20000 --out weights.npz
     python -m paper_1803_02977_amd.warmstart evaluate --weights weights.npz --grids 100
 
-Training targets are steady states of the solver (runs stepped until no cell
-changes by more than 1e-6 of the grid's largest height in one step) from
-seeded (K, U, h0) realizations.  At a steady state every slope equals
-(U/K) A^-m whatever the time step, so targets are generated with a long step
-(``GEN_DT``) that gets there in about a tenth of the steps; the time step
-only changes which of the equally valid drainage networks forms.  The
-evaluation runs both the cold and the warm start at the workload's own
-dt = 1000 yr.
+Training targets are steady states of the solver (no cell changes by more
+than 1e-6 of the grid's largest height in one step) from seeded (K, U, h0)
+realizations at the workload's dt = 1000 yr.  They are reached by
+steady-state projections (every cell set to where the implicit update leaves
+it, given the routing of the current heights; lem_batch_project_to_steady)
+until the heights stop changing, then confirmed by the method's own steps;
+``--gen steps`` uses steps alone.  The evaluation times, on held-out
+realizations, the cold start (noise surface) and the warm start (the
+network's prediction), each by steps alone and by projections then steps.
 """
 from __future__ import annotations
 
@@ -38,7 +39,6 @@ from .surrogate import Surrogate, init_params, load_params, save_params  # noqa:
 DX = 100.0
 M = 0.5
 DT = 1000.0
-GEN_DT = 1e4
 RTOL = 1e-6
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_weights.npz")
 
@@ -53,7 +53,7 @@ def _grids(u, ny, nx, dt):
     return [W.Realization(ny, nx, DX, DX, dt, M, float(v), 1e-5, 0) for v in u]
 
 
-def steady_states(K, U, h0, dt=GEN_DT, check_every=10, max_steps=200000, chunk=None,
+def steady_states(K, U, h0, dt=DT, check_every=10, max_steps=200000, chunk=None,
                   label="steady", project=False, stats=None):
     """Runs the batch solver from h0 (device tensors [n, ny, nx]) with the K
     and U fields until every grid is steady; returns (h, steps per grid).
@@ -170,15 +170,27 @@ def make_dataset(count, first_seed, device, piece=1000):
     return K, U, h0
 
 
-def train(net, K, U, h0, target, epochs, batch, lr, lr_min, seed=0, log_every=200):
+def validation_loss(net, K, U, h0, target, batch):
+    """Mean loss over held-out samples (whole batches only)."""
+    n = (K.shape[0] // batch) * batch
+    acc = 0.0
+    for i in range(0, n, batch):
+        loss, _ = net.loss_grad(K[i:i + batch].contiguous(), U[i:i + batch].contiguous(),
+                                h0[i:i + batch].contiguous(), target[i:i + batch].contiguous())
+        acc += loss
+    return acc / max(n // batch, 1)
+
+
+def train(net, K, U, h0, target, epochs, batch, lr, lr_min, seed=0, log_every=200, val=None):
     """Adam with a cosine learning-rate decay over all steps; returns the
-    per-epoch mean losses."""
+    per-epoch mean losses (and, with val = (K, U, h0, target) of held-out
+    samples, their loss after each epoch)."""
     import torch
     n = K.shape[0]
     rng = np.random.default_rng(seed)
     per_epoch = n // batch
     total = epochs * per_epoch
-    losses = []
+    losses, val_losses = [], []
     step = 0
     t0 = time.perf_counter()
     for ep in range(epochs):
@@ -195,8 +207,12 @@ def train(net, K, U, h0, target, epochs, batch, lr, lr_min, seed=0, log_every=20
                 _log(f"epoch {ep} step {step}/{total} loss {loss:.5f} lr {lr_t:.2e} "
                      f"{time.perf_counter() - t0:.1f} s")
         losses.append(acc / per_epoch)
-        _log(f"epoch {ep} mean loss {losses[-1]:.5f}")
-    return losses
+        if val is not None:
+            val_losses.append(validation_loss(net, *val, batch))
+            _log(f"epoch {ep} mean loss {losses[-1]:.5f}, held-out loss {val_losses[-1]:.5f}")
+        else:
+            _log(f"epoch {ep} mean loss {losses[-1]:.5f}")
+    return (losses, val_losses) if val is not None else losses
 
 
 def predict(net, K, U, h0, batch):
@@ -306,7 +322,11 @@ def main():
     t.add_argument("--batch", type=int, default=16)
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--lr-min", type=float, default=5e-5)
-    t.add_argument("--gen-dt", type=float, default=GEN_DT)
+    t.add_argument("--gen-dt", type=float, default=DT)
+    t.add_argument("--gen", choices=("project", "steps"), default="project",
+                   help="targets: fixed points of steady-state projections (then confirmed by "
+                        "steps), or runs of steps alone")
+    t.add_argument("--val", type=int, default=1000, help="held-out samples for the validation loss")
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--out", default=WEIGHTS_PATH)
     t.add_argument("--report", default=None)
@@ -320,30 +340,42 @@ def main():
     report = {}
     if args.cmd == "train":
         t0 = time.perf_counter()
-        K, U, h0 = make_dataset(args.samples, W.WARMSTART_TRAIN_SEED, dev)
-        _log(f"inputs for {args.samples} realizations on the device, "
-             f"{time.perf_counter() - t0:.1f} s")
+        total = args.samples + args.val
+        # Training seeds, then the validation seeds right after them (the
+        # evaluation's held-out seeds start far above both).
+        K, U, h0 = make_dataset(total, W.WARMSTART_TRAIN_SEED, dev)
+        _log(f"inputs for {total} realizations on the device, {time.perf_counter() - t0:.1f} s")
         t0 = time.perf_counter()
-        hs, steps = steady_states(K, U, h0, dt=args.gen_dt, chunk=200, label="data")
+        st = {}
+        hs, steps = steady_states(K, U, h0, dt=args.gen_dt, chunk=200, label="data",
+                                  project=args.gen == "project", stats=st)
         t_gen = time.perf_counter() - t0
-        ok = steps >= 0
-        _log(f"steady states: {int(ok.sum())}/{args.samples} converged, mean {steps[ok].mean():.0f} "
-             f"steps, {t_gen:.1f} s")
-        idx = torch.from_numpy(np.nonzero(ok)[0]).to(dev)
-        K, U, h0, hs = K[idx], U[idx], h0[idx], hs[idx]
+        its = st.get("projections", np.zeros_like(steps))
+        ok = (steps >= 0) & (its >= 0)
+        _log(f"steady states: {int(ok.sum())}/{total} converged, mean {steps[ok].mean():.0f} "
+             f"steps after {its[ok].mean():.0f} projections, {t_gen:.1f} s")
+        tr = np.nonzero(ok[:args.samples])[0]
+        va = args.samples + np.nonzero(ok[args.samples:])[0]
+        sel = lambda idx: tuple(a[torch.from_numpy(idx).to(dev)] for a in (K, U, h0, hs))
+        Kt, Ut, h0t, hst = sel(tr)
+        val = sel(va) if len(va) else None
+        del K, U, h0, hs
         net = Surrogate(args.batch, side, side, device=dev)
         net.set_params(init_params(args.seed))
         t0 = time.perf_counter()
-        losses = train(net, K, U, h0, hs, args.epochs, args.batch, args.lr, args.lr_min,
-                       seed=args.seed)
+        out = train(net, Kt, Ut, h0t, hst, args.epochs, args.batch, args.lr, args.lr_min,
+                    seed=args.seed, val=val)
+        losses, val_losses = out if val is not None else (out, [])
         t_train = time.perf_counter() - t0
         p = net.get_params().cpu().numpy()
         save_params(args.out, p)
-        report = {"samples": args.samples, "converged": int(ok.sum()), "gen_dt": args.gen_dt,
+        report = {"samples": args.samples, "validation_samples": int(len(va)),
+                  "converged": int(ok.sum()), "gen": args.gen, "gen_dt": args.gen_dt,
+                  "gen_projections_mean": float(its[ok].mean()),
                   "gen_steps_mean": float(steps[ok].mean()), "gen_s": t_gen,
                   "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
-                  "epoch_losses": losses, "train_s": t_train,
-                  "train_steps_per_s": args.epochs * (int(ok.sum()) // args.batch) / t_train}
+                  "epoch_losses": losses, "validation_losses": val_losses, "train_s": t_train,
+                  "train_steps_per_s": args.epochs * (len(tr) // args.batch) / t_train}
         _log(json.dumps(report))
     else:
         net = Surrogate(16, side, side, device=dev)

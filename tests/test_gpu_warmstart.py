@@ -1,10 +1,12 @@
 """GPU: what the trained warm start gains.  Held-out realizations (seeds not
 used in training) are run to steady state (no cell changes by more than
-1e-6 of the grid's largest height in one step) at dt = 1000 yr twice with
-the same batch solver: from the noise surface (cold) and from the network's
-prediction (warm).  The warm runs must converge and take fewer steps in
-total; the prediction must also be far closer to the cold run's steady state
-than the noise surface is."""
+1e-6 of the grid's largest height in one step) at dt = 1000 yr with the same
+batch solver from the noise surface (cold) and from the network's prediction
+(warm), by the method's steps alone and by steady-state projections followed
+by steps.  Warm runs must converge in fewer steps, and fewer projections, in
+total and for the slowest grid (which sets a batch's time); the prediction
+must also be far closer to the cold run's steady state than the noise
+surface is."""
 from __future__ import annotations
 
 import os
@@ -26,11 +28,20 @@ def test_warm_start_reaches_steady_state_in_fewer_steps():
     print("[gpu] warm start: 4 held-out 256x256 grids, cold and warm", flush=True)
     net = Surrogate(4, 256, 256, device=torch.device("cuda:0"))
     net.set_params(load_params(WS.WEIGHTS_PATH))
-    r = WS.evaluate(net, 4, batch=4, chunk=4000)
+    r = WS.evaluate(net, 4, batch=4, chunk=4000, project=True)
     net.close()
-    print(f"[gpu] cold {r['cold_steps']} warm {r['warm_steps']}", flush=True)
-    assert r["all_converged"]
+    pc, pw = r["projected"]["cold"], r["projected"]["warm"]
+    print(f"[gpu] steps cold {r['cold_steps']} warm {r['warm_steps']}; projections cold "
+          f"{pc['projections_mean']}/{pc['projections_max']} warm "
+          f"{pw['projections_mean']}/{pw['projections_max']}; seconds {r['cold_s']:.2f} "
+          f"{r['warm_s']:.2f} {pc['s']:.3f} {pw['s']:.3f}", flush=True)
+    assert r["all_converged"] and pc["all_converged"] and pw["all_converged"]
     assert sum(r["warm_steps"]) < sum(r["cold_steps"]), r
+    assert max(r["warm_steps"]) < max(r["cold_steps"]), r
+    assert pw["projections_mean"] < pc["projections_mean"], r
+    assert pw["projections_max"] < pc["projections_max"], r
+    # Projections and steps end after at most one check of the steps.
+    assert pc["steps_after_max"] <= 10 and pw["steps_after_max"] <= 10, r
     assert r["prediction_rel_l2_vs_cold_steady"] < 0.6 * r["noise_rel_l2_vs_cold_steady"], r
 
 
