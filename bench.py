@@ -142,11 +142,16 @@ SWEEP_REGIONS = (("A", 100, 400, 0.33), ("B", 400, 1000, 0.16), ("C", 1000, 2500
                  ("D", 2500, 16000, 0.92))
 
 
-def _batch_tuning():
-    """The tuned launch settings for a batch of this size (tuning.json)."""
+def _batch_tuning(args):
+    """The tuned launch settings for a batch of this size (tuning.json), with
+    the level pass forced by --level-pass when it is given."""
     from paper_1803_02977_amd import tune
-    t = tune.lookup(sum(r.ny * r.nx for r in W.batch_realizations(512)))
-    return {} if t is None else {"global_workgroups": t[0], "tail_level": t[1]}
+    t = tune.lookup(sum(r.ny * r.nx for r in W.batch_realizations(512)), batch=True) or {}
+    if args.level_pass:
+        t = {**t, "level_pass": args.level_pass}
+        if args.level_pass == 1:
+            t["level_threads"] = 0
+    return t
 
 
 def bench_batch(args):
@@ -162,7 +167,8 @@ def bench_batch(args):
     h0 = torch.from_numpy(W.batch_initial_heights(reals)).to(dev)
     h = h0.clone()
     b = Batch(reals, device=dev)
-    mode = b.set_tuning(**{**_batch_tuning(), "level_pass": args.level_pass})["level_pass"]
+    applied = b.set_tuning(**_batch_tuning(args))
+    mode = applied["level_pass"]
     if args.warmup > 0:
         b.run(h, args.warmup)
         b.sync()
@@ -184,7 +190,7 @@ def bench_batch(args):
     # Kernel times with the library's HIP events on its stream: a second run
     # of the same steps with phase timers (slower by one sync per step).
     bt = Batch(reals, flags=LEM_F_PHASE_TIMERS, device=dev)
-    bt.set_tuning(**{**_batch_tuning(), "level_pass": args.level_pass})
+    bt.set_tuning(**_batch_tuning(args))
     h.copy_(h0)
     bt.run(h, steps)
     bt.sync()
@@ -247,6 +253,13 @@ def bench_batch(args):
         "level_pass": "one workgroup per grid" if mode == 2 else "one device-wide pass",
         "kernel_ms_per_step": {"k_tile_step": tile_ms, "k_chunk_trees": chunk_ms,
                                level_name: level_ms},
+        # Device clock of a tile workgroup, mean over workgroups, per phase.
+        "tile_wg_phase_us_per_step": {
+            k: round(stt.tile_phase_ms[i] / steps * 1e3, 3)
+            for i, k in enumerate(("stage", "receivers", "donors_walks", "clean",
+                                   "erosion", "writeback"))},
+        "levels_max": int(stt.max_nlevels),
+        "tuning": applied,
         "roofline": roof,
     }
     if not args.no_cpu:
@@ -678,6 +691,9 @@ def main():
     # whole grid: trees inside a tile and crossing trees together).
     offsets = solver.routing()["offsets"]
     level_sizes = np.diff(np.asarray(offsets, dtype=np.int64)).tolist()
+    from paper_1803_02977_amd import lem as L
+    tq = L.lem_get_tuning(solver.ctx)
+    applied = {name: getattr(tq, name) for name, _ in L.lem_tuning._fields_}
     solver.close()
 
     # Per-kernel device time, measured live with HIP events on the library's
@@ -762,6 +778,7 @@ def main():
             k: round(st.tile_phase_ms[i] / steps * 1e3, 3)
             for i, k in enumerate(("stage", "receivers", "donors_walks", "clean",
                                    "erosion", "writeback"))},
+        "tuning": applied,
         "crossing_cells_per_step": crossing,
         "crossing_frac": round(crossing / cells, 4),
     }
@@ -781,5 +798,22 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def release_gpu():
+    """Frees what the run still holds on the GPU before the interpreter exits:
+    every library context is closed where it was used; this drops the last
+    tensors and torch's cached blocks so that nothing is torn down by
+    finalizers after a profiler has detached."""
+    if "torch" not in sys.modules:
+        return
+    import gc
+
+    import torch
+    gc.collect()
+    if torch.cuda.is_available() and torch.cuda.is_initialized():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+
 if __name__ == "__main__":
     main()
+    release_gpu()

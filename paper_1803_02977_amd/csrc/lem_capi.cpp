@@ -329,7 +329,7 @@ lem_status create_impl(lem_ctx* ctx, void* d_workspace, size_t ws_bytes, void* h
   int cus = 0, per_cu = 0, rate = 0, per_cu_chunk = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
   if (e == hipSuccess) e = lem::global_kernel_occupancy(&per_cu);
-  if (e == hipSuccess) e = lem::chunk_kernel_occupancy(&per_cu_chunk);
+  if (e == hipSuccess) e = lem::chunk_kernel_occupancy(ng > 1, &per_cu_chunk);
   int per_cu_tile = 0;
   if (e == hipSuccess) e = lem::tile_kernel_occupancy(&per_cu_tile);
   if (e == hipSuccess && ctx->mfd) {

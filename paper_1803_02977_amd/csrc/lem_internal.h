@@ -191,7 +191,7 @@ hipError_t launch_global_levels(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s);
 // Chunk stage of the crossing trees (before the level pass) on `grid` workgroups.
 hipError_t launch_chunk_trees(const StepArgs& a, int grid, hipStream_t s);
-hipError_t chunk_kernel_occupancy(int* blocks_per_cu);
+hipError_t chunk_kernel_occupancy(bool batch, int* blocks_per_cu);
 // Multiple flow directions: routing (weight sums, receiver counters, roots),
 // then levels, areas and heights in one cooperative launch of `grid`
 // workgroups.

@@ -1,35 +1,41 @@
 // lem_kernels.hip -- gfx950 kernels of the landscape-evolution hot path.
 //
-// One time step (Barnes, arXiv:1803.02977, Steps 2 to 7) is two launches.
+// One time step (Barnes, arXiv:1803.02977, Steps 2 to 7) is three launches.
 //
 //  k_tile_step   one workgroup of 512 threads per 64x64 tile.  The tile's heights and a
-//      2-cell halo are staged in LDS once.  In LDS the workgroup computes
-//      Step 2 / Algorithm 1 (receivers) for the tile and its 1-cell ring,
-//      Step 3 / Algorithm 2 (donor masks) for the tile, and the breadth-first
-//      levels of Step 4 / Algorithm 3 restricted to the tile, starting from
-//      every cell without a receiver and from every cell whose receiver lies
-//      outside the tile.  A tree whose root has no receiver and which has no
-//      donor outside the tile is the whole tree of the method: its levels are
-//      its global levels, so the workgroup finishes it in LDS -- Step 5 /
-//      Algorithm 4 (drainage counts, deepest level first) and Steps 6-7 /
-//      Algorithms 5-6 (uplift and the implicit n = 1 update, level by level
-//      from the root) -- and writes the new heights.  Every other tree
-//      ("crossing": it leaves or enters the tile) is handed to the global
-//      pass: its roots are appended to the global queue.  Heights are read
-//      from one buffer and written to the other, so halo reads never see a
-//      neighbouring tile's new values.
+//      2-cell halo are staged in LDS once; each thread owns a vertical strip
+//      of 8 cells of one column.  In LDS the workgroup computes Step 2 /
+//      Algorithm 1 (receivers) for the tile and its 1-cell ring, Step 3 /
+//      Algorithm 2 (donor masks) for the tile, and, by walks down the
+//      receivers, each cell's tile-local root, its depth below that root and
+//      the number of cells upstream of it.  A tree whose root has no
+//      receiver and which has no donor outside the tile is a whole tree of
+//      the method: its depths are its levels (Step 4 / Algorithm 3) and its
+//      counts its drainage areas (Step 5 / Algorithm 4), so the workgroup
+//      finishes it -- uplift and the implicit n = 1 update level by level
+//      from the root (Steps 6-7 / Algorithms 5-6) -- and writes the new
+//      heights.  Every other tree ("crossing": it leaves or enters the tile)
+//      is handed on: its root is queued.  Heights are read from one buffer
+//      and written to the other, so halo reads never see a neighbouring
+//      tile's new values.
 //
-//  k_global_levels   one cooperative (persistent) kernel of at most
-//      kGlobalMaxWGs workgroups of 1024 threads for the crossing trees, with device-side
-//      level loops: breadth-first expansion (a workgroup prefix scan per
-//      chunk and one atomic add per chunk to reserve its output), counts in
-//      reverse level order (each queue position pulls its donors' counts,
-//      which sit contiguously in the next level), then uplift and erosion
-//      from the roots outward (the receiver's new height is read from the
-//      queue-order copy the previous level wrote).  Large levels are shared
-//      by all workgroups and end in a grid-wide barrier; runs of small levels
-//      are done by one workgroup with workgroup barriers only, because a
-//      grid-wide barrier costs far more than a small level's work.
+//  k_chunk_trees   persistent workgroups of 256 threads take chunks of
+//      queued crossing roots from a work counter and carry out Steps 4-7 for
+//      their whole trees in LDS, with workgroup barriers only.  A chunk whose
+//      trees outgrow the stage's capacity (cells or levels) is staged for
+//      the level pass below.
+//
+//  k_global_levels   (one grid) a cooperative kernel of at most kGlobalMaxWGs
+//      workgroups of 1024 threads for the trees the chunk stage handed on,
+//      with device-side level loops: breadth-first expansion (a workgroup
+//      prefix scan per chunk and one atomic add per chunk to reserve its
+//      output), counts in reverse level order (each queue position pulls its
+//      donors' counts, which sit contiguously in the next level), then uplift
+//      and erosion from the roots outward.  Large levels are shared by all
+//      workgroups and end in a grid-wide barrier; runs of small levels are
+//      done by one workgroup with workgroup barriers only.  It returns at
+//      once when nothing was handed on.
+//  k_grid_levels   (batches) the same level pass with one workgroup per grid.
 //
 // The results of the method do not depend on the order cells are processed
 // in (receivers, levels and counts are exact; each height depends only on
@@ -402,6 +408,7 @@ static_assert(kTileThreads % kTW == 0 && kTH % (kTileThreads / kTW) == 0, "strip
 static_assert(kStrip == 8, "codes packed 4 bits a cell in one word, levels 8 bits in two");
 static_assert(kRing <= kTileThreads, "one ring cell per thread");
 static_assert(kSN % 4 == 0, "byte arrays cleared as words");
+static_assert(kSN <= 0x2000, "level-list entries: 13-bit LDS index and 3-bit code");
 
 // Offset of neighbour k in the tile pass's LDS layout: eight signed bytes in
 // one word, so a run-time k costs a shift and a sign extension.
@@ -668,40 +675,59 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
     // has a donor outside; such trees are marked at their local root.  A
     // walk longer than kLocalDepthCap (a receiver cycle under fixed routing,
     // or a very deep tree) sends the whole tile to the crossing-tree passes.
+    // The thread's eight walks advance one step per round, so their LDS
+    // reads are in flight together.  A walk's state is one word: its cell
+    // (bits 0-15), that cell's code (16-19) and its steps so far (24-31).
+    uint32_t wk[kStrip];
+    uint32_t act = 0, exitm = 0;
+#pragma unroll
+    for (int t = 0; t < kStrip; ++t) {
+      const uint32_t cv = (codes >> (4 * t)) & 15u;
+      wk[t] = (uint32_t)(li0 + t * kSW) | (cv << 16);
+      act |= (uint32_t)(cv < kSink) << t;
+    }
+    while (act) {
+      uint32_t cu[kStrip];
+      int un[kStrip];
+#pragma unroll
+      for (int t = 0; t < kStrip; ++t) {
+        const int v = (int)(wk[t] & 0xFFFFu);
+        // A finished walk re-reads its own cell (in bounds, result unused).
+        un[t] = ((act >> t) & 1u) ? v + lds_off((int)((wk[t] >> 16) & 15u)) : v;
+        cu[t] = rc[un[t]];
+      }
+#pragma unroll
+      for (int t = 0; t < kStrip; ++t) {
+        if (!((act >> t) & 1u)) continue;
+        const int u = un[t];
+        if (cu[t] & kRingFlag) {
+          exitm |= 1u << t;
+          act &= ~(1u << t);
+          continue;
+        }
+        atomicAdd(&clw[u >> 1], 1u << ((u & 1) * 16));
+        const uint32_t d = (wk[t] >> 24) + 1u;
+        wk[t] = (uint32_t)u | (cu[t] << 16) | (d << 24);
+        if (cu[t] >= kSink) {
+          act &= ~(1u << t);
+        } else if (d >= (uint32_t)kLocalDepthCap) {
+          s_all = 1;
+          act &= ~(1u << t);
+        }
+      }
+    }
     uint64_t deps = 0;
     uint32_t roots[kStrip / 2];
 #pragma unroll
     for (int t = 0; t < kStrip; ++t) {
-      int v = li0 + t * kSW;
-      uint32_t cv = (codes >> (4 * t)) & 15u;
-      uint32_t d = 0;
-      bool exits = false;
-      if (cv < kSink) {
-        for (;;) {
-          const int u = v + lds_off((int)cv);
-          const uint32_t cu = rc[u];
-          if (cu & kRingFlag) {
-            exits = true;
-            break;
-          }
-          atomicAdd(&clw[u >> 1], 1u << ((u & 1) * 16));
-          ++d;
-          v = u;
-          cv = cu;
-          if (cu >= kSink) break;
-          if (d >= (uint32_t)kLocalDepthCap) {
-            s_all = 1;
-            break;
-          }
-        }
-      }
+      const int v = (int)(wk[t] & 0xFFFFu);
       // Outward directions of a border cell: 0-2 (top row), 5-7 (bottom
       // row), 0, 3, 5 (left column), 2, 4, 7 (right column).
       const int sy = sy0 + t;
       const uint32_t out = (sy == 0 ? 0x07u : 0u) | (sy == kTH - 1 ? 0xE0u : 0u) |
                            (tx == 0 ? 0x29u : 0u) | (tx == kTW - 1 ? 0x94u : 0u);
-      if (exits || (((dms >> (8 * t)) & out) != 0)) xr[v] = 1;
-      deps |= (uint64_t)d << (8 * t);
+      if (((exitm >> t) & 1u) || (((dms >> (8 * t)) & out) != 0)) xr[v] = 1;
+      deps |= (uint64_t)(wk[t] >> 24) << (8 * t);
       if (t & 1)
         roots[t >> 1] |= (uint32_t)v << 16;
       else
@@ -775,15 +801,17 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
       const int incl = wave_inclusive_scan(cnt);
       const int total = __shfl(incl, 63, 64);
       int pos = incl - cnt;
+      // List entries: the cell's LDS index (bits 0-12) and its code (13-15).
       while (at) {
         const int t = __ffs(at) - 1;
         at &= at - 1;
-        wl[pos++] = (uint16_t)(li0 + t * kSW);
+        wl[pos++] = (uint16_t)((li0 + t * kSW) | (((codes >> (4 * t)) & 7u) << 13));
       }
       __builtin_amdgcn_wave_barrier();
-      for (int j = lane; j < total; j += 64) {
-        const int li = wl[j];
-        const int code = rc[li];
+      // New height of the cell of list entry e.
+      auto erode = [&](uint32_t e) -> double {
+        const int li = (int)(e & 0x1FFFu);
+        const int code = (int)(e >> 13);
         const int u = li + lds_off(code);
         int64_t c = 0;
         if (need_c) {
@@ -796,20 +824,18 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
         const uint32_t count = (clw[li >> 1] >> ((li & 1) * 16)) & 0xFFFFu;
         const double udt = a.Uf ? a.Uf[c] * G.dt : G.udt;
         const double h0 = hs[li] + udt;
-        double hn;
         if (table_f && count < (uint32_t)kAmTab) {
           const double f = ftl[code_class(code) * kAmTab + count];
-          if (a.project) {
-            hn = f > 0.0 ? hr + udt / f : h0;
-          } else {
-            const double g = 1.0 + f;
-            hn = (h0 + f * hr) / g;
-          }
-        } else {
-          hn = eroded_height_general(a.grids, gi, a.Kf, w.amtab, count, code, c, h0, hr,
-                                     a.project, udt);
+          if (a.project) return f > 0.0 ? hr + udt / f : h0;
+          const double g = 1.0 + f;
+          return (h0 + f * hr) / g;
         }
-        hs[li] = hn;
+        return eroded_height_general(a.grids, gi, a.Kf, w.amtab, count, code, c, h0, hr,
+                                     a.project, udt);
+      };
+      for (int j = lane; j < total; j += 64) {
+        const uint32_t e0 = wl[j];
+        hs[e0 & 0x1FFFu] = erode(e0);
       }
       __syncthreads();
     }
@@ -1392,12 +1418,13 @@ __global__ __launch_bounds__(1024) void k_grid_levels_finish(StepArgs a) {
 // writes nothing; its roots are staged for the level pass that follows
 // (the global pass: behind the chunk roots in q/gq/kq; the per-grid pass:
 // in the grid's slice of fc/mq), which orders those trees as before.
-__global__ __launch_bounds__(kChunkThreads) void k_chunk_trees(StepArgs a) {
+template <bool kMulti>
+__global__ __launch_bounds__(kChunkThreads, 4) void k_chunk_trees(StepArgs a) {
   constexpr int NT = kChunkThreads;
   __shared__ int32_t s_cell[kChunkCap];      // cell of each entry, level-major
   __shared__ double s_h[kChunkCap];          // uplifted start height, then new height
   __shared__ uint16_t s_par[kChunkCap];      // entry of the receiver
-  __shared__ uint16_t s_grid[kChunkCap];     // grid of the entry
+  __shared__ uint16_t s_grid[kMulti ? kChunkCap : 1];  // grid of the entry (batches)
   __shared__ uint32_t s_cnt[kChunkCap / 2];  // upstream counts, two 16-bit halves a word
   __shared__ uint8_t s_k[kChunkCap];         // receiver code (roots: kSink or kBase)
   __shared__ uint16_t s_lev[kChunkLevCap + 2];
@@ -1410,7 +1437,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_trees(StepArgs a) {
   const int tid = threadIdx.x;
   const int32_t nroots = w.lcnt[0];  // final: written by the tile pass
   const int R = a.chunk_roots;
-  const bool multi = a.ngrids > 1;
+  constexpr bool multi = kMulti;  // a batch: entries carry their grid
   int64_t my_total = 0;
   int32_t my_nl = 0;
   uint64_t tk[3] = {0, 0, 0};
@@ -1429,7 +1456,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_trees(StepArgs a) {
     for (int j = tid; j < nr; j += NT) {
       s_cell[j] = w.q[r0 + j];
       s_k[j] = w.kq[r0 + j];
-      s_grid[j] = multi ? w.gq[r0 + j] : 0;
+      if (multi) s_grid[j] = w.gq[r0 + j];
     }
     if (tid == 0) {
       s_lev[0] = 0;
@@ -1450,7 +1477,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_trees(StepArgs a) {
         int g = 0;
         if (i < hi) {
           c = s_cell[i];
-          g = s_grid[i];
+          g = multi ? s_grid[i] : 0;
           m = w.dmask[c];
           double hv = a.h_in[c];
           if (s_k[i] != kBase) hv = hv + (a.Uf ? a.Uf[c] * a.grids[g].dt : a.grids[g].udt);
@@ -1470,7 +1497,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_trees(StepArgs a) {
             m &= m - 1;
             s_cell[pos] = (int32_t)(c + neighbour_offset(b, nx));
             s_par[pos] = (uint16_t)i;
-            s_grid[pos] = (uint16_t)g;
+            if (multi) s_grid[pos] = (uint16_t)g;
             s_k[pos] = (uint8_t)(7 - b);
             ++pos;
           }
@@ -1534,12 +1561,24 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_trees(StepArgs a) {
         const uint32_t count = (s_cnt[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
         double hn = s_h[i];
         if (l > 0) {
-          const int gi = s_grid[i];
+          const int gi = multi ? s_grid[i] : 0;
           const GridDev& G = a.grids[gi];
-          double f, g;
-          erosion_factor(a, G, gi, count, s_k[i], c, &f, &g);
+          const int k = s_k[i];
+          const double hr = s_h[s_par[i]];
           const double udt = a.Uf ? a.Uf[c] * G.dt : G.udt;
-          hn = new_height(G, a.project != 0, hn, s_h[s_par[i]], f, g, udt);
+          if (!a.Kf && !G.newton && count < (uint32_t)kAmTab) {
+            // F from the grid's table (scalar K, n = 1, small counts).
+            const double f = w.ftab[(gi * 3 + code_class(k)) * kAmTab + count];
+            if (a.project) {
+              hn = f > 0.0 ? hr + udt / f : hn;
+            } else {
+              const double g = 1.0 + f;
+              hn = (hn + f * hr) / g;
+            }
+          } else {
+            hn = eroded_height_general(a.grids, gi, a.Kf, w.amtab, count, k, c, hn, hr, a.project,
+                                       udt);
+          }
           s_h[i] = hn;
         }
         a.h_out[c] = hn;
@@ -2119,13 +2158,17 @@ hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s) {
 }
 
 hipError_t launch_chunk_trees(const StepArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_chunk_trees, dim3((unsigned)grid), dim3(kChunkThreads), 0, s, a);
+  if (a.ngrids > 1)
+    hipLaunchKernelGGL(k_chunk_trees<true>, dim3((unsigned)grid), dim3(kChunkThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_chunk_trees<false>, dim3((unsigned)grid), dim3(kChunkThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t chunk_kernel_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_chunk_trees,
-                                                      kChunkThreads, 0);
+hipError_t chunk_kernel_occupancy(bool batch, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, batch ? (const void*)k_chunk_trees<true> : (const void*)k_chunk_trees<false>,
+      kChunkThreads, 0);
 }
 
 hipError_t launch_mfd_route(const StepArgs& a, hipStream_t s) {

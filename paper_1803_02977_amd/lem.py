@@ -284,14 +284,15 @@ def _set_tuning(ctx, *fields):
     return {name: getattr(t, name) for name, _ in lem_tuning._fields_}
 
 
-def _apply_tuning(obj, cells, tuning):
-    """tuning: None (library defaults), "auto" (tuning.json if present), a
-    tuple of lem_tuning fields in order or a dict of them by name."""
+def _apply_tuning(obj, cells, tuning, batch=False):
+    """tuning: None (library defaults), "auto" (tuning.json's setting for a
+    single grid or a batch of that many cells, if present), a tuple of
+    lem_tuning fields in order or a dict of them by name."""
     if tuning is None:
         return
     if tuning == "auto":
         from . import tune
-        tuning = tune.lookup(cells)
+        tuning = tune.lookup(cells, batch)
         if tuning is None:
             return
     if isinstance(tuning, dict):
@@ -424,7 +425,7 @@ class Batch:
         with torch.cuda.device(self.device):
             self.ctx = lem_batch_create(descs, flags, self.workspace.data_ptr(), nbytes,
                                         self.stream.cuda_stream)
-        _apply_tuning(self, self.total_cells, tuning)
+        _apply_tuning(self, self.total_cells, tuning, batch=len(descs) > 1)
 
     def _check_h(self, h):
         torch = self.torch
