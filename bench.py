@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--grids", type=int, default=100, help="held-out grids (warm-start workload)")
     ap.add_argument("--plain-sample", type=int, default=10,
                     help="warm-start workload: realizations timed through the plain solver")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="batch workload: also run the realizations as this many batches on "
+                         "their own HIP streams, concurrently (0 or 1: one batch only)")
     ap.add_argument("--level-pass", type=int, default=0,
                     help="batch workload: 0 automatic, 1 one device-wide pass, 2 one workgroup "
                          "per grid")
@@ -154,13 +157,70 @@ def _batch_tuning(args):
     return t
 
 
+def run_streams(args, reals, steps, h_ref, tuning):
+    """The same realizations as `args.streams` batches (sizes dealt round
+    robin, largest first), each with its own context on its own HIP stream,
+    run concurrently: while one batch's level pass keeps a few CUs busy with
+    its deepest grids, the others' tile passes fill the rest.  Every grid must
+    end bit-identical to the one-batch run (`h_ref`)."""
+    import torch
+
+    from paper_1803_02977_amd import Batch
+    dev = h_ref.device
+    k = args.streams
+    offs = np.cumsum([0] + [r.ny * r.nx for r in reals])
+    order = sorted(range(len(reals)), key=lambda i: -reals[i].ny * reals[i].nx)
+    groups = [order[j::k] for j in range(k)]
+    runs = []
+    for g in groups:
+        st = torch.cuda.Stream(device=dev)
+        rs = [reals[i] for i in g]
+        hg0 = torch.from_numpy(W.batch_initial_heights(rs)).to(dev)
+        b = Batch(rs, device=dev, stream=st, tuning=None)
+        b.set_tuning(**tuning)  # the one batch's setting
+        runs.append((b, st, hg0, hg0.clone(), g))
+    if args.warmup > 0:
+        for b, st, hg0, hg, g in runs:
+            b.run(hg, args.warmup)
+        torch.cuda.synchronize()
+    for b, st, hg0, hg, g in runs:
+        hg.copy_(hg0)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(runs[0][1])
+    ends = []
+    t0 = time.perf_counter()
+    for b, st, hg0, hg, g in runs:
+        if st is not runs[0][1]:
+            st.wait_event(start)
+        b.run(hg, steps)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(st)
+        ends.append(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = max(start.elapsed_time(e) for e in ends)
+    equal = True
+    for b, st, hg0, hg, g in runs:
+        o = 0
+        for i in g:
+            n = reals[i].ny * reals[i].nx
+            equal &= bool(torch.equal(hg[o:o + n], h_ref[offs[i]:offs[i] + n]))
+            o += n
+        b.close()
+    cells = int(offs[-1])
+    return {"streams": k, "value": cells * steps / (ms / 1e3), "ms_per_step": ms / steps,
+            "wall_s": wall, "bit_identical_to_one_batch": equal,
+            "batch_cells": [int(sum(reals[i].ny * reals[i].nx for i in g)) for g in groups]}
+
+
 def bench_batch(args):
     """512 independent realizations (sizes 128..1024, per-realization K, U, m)
     advanced together for 500 steps; compared with the same grids run one by
     one through the single-grid path on the same GPU."""
     import torch
 
-    from paper_1803_02977_amd import LEM_F_PHASE_TIMERS, Batch, Solver
+    from paper_1803_02977_amd import LEM_F_PHASE_TIMERS, LEM_F_TILE_CLOCKS, Batch, Solver
     reals = W.batch_realizations(512, seed=args.seed)
     steps = args.steps or 500
     dev = torch.device("cuda:0")
@@ -196,10 +256,19 @@ def bench_batch(args):
     bt.sync()
     stt = bt.stats()
     bt.close()
+    # Device clocks per phase inside every tile workgroup (a run of its own).
+    bc = Batch(reals, flags=LEM_F_TILE_CLOCKS, device=dev)
+    bc.set_tuning(**_batch_tuning(args))
+    h.copy_(h0)
+    bc.run(h, steps)
+    bc.sync()
+    tile_phase_ms = list(bc.stats().tile_phase_ms)
+    bc.close()
     tile_ms = stt.kernel_ms[0] / steps
     chunk_ms = stt.kernel_ms[2] / steps
     level_ms = (stt.kernel_ms[1] - stt.kernel_ms[2]) / steps
     cross = stt.crossing_run / steps
+    streams = run_streams(args, reals, steps, h, applied) if args.streams > 1 else None
     level_name = "k_grid_levels" if mode == 2 else "k_global_levels"
     if level_ms >= max(tile_ms, chunk_ms):
         roof = {"bound": "hbm", "kernel": level_name,
@@ -235,9 +304,16 @@ def bench_batch(args):
         for s_ in solvers:
             s_.close()
         one_value = cells * one_steps / one_wall
+    # The faster schedule is the workload's figure (both give the same bits).
+    one_batch = {"value": value, "ms_per_step": ms / steps}
+    schedule = "one batch"
+    if streams and streams["bit_identical_to_one_batch"] and streams["value"] > value:
+        value, ms = streams["value"], streams["ms_per_step"] * steps
+        schedule = f"{streams['streams']} concurrent batches on their own streams"
     out = {
         "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": ms / steps,
+        "schedule": schedule, "one_batch": one_batch,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": BATCH_NAME, "realizations": len(reals), "cells": cells,
@@ -255,10 +331,16 @@ def bench_batch(args):
                                level_name: level_ms},
         # Device clock of a tile workgroup, mean over workgroups, per phase.
         "tile_wg_phase_us_per_step": {
-            k: round(stt.tile_phase_ms[i] / steps * 1e3, 3)
+            k: round(tile_phase_ms[i] / steps * 1e3, 3)
             for i, k in enumerate(("stage", "receivers", "donors_walks", "clean",
                                    "erosion", "writeback"))},
         "levels_max": int(stt.max_nlevels),
+        "concurrent_batches": streams,
+        # Crossing-tree phases by the device clock (per-grid level pass: the
+        # longest workgroup of each phase, per step).
+        "crossing_phase_ms_per_step": {"order": stt.phase_ms[1] / steps,
+                                       "accumulate": stt.phase_ms[2] / steps,
+                                       "erode": stt.phase_ms[3] / steps},
         "tuning": applied,
         "roofline": roof,
     }
@@ -654,7 +736,7 @@ def main():
         return
     import torch
 
-    from paper_1803_02977_amd import LEM_F_PHASE_TIMERS, Solver
+    from paper_1803_02977_amd import LEM_F_PHASE_TIMERS, LEM_F_TILE_CLOCKS, Solver
 
     w = W.WORKLOADS[args.workload]
     steps = args.steps or w.steps
@@ -706,6 +788,15 @@ def main():
     st = tsolver.stats()
     tsolver_crossing = st.crossing_run / steps
     tsolver.close()
+    # Device clocks per phase inside every tile workgroup: a run of its own,
+    # since they slow the tile pass that the run above times.
+    h.copy_(h0)
+    csolver = Solver(w.ny, w.nx, w.dx, w.dy, w.dt, w.m, w.U, w.K, device=dev,
+                     flags=LEM_F_TILE_CLOCKS)
+    csolver.run(h, steps, K=Kt)
+    csolver.sync()
+    tile_phase_ms = list(csolver.stats().tile_phase_ms)
+    csolver.close()
     tile_ms = st.kernel_ms[0] / steps
     chunk_ms = st.kernel_ms[2] / steps
     global_ms = (st.kernel_ms[1] - st.kernel_ms[2]) / steps
@@ -775,7 +866,7 @@ def main():
                                            "erode": st.phase_ms[3] / steps},
         # Device clock of a tile workgroup, mean over workgroups, per phase.
         "tile_wg_phase_us_per_step": {
-            k: round(st.tile_phase_ms[i] / steps * 1e3, 3)
+            k: round(tile_phase_ms[i] / steps * 1e3, 3)
             for i, k in enumerate(("stage", "receivers", "donors_walks", "clean",
                                    "erosion", "writeback"))},
         "tuning": applied,

@@ -56,6 +56,8 @@ typedef enum lem_status {
 /* lem_params.flags */
 #define LEM_F_VALIDATE 0x1u     /* scan h, K and U for non-finite values before a run */
 #define LEM_F_PHASE_TIMERS 0x2u /* record per-phase device time with HIP events       */
+#define LEM_F_TILE_CLOCKS 0x4u  /* per-phase device clocks in every tile workgroup
+                                   (lem_stats.tile_phase_ms); slows the tile pass    */
 
 /* Problem statement (section "The Equation"; Step 1 "Initialization"):
  *   ny, nx  rows and columns, each >= 3, ny*nx <= 2^31-1;
@@ -102,7 +104,8 @@ typedef struct lem_stats_t {
                               trees that cross tile edges (1-3 by the device clock
                               of one workgroup: the chunk stage's first workgroup
                               when that stage runs, else the global level kernel's
-                              first)                                               */
+                              first; the per-grid level pass adds, per step and
+                              phase, the longest time of any of its workgroups)    */
   double kernel_ms[3];     /* HIP-event ms of the last run with LEM_F_PHASE_TIMERS,
                               summed over its steps: [0] the tile pass, [1] the
                               trees that cross tile edges (chunk stage and level
@@ -111,7 +114,7 @@ typedef struct lem_stats_t {
   int64_t crossing_last;   /* cells of the most recent step whose drainage tree
                               crosses a tile edge (resolved by the global pass)     */
   int64_t crossing_run;    /* the same, summed over the steps of the last run       */
-  double tile_phase_ms[6]; /* with LEM_F_PHASE_TIMERS: device-clock ms of one tile
+  double tile_phase_ms[6]; /* with LEM_F_TILE_CLOCKS: device-clock ms of one tile
                               workgroup on average, summed over the steps of the last
                               run, per phase: [0] staging the heights, [1] receivers,
                               [2] donor masks, walks to the tile-local roots and
@@ -229,7 +232,7 @@ typedef struct lem_grid {
 size_t lem_batch_workspace_bytes(const lem_grid* grids, int32_t count);
 
 /* As lem_create for a batch of `count` grids (host array, copied).  flags:
- * LEM_F_VALIDATE and/or LEM_F_PHASE_TIMERS. */
+ * LEM_F_VALIDATE, LEM_F_PHASE_TIMERS and/or LEM_F_TILE_CLOCKS. */
 lem_status lem_batch_create(const lem_grid* grids, int32_t count, uint32_t flags,
                             void* d_workspace, size_t ws_bytes, void* hip_stream,
                             lem_ctx** out);
@@ -343,8 +346,8 @@ const char* lem_last_error(const lem_ctx* ctx);
  * (LEM_STATIC_WORKSPACE_BYTES on each device the library runs on, kept until
  * the process ends) instead of one the caller passes.  Nothing is allocated
  * on the device and no allocating library routine is called.
- *   p        grid and parameters as for lem_create; LEM_F_PHASE_TIMERS is
- *            rejected (LEM_E_ARG);
+ *   p        grid and parameters as for lem_create; LEM_F_PHASE_TIMERS and
+ *            LEM_F_TILE_CLOCKS are rejected (LEM_E_ARG);
  *   d_h      float64 ny*nx heights on the current device, row-major,
  *            updated in place; d_K, d_U optional per-cell fields (NULL:
  *            the scalars in p);

@@ -89,7 +89,10 @@ lem_status check_params(const lem_params* p, std::string* why) {
   lem_status st = check_grid(p->ny, p->nx, p->dx, p->dy, p->dt, p->m, p->n, p->U, p->K, p->eps,
                              p->max_newton, why);
   if (st != LEM_OK) return st;
-  if (p->flags & ~(LEM_F_VALIDATE | LEM_F_PHASE_TIMERS)) { *why = "unknown flag bits"; return LEM_E_ARG; }
+  if (p->flags & ~(LEM_F_VALIDATE | LEM_F_PHASE_TIMERS | LEM_F_TILE_CLOCKS)) {
+    *why = "unknown flag bits";
+    return LEM_E_ARG;
+  }
   return LEM_OK;
 }
 
@@ -161,6 +164,7 @@ lem::StepArgs make_args(const lem_ctx* ctx, const double* d_K, const double* d_U
   a.ntiles = ctx->ntiles;
   a.n = (int32_t)ctx->cells;
   a.timers = (ctx->flags & LEM_F_PHASE_TIMERS) ? 1 : 0;
+  a.tile_clocks = (ctx->flags & LEM_F_TILE_CLOCKS) ? 1 : 0;
   a.Kf = d_K;
   a.Uf = d_U;
   a.w = ctx->w;
@@ -467,7 +471,7 @@ lem_status lem_batch_create(const lem_grid* grids, int32_t count, uint32_t flags
                             void* d_workspace, size_t ws_bytes, void* hip_stream, lem_ctx** out) {
   if (!out) return LEM_E_ARG;
   *out = nullptr;
-  if (flags & ~(LEM_F_VALIDATE | LEM_F_PHASE_TIMERS)) return LEM_E_ARG;
+  if (flags & ~(LEM_F_VALIDATE | LEM_F_PHASE_TIMERS | LEM_F_TILE_CLOCKS)) return LEM_E_ARG;
   lem_ctx* ctx = new (std::nothrow) lem_ctx();
   if (!ctx) return LEM_E_ARG;
   std::string why;

@@ -80,7 +80,8 @@ struct Ctrl {
   int32_t glob_total;      // cells ordered by the global level pass (current step)
   uint64_t tile_ticks[kTilePhases];  // tile pass: device clock per phase, summed over workgroups
   uint64_t tile_wgs;       // tile-pass workgroups timed
-  int32_t pad[18];
+  uint64_t grid_phase_max[3];  // per-grid level pass: longest workgroup per phase (current step)
+  int32_t pad[12];
   // Grid-wide barrier of the global level kernel (own cache lines).
   uint32_t bar_count;
   uint32_t pad1[31];
@@ -176,6 +177,7 @@ struct StepArgs {
   int32_t chunked;       // crossing trees go through the chunk stage first
   int32_t chunk_roots;   // roots per chunk of that stage
   int32_t project;       // steady-state projection instead of the implicit update
+  int32_t tile_clocks;   // per-phase device clocks in every tile workgroup
   double mfd_p;          // exponent of the slope in the flow shares
 };
 

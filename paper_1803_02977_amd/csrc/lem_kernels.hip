@@ -522,7 +522,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
   const int sy0 = kStrip * ty;                // first strip row within the tile
   const int li0 = (sy0 + 2) * kSW + tx + 2;   // LDS index of the strip's first cell
   uint16_t* wl = wlist + (tid / 64) * (64 * kStrip);
-  const bool clock = a.timers && tid == 0;    // per-phase device clock (LEM_F_PHASE_TIMERS)
+  const bool clock = a.tile_clocks && tid == 0;  // per-phase device clock (LEM_F_TILE_CLOCKS)
   static_assert(3 * kAmTab <= 2 * kTileThreads, "at most two table entries per thread");
   const bool has_ft0 = tid < 3 * kAmTab, has_ft1 = tid + kTileThreads < 3 * kAmTab;
   {
@@ -842,7 +842,9 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
     if (clock) tk[5] = wall_clock64();
 
     // Write the tile back (heights of crossing trees unchanged here: the
-    // crossing-tree passes overwrite them); queue the roots of crossing trees.
+    // crossing-tree passes read their starting heights from the output
+    // buffer, so that a cell's read and its later write share one cache
+    // line, and overwrite them); queue the roots of crossing trees.
     // Addresses are formed here, from a column index the compiler cannot
     // trace back (an empty asm), so that they are not computed early and
     // kept through the erosion.
@@ -1028,7 +1030,7 @@ __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32
     double f, g;
     erosion_factor(a, G, gi, w.cnt[i], w.kq[i], c, &f, &g);
     const double udt = a.Uf ? a.Uf[c] * G.dt : G.udt;
-    const double h0 = a.h_in[c] + udt;
+    const double h0 = a.h_out[c] + udt;
     const double hn = new_height(G, a.project != 0, h0, hr, f, g, udt);
     w.hq[i] = hn;
     a.h_out[c] = hn;
@@ -1189,7 +1191,7 @@ __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
     accumulate_level(w, 0, a1, wg, nwg);
     for (int64_t i = (int64_t)wg * kBlock + tid; i < a1; i += (int64_t)nwg * kBlock) {
       const int32_t c = w.q[i];
-      double hv = a.h_in[c];
+      double hv = a.h_out[c];
       if (w.kq[i] == kSink) {
         const GridDev& G = a.grids[w.gq[i]];
         hv = hv + (a.Uf ? a.Uf[c] * G.dt : G.udt);
@@ -1298,6 +1300,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
   __shared__ int wsum[NT / 64];
   __shared__ int32_t s_next;
+  __shared__ uint64_t s_tk[3];
   const Work w = a.w;
   const int gi = blockIdx.x;
   const int tid = threadIdx.x;
@@ -1312,6 +1315,9 @@ __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
   }
   const int32_t base = (int32_t)G.offset;
   int32_t* lev = w.lev + G.offset + 2 * (int64_t)gi;
+  // Phase clocks (LEM_F_PHASE_TIMERS) live in LDS, not in registers.
+  const bool clock = a.timers && tid == 0;
+  if (clock) s_tk[0] = wall_clock64();
   if (a.chunked) {
     // Roots of the chunks the chunk stage could not hold, staged in fc/mq.
     for (int32_t j = tid; j < nroots; j += NT) {
@@ -1339,15 +1345,17 @@ __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
     ++L;
   }
   __syncthreads();
+  if (clock) s_tk[1] = wall_clock64();
   // Step 5: counts, deepest level first.
   for (int32_t l = L; l >= 0; --l) {
     accumulate_level<NT>(w, lev[l], lev[l + 1], 0, 1);
     __syncthreads();
   }
+  if (clock) s_tk[2] = wall_clock64();
   // Level 0: uplift of the interior roots (perimeter roots keep their height).
   for (int32_t i = lev[0] + tid; i < lev[1]; i += NT) {
     const int32_t c = w.q[i];
-    double hv = a.h_in[c];
+    double hv = a.h_out[c];
     if (w.kq[i] == kSink) hv = hv + (a.Uf ? a.Uf[c] * G.dt : G.udt);
     a.h_out[c] = hv;
     w.hq[i] = hv;
@@ -1370,6 +1378,13 @@ __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
     w.gcnt[gi] = 0;
     w.gnl[gi] = L + 1;
     w.gtot[gi] = hi - base;
+  }
+  if (clock) {
+    const uint64_t tk3 = wall_clock64();
+    Ctrl* ct = w.ctrl;
+    atomicMax((unsigned long long*)&ct->grid_phase_max[0], (unsigned long long)(s_tk[1] - s_tk[0]));
+    atomicMax((unsigned long long*)&ct->grid_phase_max[1], (unsigned long long)(s_tk[2] - s_tk[1]));
+    atomicMax((unsigned long long*)&ct->grid_phase_max[2], (unsigned long long)(tk3 - s_tk[2]));
   }
 }
 
@@ -1399,6 +1414,11 @@ __global__ __launch_bounds__(1024) void k_grid_levels_finish(StepArgs a) {
     Ctrl* ct = w.ctrl;
     ct->dirty_nlevels = smax[0];
     finish_step(a, ct, ssum[0], smax[0], 0);
+    if (a.timers)
+      for (int k = 0; k < 3; ++k) {
+        ct->ticks[k + 1] += ct->grid_phase_max[k];
+        ct->grid_phase_max[k] = 0;
+      }
   }
 }
 
@@ -1479,7 +1499,7 @@ __global__ __launch_bounds__(kChunkThreads, 4) void k_chunk_trees(StepArgs a) {
           c = s_cell[i];
           g = multi ? s_grid[i] : 0;
           m = w.dmask[c];
-          double hv = a.h_in[c];
+          double hv = a.h_out[c];
           if (s_k[i] != kBase) hv = hv + (a.Uf ? a.Uf[c] * a.grids[g].dt : a.grids[g].udt);
           s_h[i] = hv;
         }

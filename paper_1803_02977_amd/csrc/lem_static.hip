@@ -45,7 +45,7 @@ hipError_t scratch_address(int device, void** out) {
 extern "C" lem_status lem_run_static(const lem_params* p, double* d_h, const double* d_K,
                                      const double* d_U, int64_t steps, void* hip_stream) {
   if (!p || !d_h || steps < 0) return LEM_E_ARG;
-  if (p->flags & LEM_F_PHASE_TIMERS) return LEM_E_ARG;
+  if (p->flags & (LEM_F_PHASE_TIMERS | LEM_F_TILE_CLOCKS)) return LEM_E_ARG;
   const size_t need = lem_workspace_bytes(p);
   if (need == 0) return LEM_E_ARG;
   if (need > kStaticWorkspaceBytes) return LEM_E_WORKSPACE;

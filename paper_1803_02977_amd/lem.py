@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblem.so")
 
 LEM_OK, LEM_E_ARG, LEM_E_SIZE, LEM_E_WORKSPACE = 0, 1, 2, 3
 LEM_E_NONFINITE, LEM_E_CYCLE, LEM_E_HIP, LEM_E_STATE = 4, 5, 6, 7
-LEM_F_VALIDATE, LEM_F_PHASE_TIMERS = 0x1, 0x2
+LEM_F_VALIDATE, LEM_F_PHASE_TIMERS, LEM_F_TILE_CLOCKS = 0x1, 0x2, 0x4
 
 # Symbols declared in include/lem.h.
 EXPORTS = ("lem_workspace_bytes", "lem_create", "lem_run", "lem_run_fixed_routing",

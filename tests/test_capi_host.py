@@ -186,4 +186,7 @@ def test_static_entry_point_rejects_oversized_grids_on_the_host():
     timers = lem.lem_params(64, 64, 100.0, 100.0, 1000.0, 0.5, 1.0, 5e-4, 1e-5, 1e-12, 100,
                             lem.LEM_F_PHASE_TIMERS)
     assert lib.lem_run_static(C.byref(timers), 256, None, None, 1, None) == lem.LEM_E_ARG
+    clocks = lem.lem_params(64, 64, 100.0, 100.0, 1000.0, 0.5, 1.0, 5e-4, 1e-5, 1e-12, 100,
+                            lem.LEM_F_TILE_CLOCKS)
+    assert lib.lem_run_static(C.byref(clocks), 256, None, None, 1, None) == lem.LEM_E_ARG
     assert lib.lem_run_static(None, 256, None, None, 1, None) == lem.LEM_E_ARG
