@@ -100,9 +100,12 @@ def parse():
     ap.add_argument("--grids", type=int, default=100, help="held-out grids (warm-start workload)")
     ap.add_argument("--plain-sample", type=int, default=10,
                     help="warm-start workload: realizations timed through the plain solver")
-    ap.add_argument("--streams", type=int, default=0,
+    ap.add_argument("--streams", type=int, default=4,
                     help="batch workload: also run the realizations as this many batches on "
                          "their own HIP streams, concurrently (0 or 1: one batch only)")
+    ap.add_argument("--stream-split", choices=("deal", "size"), default="size",
+                    help="batch workload with --streams: deal the realizations round robin by "
+                         "size, or group them by size")
     ap.add_argument("--level-pass", type=int, default=0,
                     help="batch workload: 0 automatic, 1 one device-wide pass, 2 one workgroup "
                          "per grid")
@@ -159,10 +162,11 @@ def _batch_tuning(args):
 
 def run_streams(args, reals, steps, h_ref, tuning):
     """The same realizations as `args.streams` batches (sizes dealt round
-    robin, largest first), each with its own context on its own HIP stream,
-    run concurrently: while one batch's level pass keeps a few CUs busy with
-    its deepest grids, the others' tile passes fill the rest.  Every grid must
-    end bit-identical to the one-batch run (`h_ref`)."""
+    robin, largest first, or grouped by size), each with its own context on
+    its own HIP stream, run concurrently: while one batch's level pass keeps a
+    few CUs busy with its deepest grids, the others' tile passes could fill
+    the rest.  Every grid must end bit-identical to the one-batch run
+    (`h_ref`)."""
     import torch
 
     from paper_1803_02977_amd import Batch
@@ -170,7 +174,10 @@ def run_streams(args, reals, steps, h_ref, tuning):
     k = args.streams
     offs = np.cumsum([0] + [r.ny * r.nx for r in reals])
     order = sorted(range(len(reals)), key=lambda i: -reals[i].ny * reals[i].nx)
-    groups = [order[j::k] for j in range(k)]
+    if args.stream_split == "deal":
+        groups = [order[j::k] for j in range(k)]
+    else:  # contiguous by size: the largest grids together, the smallest together
+        groups = [order[j * len(order) // k:(j + 1) * len(order) // k] for j in range(k)]
     runs = []
     for g in groups:
         st = torch.cuda.Stream(device=dev)
@@ -671,16 +678,32 @@ def cpu_baseline(w, h0, K, steps):
 
 
 def cpu_full(args):
-    """The serial oracle over whole workloads (one JSON line each)."""
+    """The serial oracle over whole workloads (one JSON line each).  The steps
+    run in segments of about 30 s, each continuing from the last one's
+    heights (the same result as one call), with a progress line after each."""
+    import oracle
     names = [W.SMALL_256.name, W.MEDIUM_2048.name]
     if args.workload == W.LARGE_10000.name:
         names.append(W.LARGE_10000.name)
+    model, nproc = host_cpu()
     for name in names:
         w = W.WORKLOADS[name]
-        h0, K, _ = W.make_inputs(w, args.seed)
-        r = cpu_baseline(w, h0, K, w.steps)
-        r["workload"] = name
-        r["seconds_per_step"] = round(r["seconds"] / w.steps, 4)
+        h, K, _ = W.make_inputs(w, args.seed)
+        p = oracle.Params(w.ny, w.nx, w.dx, w.dy, w.dt, w.m, 1.0, w.U, w.K)
+        seg = max(1, int(30 * 1.5e7 // w.cells))
+        done, total = 0, 0.0
+        while done < w.steps:
+            k = min(seg, w.steps - done)
+            t = time.perf_counter()
+            h = oracle.run(h, p, k, K=K)["h"]
+            total += time.perf_counter() - t
+            done += k
+            print(f"[cpu-full] {name}: {done}/{w.steps} steps, {total:.1f} s", file=sys.stderr,
+                  flush=True)
+        r = dict(workload=name, value=w.cells * w.steps / total, unit="cell-updates/s", cores=1,
+                 kind="oracle", steps=w.steps, seconds=round(total, 2),
+                 seconds_per_step=round(total / w.steps, 4), cpu_model=model, nproc=nproc,
+                 sample=f"all {w.steps} steps of the {w.ny}x{w.nx} grid, serial C oracle")
         print(json.dumps(r), flush=True)
 
 

@@ -1668,6 +1668,8 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
       const int y = (int)(c / nx), x = (int)(c % nx);
       double wsum_c = 0.0;
       int nrec = 0;
+      uint32_t recs = 0;    // receivers: neighbours below this interior cell
+      uint32_t donors = 0;  // interior neighbours above this cell
       const double hc = a.h_in[c];
       if (y > 0 && x > 0 && y < ny - 1 && x < nx - 1) {
 #pragma unroll
@@ -1676,10 +1678,22 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
           if (hc - hr > 0.0) {
             wsum_c += slope_pow((hc - hr) / class_dist(G, k), a.mfd_p);
             ++nrec;
+            recs |= 1u << k;
           }
+          const int yy = y + code_dy(k), xx = x + code_dx(k);
+          if (yy > 0 && xx > 0 && yy < ny - 1 && xx < nx - 1 && hr - hc > 0.0) donors |= 1u << k;
+        }
+      } else {
+        for (int k = 0; k < 8; ++k) {
+          const int yy = y + code_dy(k), xx = x + code_dx(k);
+          if (yy > 0 && xx > 0 && yy < ny - 1 && xx < nx - 1 &&
+              a.h_in[c + neighbour_offset(k, nx)] - hc > 0.0)
+            donors |= 1u << k;
         }
       }
       w.par[c] = nrec;
+      w.mq[c] = (uint8_t)donors;
+      w.kq[c] = (uint8_t)recs;
       MfdCell& mc = w.mc[c];
       mc.h = hc;
       mc.wsum = wsum_c;
@@ -1709,7 +1723,7 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
                            uint64_t* wsum64, int* s_base) {
   const Work& w = a.w;
   const GridDev& G = a.grids[0];
-  const int ny = G.ny, nx = G.nx;
+  const int nx = G.nx;
   const int tid = threadIdx.x;
   constexpr int W = ITEMS / 4, CHUNK = kBlock * ITEMS;
   for (int64_t base = lo + (int64_t)wg * CHUNK; base < hi; base += (int64_t)nwg * CHUNK) {
@@ -1724,14 +1738,11 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
       if (i < hi) {
         const int32_t c = w.q[i];
         cs[j] = c;
-        const int y = c / nx, x = c % nx;
-        const double hc = a.h_in[c];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int yy = y + code_dy(k), xx = x + code_dx(k);
-          if (yy <= 0 || xx <= 0 || yy >= ny - 1 || xx >= nx - 1) continue;  // perimeter or outside
+        // Donors: the interior neighbours above the cell (mask from the routing).
+        for (uint32_t m = w.mq[c]; m; m &= m - 1) {
+          const int k = __ffs(m) - 1;
           const int32_t d = c + (int32_t)neighbour_offset(k, nx);
-          if (a.h_in[d] - hc > 0.0 && atomicSub(&w.par[d], 1) == 1) ready[j] |= 1u << k;
+          if (atomicSub(&w.par[d], 1) == 1) ready[j] |= 1u << k;
         }
         v[j >> 2] += (uint64_t)__popc(ready[j]) << (16 * (j & 3));
       }
@@ -1764,22 +1775,18 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
 __device__ void mfd_area_level(const StepArgs& a, int32_t a0, int32_t a1, int wg, int nwg) {
   const Work& w = a.w;
   const GridDev& G = a.grids[0];
-  const int ny = G.ny, nx = G.nx;
+  const int nx = G.nx;
   for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1; i += (int64_t)nwg * kBlock) {
     const int32_t c = w.q[i];
-    const int y = c / nx, x = c % nx;
     const double hc = w.mc[c].h;
     double acc = G.dxdy;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int yy = y + code_dy(k), xx = x + code_dx(k);
-      if (yy <= 0 || xx <= 0 || yy >= ny - 1 || xx >= nx - 1) continue;
+    // Donors in neighbour order (mask from the routing: interior neighbours above c).
+    for (uint32_t m = w.mq[c]; m; m &= m - 1) {
+      const int k = __ffs(m) - 1;
       const MfdCell& md = w.mc[c + (int32_t)neighbour_offset(k, nx)];
       const double hd = md.h;
-      if (hd - hc > 0.0) {
-        const double share = slope_pow((hd - hc) / class_dist(G, k), a.mfd_p) / md.wsum;
-        acc += share * md.area;
-      }
+      const double share = slope_pow((hd - hc) / class_dist(G, k), a.mfd_p) / md.wsum;
+      acc += share * md.area;
     }
     w.mc[c].area = acc;
   }
@@ -1805,21 +1812,19 @@ __device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int w
     const double ac = mc.area;
     const double kdt = (a.Kf ? a.Kf[c] : G.K) * G.dt;
     double sumf = 0.0, sumfh = 0.0;
-    int nrec = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    // Receivers in neighbour order (mask from the routing).
+    const uint32_t recs = w.kq[c];
+    for (uint32_t m = recs; m; m &= m - 1) {
+      const int k = __ffs(m) - 1;
       const int32_t r = c + (int32_t)neighbour_offset(k, nx);
       const double hr = a.h_in[r];
-      if (hc - hr > 0.0) {
-        const double dk = class_dist(G, k);
-        const double share = slope_pow((hc - hr) / dk, a.mfd_p) / wc;
-        const double f = (kdt * area_power_call(share * ac, G.use_sqrt, G.m)) / dk;
-        sumf += f;
-        sumfh += f * a.h_out[r];
-        ++nrec;
-      }
+      const double dk = class_dist(G, k);
+      const double share = slope_pow((hc - hr) / dk, a.mfd_p) / wc;
+      const double f = (kdt * area_power_call(share * ac, G.use_sqrt, G.m)) / dk;
+      sumf += f;
+      sumfh += f * a.h_out[r];
     }
-    a.h_out[c] = nrec ? (hup + sumfh) / (1.0 + sumf) : hup;
+    a.h_out[c] = recs ? (hup + sumfh) / (1.0 + sumf) : hup;
   }
 }
 
