@@ -280,13 +280,28 @@ __device__ __noinline__ double eroded_height_general(const GridDev* grids, int g
   return new_height(G, project != 0, h0, hr, f, g, udt);
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP: shifts by 1,
+// 2, 4 and 8 inside each row of 16 lanes (lanes shifted in from outside the
+// row add 0), then the last lane of row 0 (of rows 0-1) is added to rows 1
+// and 3 (to rows 2 and 3).  Every lane of the wave must be active.
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int u = __shfl_up(v, d, 64);
-    if (lane >= d) v += u;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
+// Maximum over the lanes 0..l of the wave (unsigned), the same pattern.
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
   return v;
 }
 
@@ -751,15 +766,12 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
       my_max = max(my_max, ok ? d : 0u);
       root_bits |= (uint32_t)(!ok && code >= kSink && code != kNone) << t;
     }
-    int my_clean = __popc(clean);
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      my_max = max(my_max, (uint32_t)__shfl_xor((int)my_max, d, 64));
-      my_clean += __shfl_xor(my_clean, d, 64);
-    }
+    // Wave totals: lane 63 of the inclusive scans.
+    const int wave_clean = __builtin_amdgcn_readlane(wave_inclusive_scan(__popc(clean)), 63);
+    const int wave_max = __builtin_amdgcn_readlane((int)wave_inclusive_max(my_max), 63);
     if (lane == 0) {
-      atomicMax(&s_cmax, (int)my_max);
-      atomicAdd(&s_clean, my_clean);
+      atomicMax(&s_cmax, wave_max);
+      atomicAdd(&s_clean, wave_clean);
     }
     // Roots go to the grid's own queue slice for the per-grid level pass, to
     // the one shared queue otherwise (the chunk stage takes them from there).
@@ -799,7 +811,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
       at &= clean;
       const int cnt = __popc(at);
       const int incl = wave_inclusive_scan(cnt);
-      const int total = __shfl(incl, 63, 64);
+      const int total = __builtin_amdgcn_readlane(incl, 63);
       int pos = incl - cnt;
       // List entries: the cell's LDS index (bits 0-12) and its code (13-15).
       while (at) {
