@@ -824,6 +824,8 @@ def main():
     chunk_ms = st.kernel_ms[2] / steps
     global_ms = (st.kernel_ms[1] - st.kernel_ms[2]) / steps
     crossing = tsolver_crossing
+    # The level pass after the chunk stage: device-wide, or one workgroup per grid.
+    level_name = "k_grid_levels" if applied["level_pass"] == 2 else "k_global_levels"
 
     cells = w.cells
     value = cells * steps / (ms / 1e3)
@@ -838,7 +840,7 @@ def main():
         kname, kms, kbytes = "k_chunk_trees", chunk_ms, alg_chunk * crossing
         per_unit = f"{alg_chunk} B per crossing-tree cell"
     else:
-        kname, kms, kbytes = "k_global_levels", global_ms, ALG_BYTES_GLOBAL * crossing
+        kname, kms, kbytes = level_name, global_ms, ALG_BYTES_GLOBAL * crossing
         per_unit = f"{ALG_BYTES_GLOBAL} B per crossing-tree cell"
     achieved = kbytes / (kms / 1e3) / 1e9
     roofline = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
@@ -881,7 +883,7 @@ def main():
                    "mean": float(levels.mean()), "per_step": [int(x) for x in levels],
                    "last_step_level_sizes": level_sizes} if len(levels) else None,
         "kernel_ms_per_step": {"k_tile_step": tile_ms, "k_chunk_trees": chunk_ms,
-                               "k_global_levels": global_ms},
+                               level_name: global_ms},
         # Device clock of the first workgroup of the crossing-tree work (the
         # chunk stage's when it runs): its time in each phase per step.
         "crossing_wg0_phase_ms_per_step": {"order": st.phase_ms[1] / steps,

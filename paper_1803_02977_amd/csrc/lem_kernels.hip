@@ -481,8 +481,10 @@ struct TileGeo {
 __device__ __forceinline__ TileGeo tile_geo(const StepArgs& a, int b) {
   TileGeo t;
   const int k = xcd_tile(b, a.ntiles);
-  const int tile = a.w.tiles[k];
-  t.gi = a.w.tgrid[k];
+  // Uniform over the workgroup: scalar registers, so the descriptor and
+  // everything derived from it stay scalar.
+  const int tile = __builtin_amdgcn_readfirstlane(a.w.tiles[k]);
+  t.gi = __builtin_amdgcn_readfirstlane(a.w.tgrid[k]);
   const GridDev& G = a.grids[t.gi];
   const int lt = tile - G.tile_base;
   t.y0 = (lt / G.tiles_x) * kTH;
@@ -799,6 +801,9 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
     const bool table_f = !a.Kf && !G.newton;
     const bool need_c = a.Kf || a.Uf || !table_f;
     const int cmax = s_cmax;
+    // Read once here: the loop below contains a call, which keeps the
+    // compiler from hoisting these loads out of it.
+    const double g_dt = G.dt, g_udt = G.udt;
     for (int l = 1; l <= cmax; ++l) {
       // The levels pass through an empty asm so that their bytes are not
       // extracted once before the loop and held (spilled) through it.
@@ -832,9 +837,9 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
         }
         double hr = hs[u];
         if (l == 1 && rc[u] == kSink)  // the receiver is an interior root: add its uplift
-          hr = hr + (a.Uf ? a.Uf[c + neighbour_offset(code, nx)] * G.dt : G.udt);
+          hr = hr + (a.Uf ? a.Uf[c + neighbour_offset(code, nx)] * g_dt : g_udt);
         const uint32_t count = (clw[li >> 1] >> ((li & 1) * 16)) & 0xFFFFu;
-        const double udt = a.Uf ? a.Uf[c] * G.dt : G.udt;
+        const double udt = a.Uf ? a.Uf[c] * g_dt : g_udt;
         const double h0 = hs[li] + udt;
         if (table_f && count < (uint32_t)kAmTab) {
           const double f = ftl[code_class(code) * kAmTab + count];
@@ -871,7 +876,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
       const int64_t c = cw + (int64_t)t * nx;
       const bool cl = (clean >> t) & 1u;
       double hv = hs[li];
-      if (cl && code == kSink) hv = hv + (a.Uf ? a.Uf[c] * G.dt : G.udt);
+      if (cl && code == kSink) hv = hv + (a.Uf ? a.Uf[c] * g_dt : g_udt);
       a.h_out[c] = hv;
       if (!wide_masks) w.dmask[c] = xr[(sy0 + t) * kTW + tx];
       if (a.export_routing) {
@@ -1054,11 +1059,12 @@ __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32
 // level pass that ran last (`cross_total` cells in `nl_cross` levels, of
 // which `glob_total` sit in the global queue for the routing export), then
 // the per-step counters are cleared for the next step.
-__device__ void finish_step(const StepArgs& a, Ctrl* ct, int64_t cross_total, int32_t nl_cross,
-                            int32_t glob_total) {
-  const Work& w = a.w;
+__device__ __forceinline__ void finish_step_core(Ctrl* ct, int32_t* hist, int32_t* lcnt,
+                                                 int chunked, int64_t step, int64_t n,
+                                                 int64_t cross_total, int32_t nl_cross,
+                                                 int32_t glob_total) {
   int64_t total = cross_total;
-  if (a.chunked) {
+  if (chunked) {
     total += ct->chunk_total;
     nl_cross = nl_cross > ct->chunk_nl ? nl_cross : ct->chunk_nl;
   }
@@ -1070,17 +1076,32 @@ __device__ void finish_step(const StepArgs& a, Ctrl* ct, int64_t cross_total, in
   ct->glob_total = glob_total;
   ct->crossing_run += total;
   if (nl > ct->max_nlevels) ct->max_nlevels = nl;
-  if (a.step < kHistCap) w.hist[a.step] = nl;
-  ct->steps = a.step + 1;
-  if ((int64_t)clean + total != (int64_t)a.n) atomicMax(&ct->status, 5);
+  if (step < kHistCap) hist[step] = nl;
+  ct->steps = step + 1;
+  if ((int64_t)clean + total != n) atomicMax(&ct->status, 5);
   ct->clean = 0;
   ct->clean_maxdepth = 0;
   ct->chunk_total = 0;
   ct->chunk_nl = 0;
   ct->chunk_next = 0;
   ct->ovf_count = 0;
-  w.lcnt[0] = 0;
-  w.lcnt[1] = 0;
+  lcnt[0] = 0;
+  lcnt[1] = 0;
+}
+
+__device__ void finish_step(const StepArgs& a, Ctrl* ct, int64_t cross_total, int32_t nl_cross,
+                            int32_t glob_total) {
+  finish_step_core(ct, a.w.hist, a.w.lcnt, a.chunked, a.step, a.n, cross_total, nl_cross,
+                   glob_total);
+}
+
+// A single grid's per-grid pass records the step itself, out of line (it
+// runs once per launch) and with plain arguments (a reference to the
+// launch's arguments would move them to scratch memory).
+__device__ __noinline__ void finish_one_grid(Ctrl* ct, int32_t* hist, int32_t* lcnt, int chunked,
+                                             int64_t step, int64_t n, int64_t total, int32_t nl) {
+  ct->dirty_nlevels = nl;
+  finish_step_core(ct, hist, lcnt, chunked, step, n, total, nl, 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
@@ -1322,6 +1343,8 @@ __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
     if (tid == 0) {
       w.gnl[gi] = 0;
       w.gtot[gi] = 0;
+      // One grid: this workgroup also records the step (no finishing launch).
+      if (a.ngrids == 1) finish_one_grid(w.ctrl, w.hist, w.lcnt, a.chunked, a.step, a.n, 0, 0);
     }
     return;
   }
@@ -1394,10 +1417,20 @@ __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
   if (clock) {
     const uint64_t tk3 = wall_clock64();
     Ctrl* ct = w.ctrl;
-    atomicMax((unsigned long long*)&ct->grid_phase_max[0], (unsigned long long)(s_tk[1] - s_tk[0]));
-    atomicMax((unsigned long long*)&ct->grid_phase_max[1], (unsigned long long)(s_tk[2] - s_tk[1]));
-    atomicMax((unsigned long long*)&ct->grid_phase_max[2], (unsigned long long)(tk3 - s_tk[2]));
+    if (a.ngrids == 1) {
+      ct->ticks[1] += s_tk[1] - s_tk[0];
+      ct->ticks[2] += s_tk[2] - s_tk[1];
+      ct->ticks[3] += tk3 - s_tk[2];
+    } else {
+      atomicMax((unsigned long long*)&ct->grid_phase_max[0],
+                (unsigned long long)(s_tk[1] - s_tk[0]));
+      atomicMax((unsigned long long*)&ct->grid_phase_max[1],
+                (unsigned long long)(s_tk[2] - s_tk[1]));
+      atomicMax((unsigned long long*)&ct->grid_phase_max[2], (unsigned long long)(tk3 - s_tk[2]));
+    }
   }
+  if (a.ngrids == 1 && tid == 0)
+    finish_one_grid(w.ctrl, w.hist, w.lcnt, a.chunked, a.step, a.n, hi - base, L + 1);
 }
 
 // After the per-grid level pass: the step's statistics (as the global pass
@@ -1474,6 +1507,12 @@ __global__ __launch_bounds__(kChunkThreads, 4) void k_chunk_trees(StepArgs a) {
   int32_t my_nl = 0;
   uint64_t tk[3] = {0, 0, 0};
   const bool clock = a.timers && blockIdx.x == 0 && tid == 0;
+  // One grid: its descriptor fields read once (inside the loops below, which
+  // contain a call, the compiler would reload them for every entry).
+  const GridDev& G0 = a.grids[0];
+  const double g0_dt = G0.dt, g0_udt = G0.udt;
+  const int g0_nx = G0.nx;
+  const bool g0_newton = G0.newton != 0;
 
   for (;;) {
     if (tid == 0) s_chunk = atomicAdd(&ct->chunk_next, 1);
@@ -1512,7 +1551,9 @@ __global__ __launch_bounds__(kChunkThreads, 4) void k_chunk_trees(StepArgs a) {
           g = multi ? s_grid[i] : 0;
           m = w.dmask[c];
           double hv = a.h_out[c];
-          if (s_k[i] != kBase) hv = hv + (a.Uf ? a.Uf[c] * a.grids[g].dt : a.grids[g].udt);
+          if (s_k[i] != kBase)
+            hv = hv + (a.Uf ? a.Uf[c] * (multi ? a.grids[g].dt : g0_dt)
+                            : (multi ? a.grids[g].udt : g0_udt));
           s_h[i] = hv;
         }
         int tot;
@@ -1522,7 +1563,7 @@ __global__ __launch_bounds__(kChunkThreads, 4) void k_chunk_trees(StepArgs a) {
           break;
         }
         if (m) {
-          const int nx = a.grids[g].nx;
+          const int nx = multi ? a.grids[g].nx : g0_nx;
           int pos = next + pre;
           while (m) {
             const int b = __ffs(m) - 1;
@@ -1597,8 +1638,8 @@ __global__ __launch_bounds__(kChunkThreads, 4) void k_chunk_trees(StepArgs a) {
           const GridDev& G = a.grids[gi];
           const int k = s_k[i];
           const double hr = s_h[s_par[i]];
-          const double udt = a.Uf ? a.Uf[c] * G.dt : G.udt;
-          if (!a.Kf && !G.newton && count < (uint32_t)kAmTab) {
+          const double udt = a.Uf ? a.Uf[c] * (multi ? G.dt : g0_dt) : (multi ? G.udt : g0_udt);
+          if (!a.Kf && !(multi ? G.newton != 0 : g0_newton) && count < (uint32_t)kAmTab) {
             // F from the grid's table (scalar K, n = 1, small counts).
             const double f = w.ftab[(gi * 3 + code_class(k)) * kAmTab + count];
             if (a.project) {
@@ -1786,18 +1827,24 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
 // in neighbour order.
 __device__ void mfd_area_level(const StepArgs& a, int32_t a0, int32_t a1, int wg, int nwg) {
   const Work& w = a.w;
+  // The grid's fields in registers before the loop: the loop calls pow, and
+  // the compiler would otherwise load them again for every donor.
   const GridDev& G = a.grids[0];
   const int nx = G.nx;
+  const double dist[3] = {G.dy, G.dx, G.ddiag};
+  const double dxdy = G.dxdy, p = a.mfd_p;
   for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1; i += (int64_t)nwg * kBlock) {
     const int32_t c = w.q[i];
     const double hc = w.mc[c].h;
-    double acc = G.dxdy;
+    double acc = dxdy;
     // Donors in neighbour order (mask from the routing: interior neighbours above c).
     for (uint32_t m = w.mq[c]; m; m &= m - 1) {
       const int k = __ffs(m) - 1;
       const MfdCell& md = w.mc[c + (int32_t)neighbour_offset(k, nx)];
       const double hd = md.h;
-      const double share = slope_pow((hd - hc) / class_dist(G, k), a.mfd_p) / md.wsum;
+      const int cls = code_class(k);
+      const double dk = cls == 0 ? dist[0] : (cls == 1 ? dist[1] : dist[2]);
+      const double share = slope_pow((hd - hc) / dk, p) / md.wsum;
       acc += share * md.area;
     }
     w.mc[c].area = acc;
@@ -1808,8 +1855,15 @@ __device__ void mfd_area_level(const StepArgs& a, int32_t a0, int32_t a1, int wg
 // with all receivers, h' = (h0 + sum F_k h_k') / (1 + sum F_k).
 __device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int wg, int nwg) {
   const Work& w = a.w;
+  // The grid's fields in registers before the loop (it calls pow and the
+  // area power).
   const GridDev& G = a.grids[0];
   const int ny = G.ny, nx = G.nx;
+  const double dist[3] = {G.dy, G.dx, G.ddiag};
+  const double g_dt = G.dt, g_udt = G.udt, g_K = G.K, g_m = G.m, p = a.mfd_p;
+  const int use_sqrt = G.use_sqrt;
+  const double* const Uf = a.Uf;
+  const double* const Kf = a.Kf;
   for (int64_t i = a0 + (int64_t)wg * kBlock + threadIdx.x; i < a1; i += (int64_t)nwg * kBlock) {
     const int32_t c = w.q[i];
     const int y = c / nx, x = c % nx;
@@ -1819,10 +1873,10 @@ __device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int w
       continue;
     }
     const MfdCell& mc = w.mc[c];
-    const double hup = hc + (a.Uf ? a.Uf[c] * G.dt : G.udt);
+    const double hup = hc + (Uf ? Uf[c] * g_dt : g_udt);
     const double wc = mc.wsum;
     const double ac = mc.area;
-    const double kdt = (a.Kf ? a.Kf[c] : G.K) * G.dt;
+    const double kdt = (Kf ? Kf[c] : g_K) * g_dt;
     double sumf = 0.0, sumfh = 0.0;
     // Receivers in neighbour order (mask from the routing).
     const uint32_t recs = w.kq[c];
@@ -1830,9 +1884,10 @@ __device__ void mfd_erode_level(const StepArgs& a, int32_t a0, int32_t a1, int w
       const int k = __ffs(m) - 1;
       const int32_t r = c + (int32_t)neighbour_offset(k, nx);
       const double hr = a.h_in[r];
-      const double dk = class_dist(G, k);
-      const double share = slope_pow((hc - hr) / dk, a.mfd_p) / wc;
-      const double f = (kdt * area_power_call(share * ac, G.use_sqrt, G.m)) / dk;
+      const int cls = code_class(k);
+      const double dk = cls == 0 ? dist[0] : (cls == 1 ? dist[1] : dist[2]);
+      const double share = slope_pow((hc - hr) / dk, p) / wc;
+      const double f = (kdt * area_power_call(share * ac, use_sqrt, g_m)) / dk;
       sumf += f;
       sumfh += f * a.h_out[r];
     }
@@ -2189,7 +2244,7 @@ hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_grid_levels<kBlock>, dim3((unsigned)a.ngrids), dim3(kBlock), 0, s, a);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || a.ngrids == 1) return e;
   hipLaunchKernelGGL(k_grid_levels_finish, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }

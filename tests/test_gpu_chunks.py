@@ -18,6 +18,7 @@ from tests.gpu_util import assert_heights_close, assert_routing_equal, oracle_pa
 pytestmark = pytest.mark.gpu
 
 CHUNKS_ON, CHUNKS_OFF = 1, 2
+LEVELS_PER_GRID = 2
 
 
 def _pyramid(ny, nx, seed, scale=1.0):
@@ -86,6 +87,16 @@ def test_chunks_that_do_not_fit_go_to_the_level_pass(shape, roots):
     assert st.crossing_last > 0
     off_h, off_r, _, _ = _run(torch, w, h0, 4, chunk_pass=CHUNKS_OFF)
     assert np.array_equal(h, off_h)
+    # The overflow of a single grid ordered by its one workgroup instead of
+    # the device-wide pass.
+    print(f"[gpu] pyramid {ny}x{nx} roots {roots} per-grid level pass", flush=True)
+    pg_h, pg_r, _, got = _run(torch, w, h0, 4, chunk_pass=CHUNKS_ON, chunk_roots=roots,
+                              level_pass=LEVELS_PER_GRID, level_threads=1024)
+    assert got["level_pass"] == LEVELS_PER_GRID
+    assert np.array_equal(h, pg_h)
+    for k in ("rec", "depth", "count"):
+        assert torch.equal(r[k], pg_r[k]), k
+    assert r["nlevels"] == pg_r["nlevels"]
 
 
 def test_batch_chunk_overflow_to_per_grid_pass():
