@@ -522,13 +522,55 @@ __device__ __forceinline__ void store_pairs(double* hs, int tid, const double2* 
   }
 }
 
+// One round of up to NS walks in lockstep (slot t active when bit t of act
+// is set).  A walk's state is one word: its cell's LDS index (bits 0-15),
+// that cell's code (16-19) and its steps so far (24-31).  A round moves each
+// active walk to its cell's receiver and adds one to that receiver's count;
+// a walk ends at a cell without a receiver, when the receiver is on the ring
+// (bit t of exitm: it leaves the tile), or at kLocalDepthCap steps (then the
+// whole tile goes to the crossing-tree passes: *all = 1).
+constexpr int kLockRounds = 2;       // rounds in place before the survivors are gathered
+constexpr uint32_t kWalkExit = 1u << 20;  // gathered state: the walk left the tile
+template <int NS>
+__device__ __forceinline__ void walk_round(uint32_t (&wk)[NS], uint32_t& act, uint32_t& exitm,
+                                           const uint8_t* rc, uint32_t* clw, int* all) {
+  uint32_t cu[NS];
+  int un[NS];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const int v = (int)(wk[t] & 0xFFFFu);
+    // A finished walk re-reads its own cell (in bounds, result unused).
+    un[t] = ((act >> t) & 1u) ? v + lds_off((int)((wk[t] >> 16) & 15u)) : v;
+    cu[t] = rc[un[t]];
+  }
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    if (!((act >> t) & 1u)) continue;
+    const int u = un[t];
+    if (cu[t] & kRingFlag) {
+      exitm |= 1u << t;
+      act &= ~(1u << t);
+      continue;
+    }
+    atomicAdd(&clw[u >> 1], 1u << ((u & 1) * 16));
+    const uint32_t d = (wk[t] >> 24) + 1u;
+    wk[t] = (uint32_t)u | (cu[t] << 16) | (d << 24);
+    if (cu[t] >= kSink) {
+      act &= ~(1u << t);
+    } else if (d >= (uint32_t)kLocalDepthCap) {
+      *all = 1;
+      act &= ~(1u << t);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
   __shared__ __align__(16) double hs[kSN];  // heights, tile + 2-cell halo; new heights
   __shared__ uint32_t clw[kSN / 2];         // upstream counts, two 16-bit halves a word
   __shared__ uint32_t rc32[kSN / 4];        // receiver codes, tile and ring (ring: | kRingFlag)
   __shared__ __align__(8) uint32_t xr32[kSN / 4];  // per local root: its tree crosses the tile edge
   __shared__ double ftl[3 * kAmTab];        // F for small counts (scalar K), per distance class
-  __shared__ uint16_t wlist[kTH * kTW];     // per wave: its cells of one level
+  __shared__ __align__(4) uint16_t wlist[kTH * kTW];  // per wave: its cells of one level
   __shared__ int wsum[kTileThreads / 64];
   __shared__ int s_all, s_clean, s_cmax, s_base;
   uint8_t* rc = (uint8_t*)rc32;
@@ -703,34 +745,51 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
       wk[t] = (uint32_t)(li0 + t * kSW) | (cv << 16);
       act |= (uint32_t)(cv < kSink) << t;
     }
-    while (act) {
-      uint32_t cu[kStrip];
-      int un[kStrip];
+    for (int r = 0; r < kLockRounds && act; ++r) walk_round<kStrip>(wk, act, exitm, rc, clw, &s_all);
+    // Tile-local trees are shallow: after the first rounds only a few walks
+    // of the wave's 512 are still going (about 44 on a noise raster), and
+    // the eight slots of a lane would mostly idle.  The wave gathers the
+    // survivors into a list in LDS (its erosion-list space, unused until the
+    // erosion), finishes them two to a lane, and each owner reads its walks'
+    // final states back (bit kWalkExit: the walk left the tile).
+    {
+      const int na = __popc(act);
+      const int incl = wave_inclusive_scan(na);
+      const int total = __builtin_amdgcn_readlane(incl, 63);
+      if (total > 2 * 64) {
+        while (act) walk_round<kStrip>(wk, act, exitm, rc, clw, &s_all);
+      } else if (total > 0) {
+        uint32_t* lst = (uint32_t*)wl;
+        int p = incl - na;
 #pragma unroll
-      for (int t = 0; t < kStrip; ++t) {
-        const int v = (int)(wk[t] & 0xFFFFu);
-        // A finished walk re-reads its own cell (in bounds, result unused).
-        un[t] = ((act >> t) & 1u) ? v + lds_off((int)((wk[t] >> 16) & 15u)) : v;
-        cu[t] = rc[un[t]];
-      }
+        for (int t = 0; t < kStrip; ++t)
+          if ((act >> t) & 1u) lst[p++] = wk[t];
+        __builtin_amdgcn_wave_barrier();
+        uint32_t tw[2] = {0u, 0u}, tact = 0, texit = 0;
 #pragma unroll
-      for (int t = 0; t < kStrip; ++t) {
-        if (!((act >> t) & 1u)) continue;
-        const int u = un[t];
-        if (cu[t] & kRingFlag) {
-          exitm |= 1u << t;
-          act &= ~(1u << t);
-          continue;
+        for (int j = 0; j < 2; ++j) {
+          const int e = lane + 64 * j;
+          if (e < total) {
+            tw[j] = lst[e];
+            tact |= 1u << j;
+          }
         }
-        atomicAdd(&clw[u >> 1], 1u << ((u & 1) * 16));
-        const uint32_t d = (wk[t] >> 24) + 1u;
-        wk[t] = (uint32_t)u | (cu[t] << 16) | (d << 24);
-        if (cu[t] >= kSink) {
-          act &= ~(1u << t);
-        } else if (d >= (uint32_t)kLocalDepthCap) {
-          s_all = 1;
-          act &= ~(1u << t);
+        while (tact) walk_round<2>(tw, tact, texit, rc, clw, &s_all);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int e = lane + 64 * j;
+          if (e < total) lst[e] = tw[j] | (((texit >> j) & 1u) ? kWalkExit : 0u);
         }
+        __builtin_amdgcn_wave_barrier();
+        p = incl - na;
+#pragma unroll
+        for (int t = 0; t < kStrip; ++t)
+          if ((act >> t) & 1u) {
+            const uint32_t v = lst[p++];
+            wk[t] = v;
+            exitm |= (uint32_t)((v & kWalkExit) != 0u) << t;
+          }
+        act = 0;
       }
     }
     uint64_t deps = 0;
