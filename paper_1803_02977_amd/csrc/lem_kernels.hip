@@ -745,52 +745,52 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_tile_step(StepArgs a) {
       wk[t] = (uint32_t)(li0 + t * kSW) | (cv << 16);
       act |= (uint32_t)(cv < kSink) << t;
     }
-    for (int r = 0; r < kLockRounds && act; ++r) walk_round<kStrip>(wk, act, exitm, rc, clw, &s_all);
     // Tile-local trees are shallow: after the first rounds only a few walks
     // of the wave's 512 are still going (about 44 on a noise raster), and
-    // the eight slots of a lane would mostly idle.  The wave gathers the
-    // survivors into a list in LDS (its erosion-list space, unused until the
-    // erosion), finishes them two to a lane, and each owner reads its walks'
-    // final states back (bit kWalkExit: the walk left the tile).
-    {
+    // the eight slots of a lane would mostly idle.  Once at most 128 remain
+    // (checked every kLockRounds rounds), the wave gathers them into a list
+    // in LDS (its erosion-list space, unused until the erosion), finishes
+    // them two to a lane, and each owner reads its walks' final states back
+    // (bit kWalkExit: the walk left the tile).
+    for (;;) {
+      for (int r = 0; r < kLockRounds && act; ++r)
+        walk_round<kStrip>(wk, act, exitm, rc, clw, &s_all);
       const int na = __popc(act);
       const int incl = wave_inclusive_scan(na);
       const int total = __builtin_amdgcn_readlane(incl, 63);
-      if (total > 2 * 64) {
-        while (act) walk_round<kStrip>(wk, act, exitm, rc, clw, &s_all);
-      } else if (total > 0) {
-        uint32_t* lst = (uint32_t*)wl;
-        int p = incl - na;
+      if (total == 0) break;
+      if (total > 2 * 64) continue;
+      uint32_t* lst = (uint32_t*)wl;
+      int p = incl - na;
 #pragma unroll
-        for (int t = 0; t < kStrip; ++t)
-          if ((act >> t) & 1u) lst[p++] = wk[t];
-        __builtin_amdgcn_wave_barrier();
-        uint32_t tw[2] = {0u, 0u}, tact = 0, texit = 0;
+      for (int t = 0; t < kStrip; ++t)
+        if ((act >> t) & 1u) lst[p++] = wk[t];
+      __builtin_amdgcn_wave_barrier();
+      uint32_t tw[2] = {0u, 0u}, tact = 0, texit = 0;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int e = lane + 64 * j;
-          if (e < total) {
-            tw[j] = lst[e];
-            tact |= 1u << j;
-          }
+      for (int j = 0; j < 2; ++j) {
+        const int e = lane + 64 * j;
+        if (e < total) {
+          tw[j] = lst[e];
+          tact |= 1u << j;
         }
-        while (tact) walk_round<2>(tw, tact, texit, rc, clw, &s_all);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int e = lane + 64 * j;
-          if (e < total) lst[e] = tw[j] | (((texit >> j) & 1u) ? kWalkExit : 0u);
-        }
-        __builtin_amdgcn_wave_barrier();
-        p = incl - na;
-#pragma unroll
-        for (int t = 0; t < kStrip; ++t)
-          if ((act >> t) & 1u) {
-            const uint32_t v = lst[p++];
-            wk[t] = v;
-            exitm |= (uint32_t)((v & kWalkExit) != 0u) << t;
-          }
-        act = 0;
       }
+      while (tact) walk_round<2>(tw, tact, texit, rc, clw, &s_all);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int e = lane + 64 * j;
+        if (e < total) lst[e] = tw[j] | (((texit >> j) & 1u) ? kWalkExit : 0u);
+      }
+      __builtin_amdgcn_wave_barrier();
+      p = incl - na;
+#pragma unroll
+      for (int t = 0; t < kStrip; ++t)
+        if ((act >> t) & 1u) {
+          const uint32_t v = lst[p++];
+          wk[t] = v;
+          exitm |= (uint32_t)((v & kWalkExit) != 0u) << t;
+        }
+      break;
     }
     uint64_t deps = 0;
     uint32_t roots[kStrip / 2];
@@ -1118,12 +1118,11 @@ __device__ __forceinline__ void erode_level(const StepArgs& a, int32_t a0, int32
 // level pass that ran last (`cross_total` cells in `nl_cross` levels, of
 // which `glob_total` sit in the global queue for the routing export), then
 // the per-step counters are cleared for the next step.
-__device__ __forceinline__ void finish_step_core(Ctrl* ct, int32_t* hist, int32_t* lcnt,
-                                                 int chunked, int64_t step, int64_t n,
-                                                 int64_t cross_total, int32_t nl_cross,
-                                                 int32_t glob_total) {
+__device__ void finish_step(const StepArgs& a, Ctrl* ct, int64_t cross_total, int32_t nl_cross,
+                            int32_t glob_total) {
+  const Work& w = a.w;
   int64_t total = cross_total;
-  if (chunked) {
+  if (a.chunked) {
     total += ct->chunk_total;
     nl_cross = nl_cross > ct->chunk_nl ? nl_cross : ct->chunk_nl;
   }
@@ -1135,32 +1134,17 @@ __device__ __forceinline__ void finish_step_core(Ctrl* ct, int32_t* hist, int32_
   ct->glob_total = glob_total;
   ct->crossing_run += total;
   if (nl > ct->max_nlevels) ct->max_nlevels = nl;
-  if (step < kHistCap) hist[step] = nl;
-  ct->steps = step + 1;
-  if ((int64_t)clean + total != n) atomicMax(&ct->status, 5);
+  if (a.step < kHistCap) w.hist[a.step] = nl;
+  ct->steps = a.step + 1;
+  if ((int64_t)clean + total != (int64_t)a.n) atomicMax(&ct->status, 5);
   ct->clean = 0;
   ct->clean_maxdepth = 0;
   ct->chunk_total = 0;
   ct->chunk_nl = 0;
   ct->chunk_next = 0;
   ct->ovf_count = 0;
-  lcnt[0] = 0;
-  lcnt[1] = 0;
-}
-
-__device__ void finish_step(const StepArgs& a, Ctrl* ct, int64_t cross_total, int32_t nl_cross,
-                            int32_t glob_total) {
-  finish_step_core(ct, a.w.hist, a.w.lcnt, a.chunked, a.step, a.n, cross_total, nl_cross,
-                   glob_total);
-}
-
-// A single grid's per-grid pass records the step itself, out of line (it
-// runs once per launch) and with plain arguments (a reference to the
-// launch's arguments would move them to scratch memory).
-__device__ __noinline__ void finish_one_grid(Ctrl* ct, int32_t* hist, int32_t* lcnt, int chunked,
-                                             int64_t step, int64_t n, int64_t total, int32_t nl) {
-  ct->dirty_nlevels = nl;
-  finish_step_core(ct, hist, lcnt, chunked, step, n, total, nl, 0);
+  w.lcnt[0] = 0;
+  w.lcnt[1] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_global_levels(StepArgs a) {
@@ -1402,8 +1386,6 @@ __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
     if (tid == 0) {
       w.gnl[gi] = 0;
       w.gtot[gi] = 0;
-      // One grid: this workgroup also records the step (no finishing launch).
-      if (a.ngrids == 1) finish_one_grid(w.ctrl, w.hist, w.lcnt, a.chunked, a.step, a.n, 0, 0);
     }
     return;
   }
@@ -1476,20 +1458,10 @@ __global__ __launch_bounds__(NT) void k_grid_levels(StepArgs a) {
   if (clock) {
     const uint64_t tk3 = wall_clock64();
     Ctrl* ct = w.ctrl;
-    if (a.ngrids == 1) {
-      ct->ticks[1] += s_tk[1] - s_tk[0];
-      ct->ticks[2] += s_tk[2] - s_tk[1];
-      ct->ticks[3] += tk3 - s_tk[2];
-    } else {
-      atomicMax((unsigned long long*)&ct->grid_phase_max[0],
-                (unsigned long long)(s_tk[1] - s_tk[0]));
-      atomicMax((unsigned long long*)&ct->grid_phase_max[1],
-                (unsigned long long)(s_tk[2] - s_tk[1]));
-      atomicMax((unsigned long long*)&ct->grid_phase_max[2], (unsigned long long)(tk3 - s_tk[2]));
-    }
+    atomicMax((unsigned long long*)&ct->grid_phase_max[0], (unsigned long long)(s_tk[1] - s_tk[0]));
+    atomicMax((unsigned long long*)&ct->grid_phase_max[1], (unsigned long long)(s_tk[2] - s_tk[1]));
+    atomicMax((unsigned long long*)&ct->grid_phase_max[2], (unsigned long long)(tk3 - s_tk[2]));
   }
-  if (a.ngrids == 1 && tid == 0)
-    finish_one_grid(w.ctrl, w.hist, w.lcnt, a.chunked, a.step, a.n, hi - base, L + 1);
 }
 
 // After the per-grid level pass: the step's statistics (as the global pass
@@ -2303,7 +2275,7 @@ hipError_t launch_grid_levels(const StepArgs& a, int threads, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_grid_levels<kBlock>, dim3((unsigned)a.ngrids), dim3(kBlock), 0, s, a);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || a.ngrids == 1) return e;
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_grid_levels_finish, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
