@@ -1775,7 +1775,7 @@ __global__ __launch_bounds__(256) void k_mfd_route(StepArgs a) {
             donors |= 1u << k;
         }
       }
-      w.par[c] = nrec;
+      ((uint8_t*)w.par)[c] = (uint8_t)nrec;  // one byte per cell, four to a word
       w.mq[c] = (uint8_t)donors;
       w.kq[c] = (uint8_t)recs;
       MfdCell& mc = w.mc[c];
@@ -1826,7 +1826,9 @@ __device__ void mfd_expand(const StepArgs& a, int32_t lo, int32_t hi, int32_t L,
         for (uint32_t m = w.mq[c]; m; m &= m - 1) {
           const int k = __ffs(m) - 1;
           const int32_t d = c + (int32_t)neighbour_offset(k, nx);
-          if (atomicSub(&w.par[d], 1) == 1) ready[j] |= 1u << k;
+          const int sh = 8 * (d & 3);
+          const uint32_t was = atomicSub((uint32_t*)w.par + (d >> 2), 1u << sh);
+          if (((was >> sh) & 0xFFu) == 1u) ready[j] |= 1u << k;
         }
         v[j >> 2] += (uint64_t)__popc(ready[j]) << (16 * (j & 3));
       }
