@@ -1715,8 +1715,9 @@ __global__ __launch_bounds__(kChunkThreads, 4) void k_chunk_trees(StepArgs a) {
 // strictly lower neighbour is a receiver and gets the share
 // S^p / sum_j S_j^p of the flow (S = slope to it); a cell is processed only
 // after all of its receivers, so its level is the longest path to a root.
-// Single grid, global memory, level-synchronous.  Levels use the dense
-// heights and a dense counter array (par: receivers not yet ordered); areas
+// Single grid, global memory, level-synchronous.  Levels use the donor masks
+// and one counter byte per cell, four to a word in par's space (receivers
+// not yet ordered); areas
 // gather each donor's height, weight sum and area from one 32-byte MfdCell
 // (grid order), about four cache lines per 3x3 neighbourhood instead of
 // three per field; erosion reads the dense old and new heights of its
