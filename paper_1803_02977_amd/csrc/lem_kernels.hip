@@ -1075,20 +1075,32 @@ __device__ void expand_level(const StepArgs& a, int32_t lo, int32_t hi, int32_t 
   }
 }
 
-// Step 5 for queue positions [a0, a1): count = 1 + the donors' counts.
+// Step 5 for queue positions [a0, a1): count = 1 + the donors' counts.  A
+// thread takes two positions at a time (a level of a deep grid has a few
+// thousand cells and one workgroup): their loads are in flight together.
 template <int NT = kBlock>
 __device__ __forceinline__ void accumulate_level(const Work& w, int32_t a0, int32_t a1, int wg,
                                                  int nwg) {
-  for (int64_t i = a0 + (int64_t)wg * NT + threadIdx.x; i < a1;
-       i += (int64_t)nwg * NT) {
-    const uint32_t m = w.mq[i];
-    uint32_t s = 1u;
-    if (m) {
-      const int32_t f = w.fc[i];
-      const int k = __popc(m);
-      for (int j = 0; j < k; ++j) s += w.cnt[f + j];
+  const int64_t stride = (int64_t)nwg * NT;
+  for (int64_t i0 = a0 + (int64_t)wg * NT + threadIdx.x; i0 < a1; i0 += 2 * stride) {
+    const int64_t ii[2] = {i0, i0 + stride};
+    uint32_t m[2] = {0u, 0u};
+    int32_t f[2] = {0, 0};
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ii[e] < a1) {
+        m[e] = w.mq[ii[e]];
+        f[e] = w.fc[ii[e]];
+      }
+    uint32_t s[2] = {1u, 1u};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = __popc(m[e]);
+      for (int j = 0; j < k; ++j) s[e] += w.cnt[f[e] + j];
     }
-    w.cnt[i] = s;
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ii[e] < a1) w.cnt[ii[e]] = s[e];
   }
 }
 
