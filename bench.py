@@ -132,13 +132,13 @@ WARM_NAME = "warmstart-100x256x256-fp64"
 NET_NAME = "warmstart-network-b16-256x256-bf16"
 MFD_NAME = "mfd-10000x10000-fp64"
 # Algorithmic bytes per cell-update of a multiple-flow-direction step:
-# routing (k_mfd_route: read h, write the receiver counter and weight sum:
-# 20 B), then k_mfd_levels: levels (queue read and append, counter update,
-# h: 24 B), areas (queue, h, donors' weight sums and areas, area write:
-# 36 B), erosion (queue, h, weight sum, area, new height written and read as
-# a receiver's: 44 B).
-ALG_BYTES_MFD_ROUTE = 20
-ALG_BYTES_MFD_LEVELS = 104
+# routing (k_mfd_route: read h, write the one-byte receiver counter and the
+# weight sum: 17 B), then k_mfd_levels: levels (queue read and append,
+# counter update, h: 18 B), areas (queue, h, donors' weight sums and areas,
+# area write: 36 B), erosion (queue, h, weight sum, area, new height written
+# and read as a receiver's: 44 B).
+ALG_BYTES_MFD_ROUTE = 17
+ALG_BYTES_MFD_LEVELS = 98
 # Square edge lengths of the size sweep; the regions (upper edge length)
 # follow the GPU scaling table of the paper (section on GPU performance),
 # whose wall-time exponents x (wall ~ N^x) are quoted beside the fit.
